@@ -1,0 +1,253 @@
+"""DIAM with P concurrent chains, FP64, in the paper's order of operations.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+The sampler follows Algorithm 1 (Section 4.3) for every chain, with the
+concurrent-chain logistics of Section 2.4.1 in their M = 1 form: every n_lag
+steps all P chains merge their local moments into the global ones (eqs.
+mom2p, mom1p, mom2g, mom1g) and one shared proposal factor is refactorised
+from the merged covariance (eq. sampcov).  Readings where the paper is
+silent or garbled are stated at each use:
+
+* The quadratic correction uses A^-1 (x - x_ref): the proposal (eq. diamnl)
+  leaves N(x_ref, alpha^2 A A^T) invariant, and Algorithm 1 prints the
+  x_ref = 0 case.  The factor 1/(2 alpha^2) uses the inflation alpha.
+* After every proposal update the correction of the *current* states is
+  recomputed under the new (A, x_ref); both states entering one acceptance
+  ratio are then measured by the same kernel.
+* x_ref = 0 until the first merge, then the merged mean, constant within a
+  window.
+* Every visited state of every step enters the moments, repeats after a
+  rejection included; local moments use the running 1/(m n_lag) average
+  (the printed recursion is off by a factor n_lag in one term).
+* C_n uses the 1/n normalisation printed in eq. sampcov.
+* Acceptance is strict: accept iff log u < log alpha; NaN rejects.
+* Cholesky failure: retry on Cov + eps_j I with eps_j = 10^j * jitter0 *
+  s, s = tr(Cov)/d if that is positive and finite else 1, j = 0, 1, ...,
+  tries-1; if every try fails the previous factor is kept.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+OK = 0
+E_NOT_PD = -4
+
+
+def diam_proposal(X, x_ref, A, W, beta, alpha=1.0):
+    """x' = x_ref + sqrt(1 - beta^2) (x - x_ref) + beta alpha A W
+    (Section 2.3.4, eq. diam; the inflation alpha of eq. diamnl)."""
+    rho = math.sqrt(1.0 - beta * beta)
+    return x_ref[:, None] + rho * (X - x_ref[:, None]) + beta * alpha * (A @ W)
+
+
+def whiten(A, x_ref, X):
+    """A^-1 (x - x_ref) for each column, by a triangular solve against the
+    lower factor A (the product Algorithm 1 applies to every state)."""
+    return sla.solve_triangular(A, X - x_ref[:, None], lower=True, check_finite=False)
+
+
+def log_accept_ratio(lp_new, lp_old, Z_new, Z_old, alpha=1.0):
+    """log alpha(x, x') of eq. accept for the DIAM kernel, as in Algorithm 1:
+    log pi(x') + |z'|^2/(2 alpha^2) - (log pi(x) + |z|^2/(2 alpha^2))."""
+    q_new = np.sum(Z_new * Z_new, axis=0)
+    q_old = np.sum(Z_old * Z_old, axis=0)
+    return (lp_new + q_new / (2.0 * alpha * alpha)) - (lp_old + q_old / (2.0 * alpha * alpha))
+
+
+def accept_decisions(la, u):
+    """Accept iff log u < log alpha (strict); NaN log alpha rejects."""
+    la = np.asarray(la, dtype=np.float64)
+    with np.errstate(invalid="ignore"):
+        acc = np.log(u) < la
+    return acc & ~np.isnan(la)
+
+
+def local_moments(Xw_p):
+    """Local first two moments of one chain over one window of n_lag states
+    (eqs. mom2p / mom1p with m = M = 1): S^p = (1/n_lag) sum x x^T,
+    m^p = (1/n_lag) sum x.  Xw_p is d x n_lag."""
+    n = Xw_p.shape[1]
+    return (Xw_p @ Xw_p.T) / n, Xw_p.sum(axis=1) / n
+
+
+def merge_global(S_glob, m_glob, N, locals_, n_lag):
+    """Merge the P chains' local moments into the global ones (eqs. mom2g /
+    mom1g).  With N prior samples and P chains of n_lag new samples each,
+    S <- (N S + n_lag sum_p S^p) / (N + P n_lag), which is the printed
+    ((k-1)/k) S + (1/(kP)) sum_p S^p when N = (k-1) P n_lag."""
+    P = len(locals_)
+    n_new = P * n_lag
+    S_sum = np.zeros_like(S_glob)
+    m_sum = np.zeros_like(m_glob)
+    for S_p, m_p in locals_:
+        S_sum += S_p
+        m_sum += m_p
+    tot = N + n_new
+    S = (N / tot) * S_glob + (n_lag / tot) * S_sum
+    m = (N / tot) * m_glob + (n_lag / tot) * m_sum
+    return S, m, tot
+
+
+def sample_covariance(S, m):
+    """C = S - m m^T (eq. sampcov)."""
+    return S - np.outer(m, m)
+
+
+def cholesky_jitter(C, jitter0=1e-12, tries=13):
+    """Lower Cholesky factor of C, with the diagonal-jitter retry rule.
+
+    Returns (L, j) where j = -1 if C itself factored, j >= 0 the jitter level
+    used, or (None, tries) if every try failed.  A try fails when LAPACK's
+    potrf meets a non-positive or NaN pivot.
+    """
+    d = C.shape[0]
+
+    def chol(M):
+        try:
+            L = np.linalg.cholesky(M)
+        except np.linalg.LinAlgError:
+            return None
+        return L if np.all(np.isfinite(L)) else None
+
+    L = chol(C)
+    if L is not None:
+        return L, -1
+    tr = float(np.trace(C)) / d
+    s = tr if (tr > 0.0 and math.isfinite(tr)) else 1.0
+    for j in range(tries):
+        L = chol(C + ((10.0 ** j) * jitter0 * s) * np.eye(d))
+        if L is not None:
+            return L, j
+    return None, tries
+
+
+@dataclass
+class DiamOracle:
+    """P chains of Algorithm 1 sharing one proposal factor (M = 1).
+
+    ``logpi`` maps a d x n block to n log-densities.  States are d x P.
+    """
+    logpi: object
+    d: int
+    P: int
+    n_lag: int
+    beta: float
+    alpha: float = 1.0
+    jitter0: float = 1e-12
+    jitter_tries: int = 13
+    X: np.ndarray = None
+    x_ref: np.ndarray = None
+    A: np.ndarray = None
+    S_glob: np.ndarray = None
+    m_glob: np.ndarray = None
+    N: float = 0.0
+    lp: np.ndarray = None
+    Z: np.ndarray = None
+    window: list = field(default_factory=list)
+    n_accepted: np.ndarray = None
+    last_jitter: int = -1
+
+    def __post_init__(self):
+        d, P = self.d, self.P
+        if self.X is None:
+            self.X = np.zeros((d, P))
+        self.X = np.array(self.X, dtype=np.float64, copy=True)
+        self.x_ref = np.zeros(d)
+        self.A = np.eye(d)
+        self.S_glob = np.zeros((d, d))
+        self.m_glob = np.zeros(d)
+        self.N = 0.0
+        self.lp = self.logpi(self.X)
+        self.Z = whiten(self.A, self.x_ref, self.X)
+        self.n_accepted = np.zeros(P, dtype=np.int64)
+
+    # -- warm start: seed the global moments, then factorise once ----------
+    def seed_moments(self, S0, m0, N0):
+        self.S_glob = np.array(S0, dtype=np.float64, copy=True)
+        self.m_glob = np.array(m0, dtype=np.float64, copy=True)
+        self.N = float(N0)
+        return self.update_proposal()
+
+    # -- one step of all P chains (Algorithm 1, loop body) -----------------
+    def step(self, W, u):
+        Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
+        Zp = whiten(self.A, self.x_ref, Xp)
+        lpp = self.logpi(Xp)
+        if np.any(np.isposinf(lpp)):
+            raise FloatingPointError("log density returned +inf")
+        la = log_accept_ratio(lpp, self.lp, Zp, self.Z, self.alpha)
+        acc = accept_decisions(la, u)
+        self.X[:, acc] = Xp[:, acc]
+        self.Z[:, acc] = Zp[:, acc]
+        self.lp[acc] = lpp[acc]
+        self.n_accepted += acc
+        self.window.append(self.X.copy())
+        return acc, la
+
+    # -- two-stage delayed acceptance with a surrogate ---------------------
+    def step_delayed(self, W, u1, u2, surrogate, s_cur):
+        """One step with a cheap first stage (Christen & Fox 2005).
+
+        Stage 1 runs the DIAM acceptance with the surrogate log-density in
+        place of log pi.  Survivors face stage 2 with
+        log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x)),
+        which makes the composite kernel reversible for pi itself.  Returns
+        (accepted, stage-1 survivors, updated s_cur)."""
+        Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
+        Zp = whiten(self.A, self.x_ref, Xp)
+        sp = surrogate(Xp)
+        la1 = log_accept_ratio(sp, s_cur, Zp, self.Z, self.alpha)
+        pass1 = accept_decisions(la1, u1)
+        acc = np.zeros(self.P, dtype=bool)
+        if np.any(pass1):
+            idx = np.nonzero(pass1)[0]
+            lpp = self.logpi(Xp[:, idx])
+            la2 = (lpp - self.lp[idx]) - (sp[idx] - s_cur[idx])
+            ok = accept_decisions(la2, u2[idx])
+            sel = idx[ok]
+            acc[sel] = True
+            self.lp[sel] = lpp[ok]
+        self.X[:, acc] = Xp[:, acc]
+        self.Z[:, acc] = Zp[:, acc]
+        s_new = s_cur.copy()
+        s_new[acc] = sp[acc]
+        self.n_accepted += acc
+        self.window.append(self.X.copy())
+        return acc, pass1, s_new
+
+    # -- every n_lag steps: merge, then refactorise -------------------------
+    def merge_moments(self):
+        if len(self.window) == 0:
+            raise RuntimeError("empty window")
+        n = len(self.window)
+        Xw = np.stack(self.window, axis=2)            # d x P x n
+        locals_ = [local_moments(Xw[:, p, :]) for p in range(self.P)]
+        self.S_glob, self.m_glob, self.N = merge_global(self.S_glob, self.m_glob, self.N, locals_, n)
+        self.window = []
+
+    def update_proposal(self):
+        C = sample_covariance(self.S_glob, self.m_glob)
+        A, j = cholesky_jitter(C, self.jitter0, self.jitter_tries)
+        self.last_jitter = j
+        if A is None:
+            return E_NOT_PD
+        self.A = A
+        self.x_ref = self.m_glob.copy()
+        self.Z = whiten(self.A, self.x_ref, self.X)
+        return OK
+
+    def run_window(self, W, U):
+        """n_lag steps with W[t] (P x d, i.e. d x P column-major) and U[t]
+        (P), then the merge and the update.  Returns the acceptance count."""
+        acc = np.zeros(self.P, dtype=np.int64)
+        for t in range(W.shape[0]):
+            a, _ = self.step(W[t].T, U[t])
+            acc += a
+        self.merge_moments()
+        self.update_proposal()
+        return acc

@@ -1,0 +1,145 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module only *draws* inputs: target parameters, initial states and the
+random numbers a sampler consumes.  It holds none of the sampler's
+arithmetic (no proposal, acceptance, moment merge or factorisation), so the
+CPU oracle and the GPU library can both be fed from it without sharing any
+part of the method.
+
+Target recipes
+--------------
+* Gaussian targets N(mu, Sigma) with Sigma = Q diag(lambda) Q^T,
+  lambda_i = i^-2 and Q the sign-fixed orthogonal factor of a seeded
+  Gaussian matrix.  The random targets of the paper's numerical section
+  (Section 3.1) are dense Gaussians whose density costs one dense
+  matrix-vector product; this family keeps that cost and makes the
+  conditioning explicit (cond(Sigma) = d^2).  Draw order: the d x d matrix
+  G first, then mu, from ``numpy.random.default_rng(seed)``.
+  The density is carried by its whitening matrix R = diag(lambda^-1/2) Q^T,
+  so that log pi(x) = -1/2 ||R (x - mu)||^2 + const.
+* Bayesian logistic regression: design A (n x d, FP32, entries N(0, 1/d)),
+  true weights w ~ N(0, I), labels y ~ Bernoulli(sigmoid(A w)), prior
+  N(0, prior_var I); draws in that order from ``default_rng(seed)``.
+* The batch of many small Gaussians: d_t log-uniform in [128, 3072] drawn
+  from ``default_rng(999)``, target t built with seed 1000 + t.
+
+Random numbers of the sampler
+-----------------------------
+Normals W are stored step-major: ``W[t]`` is a P x d C-ordered block, which
+is the d x P column-major matrix the library expects (chain p = column p).
+Uniforms lie strictly inside (0, 1): u = (k + 0.5) / 2^52 with k an integer
+in [0, 2^52), every value exact in FP64, so log u is always finite and < 0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+import math
+
+import numpy as np
+
+__all__ = [
+    "GaussianTarget",
+    "gaussian_target",
+    "gaussian_exact_draws",
+    "gaussian_warm_moments",
+    "LogRegData",
+    "logreg_data",
+    "batch_dims",
+    "draw_normals",
+    "draw_uniforms",
+    "unit_vectors",
+]
+
+
+@dataclass
+class GaussianTarget:
+    d: int
+    mu: np.ndarray      # (d,)    float64
+    Q: np.ndarray       # (d, d)  float64, orthogonal, column i <-> lambda_i
+    lam: np.ndarray     # (d,)    float64, lambda_i = i^-2
+    R: np.ndarray       # (d, d)  float64, R = diag(lambda^-1/2) Q^T
+    Sigma: np.ndarray   # (d, d)  float64, Q diag(lambda) Q^T
+
+    @property
+    def v_min(self) -> np.ndarray:
+        """Eigenvector of the smallest eigenvalue of Sigma."""
+        return self.Q[:, -1].copy()
+
+    @property
+    def v_max(self) -> np.ndarray:
+        """Eigenvector of the largest eigenvalue of Sigma."""
+        return self.Q[:, 0].copy()
+
+
+def gaussian_target(d: int, seed: int) -> GaussianTarget:
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((d, d))
+    mu = rng.standard_normal(d)
+    Q, Rq = np.linalg.qr(G)
+    s = np.sign(np.diag(Rq))
+    s[s == 0] = 1.0
+    Q = Q * s[None, :]
+    i = np.arange(1, d + 1, dtype=np.float64)
+    lam = i ** -2.0
+    R = i[:, None] * Q.T
+    Sigma = (Q * lam[None, :]) @ Q.T
+    Sigma = 0.5 * (Sigma + Sigma.T)
+    return GaussianTarget(d=d, mu=mu, Q=Q, lam=lam, R=np.ascontiguousarray(R), Sigma=Sigma)
+
+
+def gaussian_exact_draws(t: GaussianTarget, n: int, seed: int) -> np.ndarray:
+    """n exact draws from N(mu, Sigma) as a d x n array (column = draw)."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((t.d, n))
+    return t.mu[:, None] + t.Q @ (np.sqrt(t.lam)[:, None] * g)
+
+
+def gaussian_warm_moments(t: GaussianTarget):
+    """Exact raw moments (S, m) = (Sigma + mu mu^T, mu) of the target, used to
+    seed the global moment accumulators for the warm-start protocol."""
+    return t.Sigma + np.outer(t.mu, t.mu), t.mu.copy()
+
+
+@dataclass
+class LogRegData:
+    A: np.ndarray        # (n, d) float32
+    y: np.ndarray        # (n,)   float32 in {0, 1}
+    w_true: np.ndarray   # (d,)   float64
+    prior_var: float
+
+
+def logreg_data(n: int = 200000, d: int = 512, seed: int = 4, prior_var: float = 10.0) -> LogRegData:
+    rng = np.random.default_rng(seed)
+    A = (rng.standard_normal((n, d)) * (1.0 / math.sqrt(d))).astype(np.float32)
+    w = rng.standard_normal(d)
+    t = A.astype(np.float64) @ w
+    p = 1.0 / (1.0 + np.exp(-t))
+    y = (rng.random(n) < p).astype(np.float32)
+    return LogRegData(A=A, y=y, w_true=w, prior_var=prior_var)
+
+
+def batch_dims(n_targets: int = 48, lo: int = 128, hi: int = 3072) -> np.ndarray:
+    rng = np.random.default_rng(999)
+    u = rng.uniform(math.log(lo), math.log(hi), size=n_targets)
+    return np.rint(np.exp(u)).astype(np.int64)
+
+
+def draw_normals(d: int, P: int, n_steps: int, seed: int) -> np.ndarray:
+    """(n_steps, P, d) float64 standard normals; W[t] is column-major d x P."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n_steps, P, d))
+
+
+def draw_uniforms(P: int, n_steps: int, seed: int, stages: int = 1) -> np.ndarray:
+    """(n_steps, stages, P) float64 uniforms in the open interval (0, 1)."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, 1 << 52, size=(n_steps, stages, P), dtype=np.int64)
+    u = (k.astype(np.float64) + 0.5) * (2.0 ** -52)
+    return u if stages > 1 else u[:, 0, :]
+
+
+def unit_vectors(d: int, n: int, seed: int) -> np.ndarray:
+    """n seeded random unit vectors as a d x n array."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((d, n))
+    return v / np.linalg.norm(v, axis=0, keepdims=True)
