@@ -1,0 +1,244 @@
+"""Benchmark: DIAM chain steps/s and ESS/s on one MI355X, mixed precision vs
+plain FP64, Gaussian target d = 4096, P = 256 chains, n_lag = 256.
+
+One benchmark "step" is one window of the sampler: n_lag steps of all P
+chains (batched proposal contraction, per-step target contraction and
+accept/reject), the moment merge (window scatter) and the refactorisation
+(FP64 Cholesky + whitening of the current states).  Inputs are synthetic:
+the seeded Gaussian target of the d = 4096 configuration (lambda_i = i^-2,
+random orthogonal Q), chains started from exact draws with the global moments
+seeded at the target's (warm-start protocol), all random numbers drawn on the
+GPU by Philox.  Everything is resident in HBM before timing starts.
+
+Prints ONE JSON line.  ``--gpus N`` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ESS/sec and chain steps/sec, d=4096 P=256: mixed-precision vs plain FP64 GPU"
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ess_per_chain(traces):
+    """Geyer initial-monotone-sequence ESS summed over chains; traces n x P."""
+    x = np.asarray(traces, dtype=np.float64)
+    n, P = x.shape
+    y = x - x.mean(axis=0, keepdims=True)
+    m = 1 << int(math.ceil(math.log2(2 * n)))
+    f = np.fft.rfft(y, m, axis=0)
+    g = np.fft.irfft(f * np.conj(f), m, axis=0)[:n] / n
+    tot = 0.0
+    for p in range(P):
+        gp = g[:, p]
+        if gp[0] <= 0:
+            continue
+        G = gp[0:2 * (n // 2):2] + gp[1:2 * (n // 2):2]
+        neg = np.nonzero(G <= 0)[0]
+        G = G[:neg[0]] if neg.size else G
+        G = np.minimum.accumulate(G)
+        tau = max((2.0 * G.sum() - gp[0]) / gp[0], 1.0 / n)
+        tot += n / tau
+    return tot
+
+
+def run_sampler(prec, tgt, args, torch, diam, profile):
+    d, P, nl = args.d, args.P, args.n_lag
+    dev = torch.device("cuda:0")
+    cfg = diam.make_config(d, P, nl, prec, beta=args.beta, seed=args.seed)
+    rdt = torch.float64 if prec == "fp64" else torch.float32
+    mu = torch.as_tensor(tgt["mu"], device=dev)
+    R = torch.as_tensor(tgt["R"], dtype=rdt, device=dev).contiguous()
+    x0 = torch.as_tensor(np.ascontiguousarray(tgt["x0"].T), device=dev)
+    s = diam.Sampler(cfg, mu, R, x0)
+    S0 = torch.as_tensor(tgt["S0"], device=dev)
+    m0 = torch.as_tensor(tgt["m0"], device=dev)
+    st, _ = s.seed_moments(S0, m0, tgt["N0"])
+    assert st == diam.OK
+    proj = torch.as_tensor(np.stack([tgt["v_max"], tgt["v_min"]]), device=dev).contiguous()
+    n_timed = args.steps * nl
+    trace = torch.empty((n_timed, 3, P), dtype=torch.float64, device=dev)
+
+    def window():
+        s.step_batch(nl)
+        s.merge_moments()
+        st, _ = s.update_proposal()
+        if st != diam.OK:
+            raise RuntimeError(f"update_proposal status {st}")
+
+    for _ in range(args.warmup):
+        window()
+    torch.cuda.synchronize()
+    s.set_trace(proj, trace)
+    if profile:
+        s.profile(True)
+        s.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        window()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    prof = s.profile_read(reset=True) if profile else None
+    tr = trace.cpu().numpy()
+    half = n_timed // 2
+    ess = {name: ess_per_chain(tr[half:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
+    nacc = s.get(diam.F_NACC).view(torch.int32).sum().item()
+    s.close()
+    chain_steps = P * n_timed
+    return {
+        "seconds": T,
+        "chain_steps_per_s": chain_steps / T,
+        "steps_per_s": n_timed / T,
+        "ms_per_window": 1e3 * T / args.steps,
+        # ESS over the second half of the timed run, divided by that half's share of the time
+        "ess_per_s": min(ess.values()) / (T * (n_timed - half) / n_timed),
+        "ess": ess,
+        "acceptance": nacc / (P * (n_timed + args.warmup * nl)),
+        "profile": prof,
+    }
+
+
+def cpu_baseline(tgt, args):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    workload: a few steps of all P chains, one merge of those steps and one
+    refactorisation, extrapolated to whole windows."""
+    from oracle import diam as od
+    from oracle import targets as ot
+    from paper_1506_05741_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    d, P, nl = args.d, args.P, args.n_lag
+    R, mu = tgt["R"], tgt["mu"]
+    o = od.DiamOracle(lambda X: ot.gaussian_logpdf(R, mu, X), d, P, nl, args.beta, X=tgt["x0"])
+    o.seed_moments(tgt["S0"], tgt["m0"], tgt["N0"])
+    ns = args.cpu_steps
+    W = synth.draw_normals(d, P, ns, 11)
+    U = synth.draw_uniforms(P, ns, 12)
+    t0 = time.perf_counter()
+    for t in range(ns):
+        o.step(W[t].T, U[t])
+    t_step = (time.perf_counter() - t0) / ns
+    t0 = time.perf_counter()
+    o.merge_moments()
+    t_merge = (time.perf_counter() - t0) * nl / ns       # the scatter scales with the window length
+    t0 = time.perf_counter()
+    o.update_proposal()
+    t_update = time.perf_counter() - t0
+    t_window = nl * t_step + t_merge + t_update
+    return {
+        "value": P * nl / t_window, "unit": "chain-steps/s", "cores": cores, "kind": "oracle",
+        "sample": f"{ns} steps of all {P} chains at d={d}, one merge of those steps scaled to n_lag={nl}, "
+                  f"one FP64 refactorisation; per window {t_window:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12, help="timed windows")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed windows")
+    ap.add_argument("--d", type=int, default=4096)
+    ap.add_argument("--P", type=int, default=256)
+    ap.add_argument("--n-lag", dest="n_lag", type=int, default=256)
+    ap.add_argument("--beta", type=float, default=0.3)
+    ap.add_argument("--seed", type=int, default=2026)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1506_05741_amd import diam, synth
+    diam.load()
+
+    # -- synthetic workload (host), seeded as the d = 4096 configuration ------
+    t0 = time.perf_counter()
+    t = synth.gaussian_target(args.d, 2)
+    x0 = synth.gaussian_exact_draws(t, args.P, 3)
+    S0, m0 = synth.gaussian_warm_moments(t)
+    tgt = dict(mu=t.mu, R=t.R, x0=x0, S0=S0, m0=m0, N0=float(args.P) * 50176,
+               v_max=t.v_max, v_min=t.v_min)
+    log(f"target built in {time.perf_counter() - t0:.1f} s")
+
+    res = run_sampler(args.precision, tgt, args, torch, diam, profile=True)
+    log(f"{args.precision}: {res['chain_steps_per_s']:.4g} chain-steps/s, ESS/s {res['ess_per_s']:.4g}, "
+        f"{res['ms_per_window']:.2f} ms/window, acceptance {res['acceptance']:.3f}")
+    ref = None
+    if not args.no_fp64 and args.precision != "fp64":
+        ref = run_sampler("fp64", tgt, args, torch, diam, profile=True)
+        log(f"fp64: {ref['chain_steps_per_s']:.4g} chain-steps/s, ESS/s {ref['ess_per_s']:.4g}, "
+            f"{ref['ms_per_window']:.2f} ms/window")
+
+    # -- roofline of the dominant kernel: the per-step target contraction -----
+    prof = res["profile"]
+    ms_t, n_t = prof["target"]
+    flops = 2.0 * args.d * args.d * args.P
+    dt = (ms_t / n_t) * 1e-3
+    tdt = "fp64" if args.precision == "fp64" else "fp32"
+    roofline = {
+        "kernel": f"k_tgt_gauss ({tdt} MFMA, Y = R (x - mu), column sums of Y^2)",
+        "bound": "mfma", "achieved": flops / dt / 1e12, "peak": PEAK[tdt] / 1e12, "unit": "TFLOP/s",
+        "frac": flops / dt / PEAK[tdt], "traffic": None, "avg_us": dt * 1e6, "launches": n_t,
+    }
+    stages = {k: {"ms_per_window": v[0] / args.steps, "regions": v[1]} for k, v in prof.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": res["chain_steps_per_s"],
+        "unit": "chain-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_window"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "bf16+fp32 MFMA, fp64 state/accept/Cholesky", "fp32": "fp32 MFMA, fp64 state/accept/Cholesky",
+                  "fp64": "fp64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"Gaussian target d={args.d} (lambda_i=i^-2, seed 2), P={args.P} chains, "
+                               f"n_lag={args.n_lag}, beta={args.beta}, warm start; step = one window",
+                   "precision": args.precision, "d": args.d, "P": args.P, "n_lag": args.n_lag},
+        "ess_per_s": res["ess_per_s"],
+        "steps_per_s": res["steps_per_s"],
+        "acceptance": res["acceptance"],
+        "stage_ms_per_window": stages,
+        "roofline": roofline,
+    }
+    if ref is not None:
+        out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],
+                       "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"]}
+        out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],
+                                  "ess": res["ess_per_s"] / ref["ess_per_s"]}
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(tgt, args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/* diam.h - C ABI of libdiam: dimension-independent adaptive Metropolis (DIAM)
+ * with P periodically synchronised chains on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Chen, Keyes, Law, Ltaief, "Accelerated dimension-independent
+ * adaptive Metropolis", arXiv:1506.05741.  The library runs, for all P chains
+ * at once, the loop of Algorithm 1 (Section 4.3) with the concurrent-chain
+ * logistics of Section 2.4.1 taken with M = 1 (all chains merge their moments
+ * every n_lag steps and share one proposal factor):
+ *
+ *   proposal      x' = x_ref + sqrt(1-beta^2) (x - x_ref) + beta alpha A W
+ *                 (Section 2.3.4, eqs. diam and diamnl)
+ *   acceptance    log alpha = log pi(x') + |z'|^2/(2 alpha^2)
+ *                             - log pi(x) - |z|^2/(2 alpha^2),
+ *                 z = A^-1 (x - x_ref)   (Section 2.2 eq. accept, in the form
+ *                 Algorithm 1 prints, with the pivot x_ref restored)
+ *   moments       running raw first and second moments of every visited
+ *                 state (eqs. mom2p/mom1p/mom2g/mom1g), C = S - m m^T
+ *                 (eq. sampcov)
+ *   refactorise   A = chol(C) every n_lag steps, x_ref = m.
+ *
+ * Conventions
+ *   - Every pointer argument is a DEVICE pointer unless marked "host".
+ *   - Matrices are column-major with leading dimension d; chain p is
+ *     column p of a d x P state matrix.  Exception: the Gaussian target's
+ *     R is row-major (R[i*d + k]).
+ *   - The caller owns every device buffer (workspace, x0, W, U, target
+ *     arrays, trace); the library owns only the opaque context.  Buffers must
+ *     outlive the context.  The library never allocates device memory.
+ *   - All work is enqueued on the stream given to diam_init, in order.
+ *     diam_update_proposal synchronises that stream (it reads the Cholesky
+ *     status back); every other call is asynchronous.
+ *   - Every call returns a diam_status; a negative value is an error and
+ *     diam_last_error() (per host thread) describes it.  No call throws.
+ *   - Precision: DIAM_FP64 runs every stage in FP64.  DIAM_FP32 runs the
+ *     proposal contraction, the target contraction and the window scatter on
+ *     FP32 MFMA.  DIAM_MIXED runs the proposal contraction and the scatter on
+ *     BF16 MFMA with FP32 accumulation and the target contraction on FP32
+ *     MFMA.  In every precision the chain states, z, log densities, the
+ *     acceptance test, the moment accumulators and the Cholesky factorisation
+ *     are FP64, and the factor and normals are rounded to the format the
+ *     contraction consumes, with the acceptance using exactly those rounded
+ *     values (the MH ratio stays exact for the kernel actually applied).
+ *   - Determinism: with fixed inputs (or a fixed seed) results are bitwise
+ *     reproducible run to run; no floating-point atomics are used.
+ */
+#ifndef DIAM_H
+#define DIAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct diam_ctx diam_ctx; /* opaque */
+
+typedef enum {
+  DIAM_OK = 0,
+  DIAM_E_ARG = -1,    /* invalid argument (null pointer, size, too-small workspace) */
+  DIAM_E_STATE = -2,  /* call out of order (see each call) */
+  DIAM_E_HIP = -3,    /* a HIP runtime call or kernel launch failed */
+  DIAM_E_NOT_PD = -4, /* Cholesky failed at every jitter level; previous factor kept */
+  DIAM_E_TARGET = -5  /* the target log density returned +inf */
+} diam_status;
+
+typedef enum { DIAM_FP64 = 0, DIAM_FP32 = 1, DIAM_MIXED = 2 } diam_precision;
+
+typedef enum { DIAM_TGT_GAUSS = 0 } diam_target_kind;
+
+/* Sampler configuration (host struct, copied by diam_init). */
+typedef struct {
+  int32_t d;            /* dimension of the state, >= 1 */
+  int32_t P;            /* number of concurrent chains, >= 1 */
+  int32_t n_lag;        /* steps between proposal updates (Section 2.4.1) */
+  int32_t precision;    /* diam_precision */
+  double beta;          /* step size, 0 < beta <= 1 (eq. diam) */
+  double alpha;         /* inflation factor, >= 1 (eq. diamnl); 1 for Gaussian targets */
+  uint64_t seed;        /* Philox4x32-10 key for internally drawn W and U */
+  double jitter0;       /* Cholesky retry: eps_j = 10^j jitter0 s, s = tr(C)/d (1 if not > 0) */
+  int32_t jitter_tries; /* number of retry levels j = 0 .. jitter_tries-1 */
+  int32_t reserved;
+} diam_config;
+
+/* Target log density (Section 2.1: only the unnormalised density is needed).
+ * DIAM_TGT_GAUSS: log pi(x) = -1/2 ||R (x - mu)||^2, R d x d row-major with
+ * R^T R = Sigma^-1 (any square root of the precision).  R is FP64 for
+ * DIAM_FP64 and FP32 otherwise; mu is FP64.  Evaluating it costs one dense
+ * d x d by d x P contraction per step, the cost model of the paper's test
+ * targets (Section 3.1). */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  const double* mu;
+  const void* R;
+} diam_target;
+
+/* Fields readable with diam_get (device-to-device copy, asynchronous). */
+typedef enum {
+  DIAM_F_X = 0,       /* d x P f64  current states */
+  DIAM_F_Z = 1,       /* d x P f64  A^-1 (x - x_ref) of the current states */
+  DIAM_F_LOGP = 2,    /* P f64      log pi of the current states */
+  DIAM_F_ZQ = 3,      /* P f64      |z|^2 of the current states */
+  DIAM_F_XREF = 4,    /* d f64      pivot x_ref */
+  DIAM_F_L = 5,       /* d x d f64  proposal factor A (lower; rounded to the
+                                    contraction format in FP32/MIXED) */
+  DIAM_F_S = 6,       /* d x d f64  global raw second moment S^glob */
+  DIAM_F_M = 7,       /* d f64      global mean m^glob */
+  DIAM_F_XI = 8,      /* d x P n f64/f32: beta alpha A W of the last
+                                    diam_step_batch call (n = its n_steps) */
+  DIAM_F_LA = 9,      /* n x P f64  log alpha of each step of the last call */
+  DIAM_F_ACC = 10,    /* n x P u8   accept decision of each step of the last call */
+  DIAM_F_NACC = 11,   /* P int32    accepted proposals since init (internal counter) */
+  DIAM_F_W = 12,      /* d x P n    normals drawn by the last call when W was NULL:
+                                    f64 (FP64), f32 (FP32), bf16 hi part (MIXED) */
+  DIAM_F_WLO = 13,    /* d x P n    bf16 lo part of those normals (MIXED only) */
+  DIAM_F_U = 14       /* n x P f64  uniforms drawn by the last call when U was NULL */
+} diam_field;
+
+typedef struct {
+  int64_t steps;          /* steps taken since init */
+  int32_t steps_in_window;/* steps since the last merge */
+  int32_t last_jitter;    /* -1: C factored as is; j >= 0: jitter level; tries: failed */
+  double n_samples;       /* N: sample count of the global moments (incl. seeded N0) */
+  int64_t windows;        /* merges since init */
+  int64_t last_call_steps;/* n_steps of the last diam_step_batch */
+} diam_stats;
+
+/* Bytes of workspace diam_init needs for cfg (host).  Returns DIAM_E_ARG on a
+ * bad configuration. */
+int diam_workspace_bytes(const diam_config* cfg, size_t* bytes);
+
+/* Create a sampler.  x0: d x P initial states (copied).  Initial proposal:
+ * A = I, x_ref = 0 (Algorithm 1 initialisation, x_ref zero until the first
+ * merge); global moments empty (N = 0).  workspace: >= diam_workspace_bytes,
+ * 256-byte aligned.  hip_stream: a hipStream_t (NULL = default stream).
+ * Evaluates log pi(x0) on the GPU before returning (asynchronously). */
+int diam_init(diam_ctx** out, const diam_config* cfg, const diam_target* tgt, void* workspace, size_t ws_bytes,
+              const double* x0, void* hip_stream);
+
+/* Advance all P chains by n_steps steps of Algorithm 1.
+ * Requires steps_in_window + n_steps <= n_lag (else DIAM_E_STATE).
+ * W: d x P x n_steps f64 standard normals (step-major, each step a d x P
+ *    column-major block), or NULL to draw them with Philox4x32-10 from the
+ *    configured seed.  In FP32/MIXED they are rounded to FP32 (MIXED: split
+ *    into bf16 hi + lo) and the acceptance uses the rounded values.
+ * U: P x n_steps f64 uniforms in (0, 1) (step-major), or NULL for Philox.
+ *    Accept iff log u < log alpha; a NaN log alpha rejects (Section 2.2).
+ * n_accepted: P int32 counters incremented per accepted proposal, or NULL.
+ * The batch of search directions beta alpha A W for the n_steps steps is
+ * formed in one contraction first, as Algorithm 1 does every n_lag steps. */
+int diam_step_batch(diam_ctx* ctx, int32_t n_steps, const double* W, const double* U, int32_t* n_accepted);
+
+/* Merge the states visited since the last merge (P chains x steps_in_window,
+ * repeats after rejection included) into the global moments, eqs. mom2p,
+ * mom1p, mom2g, mom1g with sample-count weights:
+ *   S <- (N S + sum x x^T) / (N + K),  m <- (N m + sum x) / (N + K),  N += K.
+ * Requires steps_in_window >= 1 (else DIAM_E_STATE). */
+int diam_merge_moments(diam_ctx* ctx);
+
+/* Refactorise: C = S - m m^T (eq. sampcov); A = chol(C) in FP64, retrying on
+ * C + eps_j I (eps_j = 10^j jitter0 tr(C)/d) when a pivot is not positive;
+ * then x_ref = m and z = A^-1 (x - x_ref) for every current state (FP64
+ * triangular solve).  jitter_used (host, may be NULL): -1, the level j, or
+ * jitter_tries when every try failed (then DIAM_E_NOT_PD, previous factor and
+ * pivot kept).  Requires steps_in_window == 0.  Synchronises the stream. */
+int diam_update_proposal(diam_ctx* ctx, int32_t* jitter_used);
+
+/* Warm start: replace the global moments by (S0, m0) with pseudo-count N0
+ * (device S0 d x d, m0 d), then diam_update_proposal.  Requires
+ * steps_in_window == 0. */
+int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double N0, int32_t* jitter_used);
+
+/* Record per-step traces for effective-sample-size estimates: for each later
+ * step t (counted from this call) trace[(t * (1 + n_proj) + f) * P + p] gets
+ * f = 0: log pi of chain p's state after the step, f >= 1: proj[:, f-1]^T x.
+ * proj: d x n_proj f64 (n_proj <= 4).  capacity: steps the trace can hold;
+ * recording stops when full.  trace == NULL disables. */
+int diam_set_trace(diam_ctx* ctx, const double* proj, int32_t n_proj, double* trace, int64_t capacity);
+
+/* Bytes of a field (host). */
+int diam_field_bytes(diam_ctx* ctx, int32_t field, size_t* bytes);
+/* Copy a field into dst (device); bytes must equal diam_field_bytes. */
+int diam_get(diam_ctx* ctx, int32_t field, void* dst, size_t bytes);
+/* Counters (host struct); does not synchronise. */
+int diam_get_stats(diam_ctx* ctx, diam_stats* out);
+
+/* Per-stage timing with HIP events recorded on the sampler's stream around
+ * each kernel group (the events are collected at the synchronisation inside
+ * diam_update_proposal and in diam_profile_read).  Stages: */
+enum {
+  DIAM_ST_RNG = 0,      /* Philox normals / uniforms, conversion of caller normals */
+  DIAM_ST_PROPOSAL = 1, /* batched beta alpha A W contraction */
+  DIAM_ST_TARGET = 2,   /* target log-density contraction (one event pair per step) */
+  DIAM_ST_STEP = 3,     /* accept / reject + next proposal (one event pair per step) */
+  DIAM_ST_MERGE = 4,    /* window transpose, scatter (SYRK), row sums, fold */
+  DIAM_ST_CHOL = 5,     /* covariance assembly + blocked Cholesky (every try) */
+  DIAM_ST_WHITEN = 6,   /* factor rounding, pivot copy, z = A^-1 (x - x_ref) */
+  DIAM_NSTAGES = 7
+};
+/* Enable (on != 0) or disable event timing.  Enabling creates the events. */
+int diam_profile_enable(diam_ctx* ctx, int32_t on);
+/* Synchronise the stream, then copy per-stage totals (host arrays of
+ * DIAM_NSTAGES): milliseconds and number of timed regions.  reset != 0 zeroes
+ * the totals afterwards. */
+int diam_profile_read(diam_ctx* ctx, double* ms, int64_t* count, int32_t reset);
+
+/* Message for the last non-OK status on this host thread. */
+const char* diam_last_error(void);
+
+/* Release the context (does not free caller buffers). */
+void diam_destroy(diam_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIAM_H */

@@ -1,0 +1,96 @@
+// Host-side launch wrappers for the DIAM kernels (all stream-ordered).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dk {
+
+enum Prec { P64 = 0, P32 = 1, PMIX = 2 };
+
+// Tile of the Gaussian target contraction (rows of R per partial sum).
+constexpr int TGT_BM = 64;
+// Rows of the state matrices handled by one step-kernel workgroup.
+constexpr int STEP_RCH = 512;
+// Cholesky / triangular-solve block size.
+constexpr int CHOL_NB = 64;
+
+inline int tgt_row_blocks(int d) { return (d + TGT_BM - 1) / TGT_BM; }
+inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
+
+// Gaussian target: part[rb][p] = sum over rows of block rb of (R (x_p - mu))_i^2.
+hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
+
+// Xi = c L W over ncols columns; L lower (d x d): f64/f32 column-major,
+// bf16 row-major; W: f64/f32 column-major, bf16 as hi and lo arrays.
+hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, void* Xi, int d, long ncols, double c,
+                   hipStream_t s);
+
+// Scatter of the shifted window Xs (d x K, FP64 result G lower, plus row sums h).
+// f64/f32: column-major Xs (ld = d); bf16: row-major transposed window (ld = K).
+size_t syrk_scratch_bytes(int d, long K);
+hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s);
+hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipStream_t s);
+
+// Fold the window into the global moments (counts N -> N + K).
+hipError_t fold_moments(const double* G, const double* h, const double* sft, double N, long K, double* S, double* m,
+                        int d, hipStream_t s);
+// Cov = S - m m^T + eps I into the lower triangle of C (upper zeroed); trace -> *tr.
+hipError_t cov_assemble(const double* S, const double* m, double eps, double* C, double* tr, int d, hipStream_t s);
+// In-place lower Cholesky; *info = 0 on success, else 1 + first failing column.
+hipError_t potrf(double* A, int d, int* info, hipStream_t s);
+// Round the factor to the working precision in place and emit the low-precision
+// copy (f32 column-major or bf16 row-major); no-op for P64.
+hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s);
+// Z = L^-1 (X - xr) in place of Z (d x P); then zq[p] = ||z_p||^2.
+hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, int d, int P,
+                       hipStream_t s);
+
+// Normals for steps [s0, s0 + n) of P chains; layout per step d x P column-major.
+hipError_t normals(Prec prec, uint64_t seed, long s0, int n, int d, int P, void* W, void* Wlo, hipStream_t s);
+// Uniforms for steps [s0, s0 + n), `stages` per step: U[t][g][p].
+hipError_t uniforms(uint64_t seed, long s0, int n, int P, int stages, double* U, hipStream_t s);
+// Caller FP64 normals -> working format (f32, or bf16 hi/lo).
+hipError_t convert_normals(Prec prec, const double* W64, long count, void* W, void* Wlo, hipStream_t s);
+
+struct StepArgs {
+  int d, P, prec;
+  double rho, c, inv2a2;                  // sqrt(1-beta^2), beta*alpha, 1/(2 alpha^2)
+  const double* xr;                       // d
+  const double* mu;                       // d (Gaussian target)
+  double* X;                              // d x P
+  double* Z;                              // d x P
+  void* V;                                // d x P, f64 or f32 target input
+  // accept half (t >= 0)
+  int do_accept;
+  const void* xi_cur;                     // d x P (f64 or f32)
+  const void* w_cur; const void* wlo_cur; // d x P
+  const double* lpp_part;                 // nrb x P
+  int nrb;
+  const double* zq_part_cur;              // nch x P
+  const double* lp_cur; const double* zq_cur;
+  double* lp_nxt; double* zq_nxt;
+  const double* u;                        // P
+  int* nacc;                              // P, accumulated
+  double* la_out; uint8_t* acc_out;       // P each (this step)
+  void* win; long win_col0;               // window store column offset (t_win * P)
+  double* trace_lp;                       // P or null
+  const double* proj; int nproj; double* proj_part;  // d x nproj; nch x nproj x P
+  int* err;
+  // propose half (next step)
+  int do_propose;
+  const void* xi_nxt;
+  const void* w_nxt; const void* wlo_nxt;
+  double* zq_part_nxt;                    // nch x P
+};
+hipError_t step(const StepArgs& a, hipStream_t s);
+
+// V = X - mu (working precision), Z = X, for the initial evaluation.
+hipError_t init_eval(int prec, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);
+// lp[p] = -1/2 sum_rb part[rb][p]; zq[p] = ||Z_p||^2.
+hipError_t init_finish(const double* part, int nrb, const double* Z, double* lp, double* zq, int d, int P,
+                       hipStream_t s);
+// trace[t][1 + k][p] = sum_ch proj_part[t][ch][k][p]
+hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P, double* trace, int nfun,
+                       hipStream_t s);
+
+}  // namespace dk

@@ -1,0 +1,896 @@
+// DIAM kernels for gfx950.  Every kernel is written for 64-wide wavefronts;
+// dense contractions run on MFMA through the tile engines of gemm.h.
+#include <math.h>
+
+#include "gemm.h"
+#include "kernels.h"
+
+using namespace gemm;
+
+namespace dk {
+
+// x' = x_ref + rho (x - x_ref) + xi, one rounding sequence used everywhere
+// the proposal of a state is formed (propose and accept must agree bitwise).
+DEV double propose1(double xr, double x, double rho, double xi) { return __fma_rn(rho, x - xr, xr) + xi; }
+
+// ============================================================================
+// (b) target log-density: Gaussian, Y = R (x - mu) on MFMA, then column sums
+// of Y^2 in FP64 per 64-row block (the caller adds the blocks in order).
+// ============================================================================
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
+                                                   double* __restrict__ part) {
+  constexpr int BM = 64, BN = 64;
+  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  __shared__ double red[2][BN];
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  EFrag<T, BM, BN> f;
+  f.zero();
+  e_gemm<T, BM, BN, BK, true, true>(f, R, d, d, V, d, P, i0, j0, 0, d, lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
+#pragma unroll
+  for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double y = (double)f.c[m][n][r];
+        s = __fma_rn(y, y, s);
+      }
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (lane < 16) red[wm][wn * (BN / 2) + n * 16 + lane] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < BN) {
+    const int j = j0 + threadIdx.x;
+    if (j < P) part[(long)blockIdx.x * P + j] = red[0][threadIdx.x] + red[1][threadIdx.x];
+  }
+}
+
+hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
+  dim3 grid(cdiv(d, TGT_BM), cdiv(P, 64));
+  if (prec == P64)
+    hipLaunchKernelGGL((k_tgt_gauss<double, 16>), grid, dim3(256), 0, s, (const double*)R, (const double*)V, d, P, part);
+  else
+    hipLaunchKernelGGL((k_tgt_gauss<float, 32>), grid, dim3(256), 0, s, (const float*)R, (const float*)V, d, P, part);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// (a) proposal contraction Xi = c L W, L lower triangular: the K range of a
+// row tile stops at its last row.
+// ============================================================================
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, const T* __restrict__ W, T* __restrict__ Xi,
+                                                   int d, int ncols, double c) {
+  constexpr int BM = 64, BN = 64;
+  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int kend = min(d, i0 + BM);
+  EFrag<T, BM, BN> f;
+  f.zero();
+  e_gemm<T, BM, BN, BK, false, true>(f, L, d, d, W, d, ncols, i0, j0, 0, kend, lds);
+#pragma unroll
+  for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, T>(m, n, r, ti, tj);
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < d && j < ncols) Xi[i + (long)j * d] = (T)(c * (double)f.c[m][n][r]);
+      }
+}
+
+// bf16: A = L~ row-major (k-contiguous); B = W hi and lo, column-major; the
+// two passes accumulate into the same fp32 registers.
+__global__ __launch_bounds__(256) void k_trigemm_bf16(const u16* __restrict__ L, const u16* __restrict__ Whi,
+                                                      const u16* __restrict__ Wlo, float* __restrict__ Xi, int d,
+                                                      int ncols, float c, int vec_ok) {
+  constexpr int BM = 64, BN = 64;
+  __shared__ u16 lds[b_lds_elems<BM, BN>()];
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int kend = min(d, i0 + BM);
+  BFrag<BM, BN> f;
+  f.zero();
+  b_gemm<BM, BN>(f, L, d, d, vec_ok, Whi, d, ncols, vec_ok, i0, j0, 0, kend, lds);
+  b_gemm<BM, BN>(f, L, d, d, vec_ok, Wlo, d, ncols, vec_ok, i0, j0, 0, kend, lds);
+#pragma unroll
+  for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN>(m, n, r, ti, tj);
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < d && j < ncols) Xi[i + (long)j * d] = c * f.c[m][n][r];
+      }
+}
+
+hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, void* Xi, int d, long ncols, double c,
+                   hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  dim3 grid(cdiv(d, 64), cdiv(ncols, 64));
+  if (prec == P64)
+    hipLaunchKernelGGL((k_trigemm_e<double, 16>), grid, dim3(256), 0, s, (const double*)L, (const double*)W,
+                       (double*)Xi, d, (int)ncols, c);
+  else if (prec == P32)
+    hipLaunchKernelGGL((k_trigemm_e<float, 32>), grid, dim3(256), 0, s, (const float*)L, (const float*)W, (float*)Xi,
+                       d, (int)ncols, c);
+  else {
+    const int vec_ok = (d % 8 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)W % 16 == 0) && ((uintptr_t)Wlo % 16 == 0);
+    hipLaunchKernelGGL(k_trigemm_bf16, grid, dim3(256), 0, s, (const u16*)L, (const u16*)W, (const u16*)Wlo,
+                       (float*)Xi, d, (int)ncols, (float)c, vec_ok);
+  }
+  return hipGetLastError();
+}
+
+// ============================================================================
+// (d) window scatter G = sum_k xs_k xs_k^T (lower tiles) and row sums h.
+// ============================================================================
+DEV void tile_pair(int t, int& bi, int& bj) {
+  // t enumerates (bi >= bj) row by row: t = bi (bi + 1)/2 + bj
+  int b = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((b + 1) * (b + 2) / 2 <= t) ++b;
+  while (b * (b + 1) / 2 > t) --b;
+  bi = b;
+  bj = t - b * (b + 1) / 2;
+}
+
+constexpr int FOLD_K = 4096;  // fp32 accumulation span before folding into fp64
+
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d, int K, int kchunk,
+                                                double* __restrict__ Gpart) {
+  constexpr int BM = 64, BN = 64;
+  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  int bi, bj;
+  tile_pair(blockIdx.x, bi, bj);
+  const int i0 = bi * BM, j0 = bj * BN;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  double acc[EFrag<T, BM, BN>::FM][EFrag<T, BM, BN>::FN][4];
+#pragma unroll
+  for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][n][r] = 0.0;
+  const int span = (sizeof(T) == 8) ? kchunk : FOLD_K;
+  for (int k0 = kb; k0 < ke; k0 += span) {
+    EFrag<T, BM, BN> f;
+    f.zero();
+    e_gemm<T, BM, BN, BK, false, false>(f, Xs, d, d, Xs, d, d, i0, j0, k0, min(ke, k0 + span), lds);
+#pragma unroll
+    for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+#pragma unroll
+      for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][n][r] += (double)f.c[m][n][r];
+  }
+  double* G = Gpart + (long)blockIdx.y * d * d;
+#pragma unroll
+  for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, T>(m, n, r, ti, tj);
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < d && j < d) G[i + (long)j * d] = acc[m][n][r];
+      }
+}
+
+// bf16: Xt is the transposed window (d x K row-major, ld = K).
+__global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, int d, int K, int kchunk, int vec_ok,
+                                                   double* __restrict__ Gpart) {
+  constexpr int BM = 64, BN = 64;
+  __shared__ u16 lds[b_lds_elems<BM, BN>()];
+  int bi, bj;
+  tile_pair(blockIdx.x, bi, bj);
+  const int i0 = bi * BM, j0 = bj * BN;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  double acc[BFrag<BM, BN>::FM][BFrag<BM, BN>::FN][4];
+#pragma unroll
+  for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][n][r] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += FOLD_K) {
+    BFrag<BM, BN> f;
+    f.zero();
+    b_gemm<BM, BN>(f, Xt, K, d, vec_ok, Xt, K, d, vec_ok, i0, j0, k0, min(ke, k0 + FOLD_K), lds);
+#pragma unroll
+    for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
+#pragma unroll
+      for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][n][r] += (double)f.c[m][n][r];
+  }
+  double* G = Gpart + (long)blockIdx.y * d * d;
+#pragma unroll
+  for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN>(m, n, r, ti, tj);
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < d && j < d) G[i + (long)j * d] = acc[m][n][r];
+      }
+}
+
+// Row sums over K of the window.  COLMAJOR: element (i, k) at X[i + k d];
+// otherwise at X[i K + k] (bf16 transposed window).
+template <typename T, bool COLMAJOR>
+__global__ __launch_bounds__(256) void k_rowsum(const T* __restrict__ X, int d, int K, int kchunk,
+                                                double* __restrict__ hpart) {
+  __shared__ double red[4][64];
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  if (COLMAJOR) {
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + r;
+    double s = 0.0;
+    if (i < d)
+      for (int k = kb + q; k < ke; k += 4) s += (double)X[i + (long)k * d];
+    red[q][r] = s;
+    __syncthreads();
+    if (threadIdx.x < 64 && i < d)
+      hpart[(long)blockIdx.y * d + i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+  } else {
+    // one row per wavefront, 4 rows per block
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= d) return;
+    double s = 0.0;
+    for (int k = kb + lane; k < ke; k += 64) s += (double)bf16_bits_to_f32(((const u16*)X)[(long)i * K + k]);
+    s = wave_sum_f64(s);
+    if (lane == 0) hpart[(long)blockIdx.y * d + i] = s;
+  }
+}
+
+// col-major d x K bf16 -> row-major d x K (ld K)
+__global__ __launch_bounds__(256) void k_transpose_bf16(const u16* __restrict__ in, u16* __restrict__ out, int d,
+                                                        long K) {
+  __shared__ u16 tile[64][66];
+  const long k0 = (long)blockIdx.x * 64;
+  const int i0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int kk = ty; kk < 64; kk += 4) {
+    const long k = k0 + kk;
+    const int i = i0 + tx;
+    tile[kk][tx] = (k < K && i < d) ? in[i + k * d] : (u16)0;
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int i = i0 + ii;
+    const long k = k0 + tx;
+    if (i < d && k < K) out[(long)i * K + k] = tile[tx][ii];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ Gpart, int ns,
+                                                       const double* __restrict__ hpart, int nh, int d,
+                                                       double* __restrict__ G, double* __restrict__ h) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long dd = (long)d * d;
+  if (e < dd) {
+    const int i = (int)(e % d), j = (int)(e / d);
+    if (i >= j) {
+      double g = 0.0;
+      for (int q = 0; q < ns; ++q) g += Gpart[q * dd + e];
+      G[e] = g;
+    }
+  }
+  if (e < d) {
+    double s = 0.0;
+    for (int q = 0; q < nh; ++q) s += hpart[(long)q * d + e];
+    h[e] = s;
+  }
+}
+
+// K is split so that at least ~512 workgroups run; chunks are whole
+// multiples of 64 columns (keeps the bf16 vector loads 16-byte aligned).
+static long syrk_kchunk(int d, long K) {
+  const int nt = cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
+  int ns = cdiv(512, nt);
+  const int maxs = (int)((K + 2047) / 2048);
+  if (ns > maxs) ns = maxs;
+  if (ns < 1) ns = 1;
+  long kc = (K + ns - 1) / ns;
+  return ((kc + 63) / 64) * 64;
+}
+static int syrk_splits(int d, long K) {
+  const long kc = syrk_kchunk(d, K);
+  const long ns = (K + kc - 1) / kc;
+  return ns < 1 ? 1 : (int)ns;
+}
+
+size_t syrk_scratch_bytes(int d, long K) {
+  const int ns = syrk_splits(d, K);
+  return (size_t)ns * d * d * sizeof(double) + (size_t)64 * d * sizeof(double);
+}
+
+hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s) {
+  const int ns = syrk_splits(d, K);
+  const int kchunk = (int)syrk_kchunk(d, K);
+  double* Gpart = (double*)scratch;
+  double* hpart = Gpart + (size_t)ns * d * d;
+  const int nt = cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
+  dim3 grid(nt, ns);
+  if (prec == P64)
+    hipLaunchKernelGGL((k_syrk_e<double, 16>), grid, dim3(256), 0, s, (const double*)Xs, d, (int)K, kchunk, Gpart);
+  else if (prec == P32)
+    hipLaunchKernelGGL((k_syrk_e<float, 32>), grid, dim3(256), 0, s, (const float*)Xs, d, (int)K, kchunk, Gpart);
+  else {
+    const int vec_ok = (K % 8 == 0) && ((uintptr_t)Xs % 16 == 0);
+    hipLaunchKernelGGL(k_syrk_bf16, grid, dim3(256), 0, s, (const u16*)Xs, d, (int)K, kchunk, vec_ok, Gpart);
+  }
+  // row sums: at most 64 K-chunks
+  const int nh = (int)((K + 4095) / 4096) < 64 ? (int)((K + 4095) / 4096) : 64;
+  const int hchunk = (int)((K + nh - 1) / nh);
+  if (prec == P64)
+    hipLaunchKernelGGL((k_rowsum<double, true>), dim3(cdiv(d, 64), nh), dim3(256), 0, s, (const double*)Xs, d, (int)K,
+                       hchunk, hpart);
+  else if (prec == P32)
+    hipLaunchKernelGGL((k_rowsum<float, true>), dim3(cdiv(d, 64), nh), dim3(256), 0, s, (const float*)Xs, d, (int)K,
+                       hchunk, hpart);
+  else
+    hipLaunchKernelGGL((k_rowsum<u16, false>), dim3(cdiv(d, 4), nh), dim3(256), 0, s, (const u16*)Xs, d, (int)K,
+                       hchunk, hpart);
+  // reduce the splits in order into G (lower) and h
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_splits, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, Gpart, ns, hpart, nh, d, G, h);
+  return hipGetLastError();
+}
+
+hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipStream_t s) {
+  dim3 grid((unsigned)((K + 63) / 64), cdiv(d, 64));
+  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, s, in, out, d, K);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// moment fold (eqs. mom2g / mom1g with sample counts), covariance assembly
+// ============================================================================
+__global__ __launch_bounds__(256) void k_fold_mean(const double* __restrict__ h, const double* __restrict__ sft, double N,
+                                                   double n, double* __restrict__ m, int d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < d) m[i] = (N * m[i] + (h[i] + n * sft[i])) / (N + n);
+}
+
+__global__ __launch_bounds__(256) void k_fold_S(const double* __restrict__ G, const double* __restrict__ h,
+                                                const double* __restrict__ sft, double N, double n,
+                                                double* __restrict__ S, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)d * d) return;
+  const int i = (int)(e % d), j = (int)(e / d);
+  const int a = i > j ? i : j, b = i > j ? j : i;
+  const double g = G[a + (long)b * d];
+  const double sxx = g + sft[a] * h[b] + h[a] * sft[b] + n * sft[a] * sft[b];
+  S[e] = (N * S[e] + sxx) / (N + n);
+}
+
+hipError_t fold_moments(const double* G, const double* h, const double* sft, double N, long K, double* S, double* m,
+                        int d, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_S, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, G, h, sft, N, (double)K, S, d);
+  hipLaunchKernelGGL(k_fold_mean, dim3(cdiv(d, 256)), dim3(256), 0, s, h, sft, N, (double)K, m, d);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_cov(const double* __restrict__ S, const double* __restrict__ m, double eps,
+                                             double* __restrict__ C, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)d * d) return;
+  const int i = (int)(e % d), j = (int)(e / d);
+  double v = 0.0;
+  if (i >= j) {
+    v = S[e] - m[i] * m[j];
+    if (i == j) v += eps;
+  }
+  C[e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ S, const double* __restrict__ m, int d,
+                                               double* __restrict__ tr) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) s += S[i + (long)i * d] - m[i] * m[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *tr = red[0];
+}
+
+hipError_t cov_assemble(const double* S, const double* m, double eps, double* C, double* tr, int d, hipStream_t s) {
+  hipLaunchKernelGGL(k_cov, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, S, m, eps, C, d);
+  if (tr) hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, S, m, d, tr);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// (e) blocked right-looking Cholesky, FP64.  Per block column: one kernel
+// factors the diagonal block in LDS (every workgroup redundantly) and solves
+// the panel rows below it; one MFMA kernel updates the trailing lower tiles.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_potrf_panel(double* __restrict__ A, int d, int j0, int jn,
+                                                     int* __restrict__ info) {
+  __shared__ double Ld[CHOL_NB][CHOL_NB + 1];
+  __shared__ double Pn[CHOL_NB][CHOL_NB + 1];
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < jn * jn; idx += 256) {
+    const int r = idx % jn, c = idx / jn;
+    Ld[r][c] = (r >= c) ? A[(j0 + r) + (long)(j0 + c) * d] : 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int c = 0; c < jn; ++c) {
+    if (tid == 0) {
+      const double p = Ld[c][c];
+      if (!(p > 0.0) && fail == 0) fail = c + 1;
+      Ld[c][c] = sqrt(p);
+    }
+    __syncthreads();
+    const double piv = Ld[c][c];
+    for (int r = c + 1 + tid; r < jn; r += 256) Ld[r][c] /= piv;
+    __syncthreads();
+    const int mm = jn - c - 1;
+    for (int idx = tid; idx < mm * mm; idx += 256) {
+      const int rr = idx % mm, qq = idx / mm;
+      if (rr >= qq) Ld[c + 1 + rr][c + 1 + qq] -= Ld[c + 1 + rr][c] * Ld[c + 1 + qq][c];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    for (int idx = tid; idx < jn * jn; idx += 256) {
+      const int r = idx % jn, c = idx / jn;
+      A[(j0 + r) + (long)(j0 + c) * d] = (r >= c) ? Ld[r][c] : 0.0;
+    }
+    if (tid == 0 && fail && *info == 0) *info = j0 + fail;
+    return;
+  }
+  const int i0 = j0 + jn + (blockIdx.x - 1) * CHOL_NB;
+  const int ni = min(CHOL_NB, d - i0);
+  for (int idx = tid; idx < ni * jn; idx += 256) {
+    const int r = idx % ni, c = idx / ni;
+    Pn[r][c] = A[(i0 + r) + (long)(j0 + c) * d];
+  }
+  __syncthreads();
+  if (tid < ni) {
+    for (int c = 0; c < jn; ++c) {
+      double x = Pn[tid][c];
+      for (int q = 0; q < c; ++q) x -= Pn[tid][q] * Ld[c][q];
+      Pn[tid][c] = x / Ld[c][c];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ni * jn; idx += 256) {
+    const int r = idx % ni, c = idx / ni;
+    A[(i0 + r) + (long)(j0 + c) * d] = Pn[r][c];
+  }
+}
+
+// Trailing update A(i, k) -= sum_c A(i, c) A(k, c) over the panel columns,
+// for the lower tiles of block rows/cols >= t0.
+__global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ double lds[e_lds_elems<BM, BN, BK>()];
+  int bi, bk;
+  tile_pair(blockIdx.x, bi, bk);
+  const int i0 = (t0 + bi) * BM, k0 = (t0 + bk) * BN;
+  const double* Pc = A + (long)j0 * d;
+  EFrag<double, BM, BN> f;
+  f.zero();
+  e_gemm<double, BM, BN, BK, false, false>(f, Pc, d, d, Pc, d, d, i0, k0, 0, jn, lds);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, double>(m, n, r, ti, tj);
+        const int i = i0 + ti, k = k0 + tj;
+        if (i < d && k < d) A[i + (long)k * d] -= f.c[m][n][r];
+      }
+}
+
+hipError_t potrf(double* A, int d, int* info, hipStream_t s) {
+  const int nb = cdiv(d, CHOL_NB);
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
+    hipLaunchKernelGGL(k_potrf_panel, dim3(nb - jb), dim3(256), 0, s, A, d, j0, jn, info);
+    const int m = nb - jb - 1;
+    if (m > 0) hipLaunchKernelGGL(k_potrf_update, dim3(m * (m + 1) / 2), dim3(256), 0, s, A, d, j0, jn, jb + 1);
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restrict__ L, void* __restrict__ Llow, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)d * d) return;
+  const int i = (int)(e % d), j = (int)(e / d);
+  const double v = (i >= j) ? L[e] : 0.0;
+  if (prec == P32) {
+    const float f = (float)v;
+    L[e] = (double)f;
+    ((float*)Llow)[e] = f;
+  } else {
+    const u16 h = f32_to_bf16_bits((float)v);
+    L[e] = (double)bf16_bits_to_f32(h);
+    ((u16*)Llow)[(long)i * d + j] = h;
+  }
+}
+
+hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s) {
+  if (prec == P64) return hipSuccess;
+  hipLaunchKernelGGL(k_round_factor, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, (int)prec, L, Llow, d);
+  return hipGetLastError();
+}
+
+// ---- whitening Z = L^-1 (X - xr) ------------------------------------------
+__global__ __launch_bounds__(256) void k_sub_ref(const double* __restrict__ X, const double* __restrict__ xr,
+                                                 double* __restrict__ Z, int d, int P) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < (long)d * P) Z[e] = X[e] - xr[e % d];
+}
+
+// Z_j <- L_jj^-1 Z_j for 64 columns per block (one thread per column).
+__global__ __launch_bounds__(64) void k_trsm_diag(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
+                                                  int j0, int jn) {
+  __shared__ double Ld[CHOL_NB][CHOL_NB + 1];
+  __shared__ double Zs[CHOL_NB][CHOL_NB + 1];
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.x * 64;
+  for (int idx = tid; idx < jn * jn; idx += 64) {
+    const int r = idx % jn, c = idx / jn;
+    Ld[r][c] = L[(j0 + r) + (long)(j0 + c) * d];
+  }
+  for (int q = 0; q < 64; ++q) {
+    const int p = p0 + q;
+    if (tid < jn) Zs[q][tid] = (p < P) ? Z[(j0 + tid) + (long)p * d] : 0.0;
+  }
+  __syncthreads();
+  const int p = p0 + tid;
+  if (p < P) {
+    for (int r = 0; r < jn; ++r) {
+      double x = Zs[tid][r];
+      for (int q = 0; q < r; ++q) x -= Ld[r][q] * Zs[tid][q];
+      Zs[tid][r] = x / Ld[r][r];
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < 64; ++q) {
+    const int pp = p0 + q;
+    if (tid < jn && pp < P) Z[(j0 + tid) + (long)pp * d] = Zs[q][tid];
+  }
+}
+
+// Z_i -= L_ij Z_j for row blocks below j
+__global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
+                                                     int j0, int jn) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ double lds[e_lds_elems<BM, BN, BK>()];
+  const int i0 = j0 + jn + blockIdx.x * BM, p0 = blockIdx.y * BN;
+  EFrag<double, BM, BN> f;
+  f.zero();
+  e_gemm<double, BM, BN, BK, false, true>(f, L + (long)j0 * d, d, d, Z + j0, d, P, i0, p0, 0, jn, lds);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, double>(m, n, r, ti, tj);
+        const int i = i0 + ti, p = p0 + tj;
+        if (i < d && p < P) Z[i + (long)p * d] -= f.c[m][n][r];
+      }
+}
+
+__global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ Z, int d, double* __restrict__ zq) {
+  __shared__ double red[256];
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    const double z = Z[i + (long)p * d];
+    s = __fma_rn(z, z, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) zq[p] = red[0];
+}
+
+hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, int d, int P,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_ref, dim3(cdiv((long)d * P, 256)), dim3(256), 0, s, X, xr, Z, d, P);
+  const int nb = cdiv(d, CHOL_NB);
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(P, 64)), dim3(64), 0, s, L, Z, d, P, j0, jn);
+    const int rem = d - (j0 + jn);
+    if (rem > 0)
+      hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(rem, 64), cdiv(P, 64)), dim3(256), 0, s, L, Z, d, P, j0, jn);
+  }
+  if (zq) hipLaunchKernelGGL(k_colnorm, dim3(P), dim3(256), 0, s, Z, d, zq);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// random numbers: Philox4x32-10 counters (stream 0 = W, 1 + g = U stage g)
+// ============================================================================
+__global__ __launch_bounds__(256) void k_normals(int prec, uint32_t k0, uint32_t k1, long g0, long total,
+                                                 void* __restrict__ W, void* __restrict__ Wlo) {
+  const long stride = (long)gridDim.x * 256;
+  if (prec == P64) {
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; 2 * q < total; q += stride) {
+      const uint64_t ctr = (uint64_t)(g0 + 2 * q);
+      const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
+      const double u1 = u01_f64(r.x, r.y), u2 = u01_f64(r.z, r.w);
+      const double rad = sqrt(-2.0 * log(u1));
+      double sn, cs;
+      sincos(6.283185307179586476925286766559 * u2, &sn, &cs);
+      double* w = (double*)W;
+      w[2 * q] = rad * cs;
+      if (2 * q + 1 < total) w[2 * q + 1] = rad * sn;
+    }
+  } else {
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; 4 * q < total; q += stride) {
+      const uint64_t ctr = (uint64_t)(g0 + 4 * q);
+      const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
+      const float ua = u01_f32(r.x), ub = u01_f32(r.y), uc = u01_f32(r.z), ud = u01_f32(r.w);
+      const float ra = sqrtf(-2.0f * logf(ua)), rc = sqrtf(-2.0f * logf(uc));
+      float s1, c1, s2, c2;
+      sincosf(6.28318530717958647692f * ub, &s1, &c1);
+      sincosf(6.28318530717958647692f * ud, &s2, &c2);
+      const float v[4] = {ra * c1, ra * s1, rc * c2, rc * s2};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long idx = 4 * q + e;
+        if (idx < total) {
+          if (prec == P32) {
+            ((float*)W)[idx] = v[e];
+          } else {
+            u16 hi, lo;
+            split_bf16(v[e], hi, lo);
+            ((u16*)W)[idx] = hi;
+            ((u16*)Wlo)[idx] = lo;
+          }
+        }
+      }
+    }
+  }
+}
+
+hipError_t normals(Prec prec, uint64_t seed, long s0, int n, int d, int P, void* W, void* Wlo, hipStream_t s) {
+  const long total = (long)n * P * d;
+  if (total <= 0) return hipSuccess;
+  const long per = (prec == P64) ? 2 : 4;
+  long nq = (total + per - 1) / per;
+  int blocks = (int)((nq + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_normals, dim3(blocks), dim3(256), 0, s, (int)prec, (uint32_t)seed, (uint32_t)(seed >> 32),
+                     s0 * (long)P * d, total, W, Wlo);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_uniforms(uint32_t k0, uint32_t k1, long s0, int n, int P, int stages,
+                                                  double* __restrict__ U) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  const long total = (long)n * stages * P;
+  if (e >= total) return;
+  const int p = (int)(e % P);
+  const long tg = e / P;
+  const int g = (int)(tg % stages);
+  const long t = tg / stages;
+  const uint64_t st = (uint64_t)(s0 + t);
+  const u4_t r = philox4x32_10({(uint32_t)st, (uint32_t)(st >> 32), 1u + (uint32_t)g, (uint32_t)(p >> 1)}, k0, k1);
+  U[e] = (p & 1) ? u01_f64(r.z, r.w) : u01_f64(r.x, r.y);
+}
+
+hipError_t uniforms(uint64_t seed, long s0, int n, int P, int stages, double* U, hipStream_t s) {
+  const long total = (long)n * stages * P;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_uniforms, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), s0, n, P, stages, U);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_convert_normals(int prec, const double* __restrict__ W64, long count,
+                                                         void* __restrict__ W, void* __restrict__ Wlo) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  const float f = (float)W64[e];
+  if (prec == P32) {
+    ((float*)W)[e] = f;
+  } else {
+    u16 hi, lo;
+    split_bf16(f, hi, lo);
+    ((u16*)W)[e] = hi;
+    ((u16*)Wlo)[e] = lo;
+  }
+}
+
+hipError_t convert_normals(Prec prec, const double* W64, long count, void* W, void* Wlo, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert_normals, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, (int)prec, W64, count,
+                     W, Wlo);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// (c) accept / reject of step t fused with the proposal of step t+1.
+// One wavefront per (chain, 512-row chunk); the chain's decision is formed
+// redundantly by every wavefront of that chain from the same partial sums in
+// the same order, so all of them agree bitwise.
+// ============================================================================
+template <int PR> struct StepT;
+template <> struct StepT<P64> { typedef double XI; typedef double WT; typedef double VT; typedef double WIN; };
+template <> struct StepT<P32> { typedef float XI; typedef float WT; typedef float VT; typedef float WIN; };
+template <> struct StepT<PMIX> { typedef float XI; typedef u16 WT; typedef float VT; typedef u16 WIN; };
+
+template <int PR>
+DEV double load_w(const void* w, const void* wlo, long e) {
+  if (PR == P64) return ((const double*)w)[e];
+  if (PR == P32) return (double)((const float*)w)[e];
+  return (double)bf16_bits_to_f32(((const u16*)w)[e]) + (double)bf16_bits_to_f32(((const u16*)wlo)[e]);
+}
+
+template <int PR>
+DEV void store_win(void* win, long e, double v) {
+  if (PR == P64) ((double*)win)[e] = v;
+  else if (PR == P32) ((float*)win)[e] = (float)v;
+  else ((u16*)win)[e] = f32_to_bf16_bits((float)v);
+}
+
+constexpr int MAXPROJ = 4;
+
+template <int PR>
+__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+  typedef typename StepT<PR>::XI XI;
+  typedef typename StepT<PR>::VT VT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.y * 4 + w;
+  const int ch = blockIdx.x;
+  if (p >= a.P) return;
+  const int d = a.d, P = a.P;
+  const int nch = gridDim.x;
+  const int r0 = ch * STEP_RCH, r1 = min(d, r0 + STEP_RCH);
+  bool acc = false;
+  if (a.do_accept) {
+    double s = 0.0;
+    for (int q = lane; q < a.nrb; q += 64) s += a.lpp_part[(long)q * P + p];
+    s = wave_sum_f64(s);
+    const double lpp = -0.5 * s;
+    double zs = 0.0;
+    for (int q = lane; q < nch; q += 64) zs += a.zq_part_cur[(long)q * P + p];
+    zs = wave_sum_f64(zs);
+    const double lp = a.lp_cur[p], zq = a.zq_cur[p];
+    const double la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
+    acc = log(a.u[p]) < la;  // NaN compares false: rejected
+    if (ch == 0 && lane == 0) {
+      a.lp_nxt[p] = acc ? lpp : lp;
+      a.zq_nxt[p] = acc ? zs : zq;
+      a.nacc[p] += acc ? 1 : 0;
+      a.la_out[p] = la;
+      a.acc_out[p] = acc ? 1 : 0;
+      if (a.trace_lp) a.trace_lp[p] = acc ? lpp : lp;
+      if (isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
+    }
+  }
+  double zacc = 0.0;
+  double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
+  const XI* xi_cur = (const XI*)a.xi_cur;
+  const XI* xi_nxt = (const XI*)a.xi_nxt;
+  VT* V = (VT*)a.V;
+  for (int i = r0 + lane; i < r1; i += 64) {
+    const long e = i + (long)p * d;
+    double x = a.X[e], z = a.Z[e];
+    const double xr = a.xr[i];
+    if (a.do_accept) {
+      if (acc) {
+        x = propose1(xr, x, a.rho, (double)xi_cur[e]);
+        z = __fma_rn(a.c, load_w<PR>(a.w_cur, a.wlo_cur, e), a.rho * z);
+        a.X[e] = x;
+        a.Z[e] = z;
+      }
+      store_win<PR>(a.win, i + (a.win_col0 + p) * (long)d, x - xr);
+      for (int k = 0; k < a.nproj; ++k) pacc[k] = __fma_rn(a.proj[i + (long)k * d], x, pacc[k]);
+    }
+    if (a.do_propose) {
+      const double xp = propose1(xr, x, a.rho, (double)xi_nxt[e]);
+      V[e] = (VT)(xp - a.mu[i]);
+      const double zp = __fma_rn(a.c, load_w<PR>(a.w_nxt, a.wlo_nxt, e), a.rho * z);
+      zacc = __fma_rn(zp, zp, zacc);
+    }
+  }
+  if (a.do_propose) {
+    zacc = wave_sum_f64(zacc);
+    if (lane == 0) a.zq_part_nxt[(long)ch * P + p] = zacc;
+  }
+  if (a.do_accept && a.nproj > 0) {
+    for (int k = 0; k < a.nproj; ++k) {
+      const double v = wave_sum_f64(pacc[k]);
+      if (lane == 0) a.proj_part[((long)ch * a.nproj + k) * P + p] = v;
+    }
+  }
+}
+
+hipError_t step(const StepArgs& a, hipStream_t s) {
+  dim3 grid(step_chunks(a.d), cdiv(a.P, 4));
+  if (a.prec == P64) hipLaunchKernelGGL(k_step<P64>, grid, dim3(256), 0, s, a);
+  else if (a.prec == P32) hipLaunchKernelGGL(k_step<P32>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_step<PMIX>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_init_eval(int prec, const double* __restrict__ X, const double* __restrict__ mu,
+                                                   void* __restrict__ V, double* __restrict__ Z, int d, long n) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const double x = X[e];
+  const double v = x - mu[e % d];
+  if (prec == P64) ((double*)V)[e] = v;
+  else ((float*)V)[e] = (float)v;
+  Z[e] = x;
+}
+
+hipError_t init_eval(int prec, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s) {
+  const long n = (long)d * P;
+  hipLaunchKernelGGL(k_init_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prec, X, mu, V, Z, d, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(64) void k_init_finish(const double* __restrict__ part, int nrb, int P,
+                                                    double* __restrict__ lp) {
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nrb; q += 64) s += part[(long)q * P + p];
+  s = wave_sum_f64(s);
+  if (threadIdx.x == 0) lp[p] = -0.5 * s;
+}
+
+hipError_t init_finish(const double* part, int nrb, const double* Z, double* lp, double* zq, int d, int P,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_init_finish, dim3(P), dim3(64), 0, s, part, nrb, P, lp);
+  hipLaunchKernelGGL(k_colnorm, dim3(P), dim3(256), 0, s, Z, d, zq);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_proj_reduce(const double* __restrict__ proj_part, int n, int nch, int nproj,
+                                                     int P, double* __restrict__ trace, int nfun) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n * nproj * P) return;
+  const int p = (int)(e % P);
+  const int k = (int)((e / P) % nproj);
+  const long t = e / ((long)P * nproj);
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += proj_part[((t * nch + c) * nproj + k) * P + p];
+  trace[(t * nfun + 1 + k) * P + p] = s;
+}
+
+hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P, double* trace, int nfun,
+                       hipStream_t s) {
+  const long total = (long)n * nproj * P;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, proj_part, n, nch, nproj, P,
+                     trace, nfun);
+  return hipGetLastError();
+}
+
+}  // namespace dk

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libdiam (include/diam.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP
+kernels of ``libdiam.so``.  PyTorch supplies device memory (the workspace and
+all caller buffers) and the stream.  ``load()`` raises when the library is
+missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiam.so")
+
+FP64, FP32, MIXED = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+
+OK, E_ARG, E_STATE, E_HIP, E_NOT_PD, E_TARGET = 0, -1, -2, -3, -4, -5
+
+F_X, F_Z, F_LOGP, F_ZQ, F_XREF, F_L, F_S, F_M, F_XI, F_LA, F_ACC, F_NACC, F_W, F_WLO, F_U = range(15)
+
+EXPORTED = (
+    "diam_workspace_bytes", "diam_init", "diam_step_batch", "diam_merge_moments", "diam_update_proposal",
+    "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
+    "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
+)
+STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("n_lag", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("jitter0", ctypes.c_double), ("jitter_tries", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class Target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_void_p),
+                ("R", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("steps_in_window", ctypes.c_int32), ("last_jitter", ctypes.c_int32),
+                ("n_samples", ctypes.c_double), ("windows", ctypes.c_int64), ("last_call_steps", ctypes.c_int64)]
+
+
+class DiamError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libdiam status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdiam.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1506_05741_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "diam_workspace_bytes": ([ctypes.POINTER(Config), ctypes.POINTER(sz)], ctypes.c_int),
+        "diam_init": ([ctypes.POINTER(vp), ctypes.POINTER(Config), ctypes.POINTER(Target), vp, sz, vp, vp],
+                      ctypes.c_int),
+        "diam_step_batch": ([vp, i32, vp, vp, vp], ctypes.c_int),
+        "diam_merge_moments": ([vp], ctypes.c_int),
+        "diam_update_proposal": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "diam_seed_moments": ([vp, vp, vp, dbl, ctypes.POINTER(i32)], ctypes.c_int),
+        "diam_set_trace": ([vp, vp, i32, vp, i64], ctypes.c_int),
+        "diam_field_bytes": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "diam_get": ([vp, i32, vp, sz], ctypes.c_int),
+        "diam_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
+        "diam_last_error": ([], ctypes.c_char_p),
+        "diam_destroy": ([vp], None),
+        "diam_profile_enable": ([vp, i32], ctypes.c_int),
+        "diam_profile_read": ([vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != OK:
+        raise DiamError(status, _lib.diam_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, 0)
+
+
+def workspace_bytes(cfg: Config) -> int:
+    lib = load()
+    n = ctypes.c_size_t()
+    _check(lib.diam_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+class Sampler:
+    """P DIAM chains on the GPU.  Tensors passed in must be CUDA tensors of the
+    documented dtype and shape (contiguous); the sampler keeps references."""
+
+    def __init__(self, cfg: Config, mu, R, x0, stream=None):
+        import torch
+        lib = load()
+        self.torch = torch
+        self.cfg = cfg
+        self.d, self.P = cfg.d, cfg.P
+        rdt = torch.float64 if cfg.precision == FP64 else torch.float32
+        assert mu.dtype == torch.float64 and mu.is_cuda and mu.numel() == cfg.d and mu.is_contiguous()
+        assert R.dtype == rdt and R.is_cuda and R.shape == (cfg.d, cfg.d) and R.is_contiguous()
+        assert x0.dtype == torch.float64 and x0.is_cuda and x0.numel() == cfg.d * cfg.P and x0.is_contiguous()
+        self._keep = [mu, R, x0]
+        nbytes = workspace_bytes(cfg)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=x0.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(x0.device)
+        self.tgt = Target(0, 0, mu.data_ptr(), R.data_ptr())
+        ctx = ctypes.c_void_p()
+        _check(lib.diam_init(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(self.tgt), _ptr(self.ws),
+                             nbytes, _ptr(x0), ctypes.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+        self.lib = lib
+        self._trace_keep = None
+
+    # -- the sampler's calls ---------------------------------------------------
+    def step_batch(self, n_steps, W=None, U=None, n_accepted=None):
+        torch = self.torch
+        if W is not None:
+            assert W.dtype == torch.float64 and W.is_cuda and W.is_contiguous()
+            assert W.numel() == self.d * self.P * n_steps
+        if U is not None:
+            assert U.dtype == torch.float64 and U.is_cuda and U.is_contiguous() and U.numel() == self.P * n_steps
+        if n_accepted is not None:
+            assert n_accepted.dtype == torch.int32 and n_accepted.is_cuda and n_accepted.numel() == self.P
+        _check(self.lib.diam_step_batch(self.ctx, int(n_steps), _ptr(W), _ptr(U), _ptr(n_accepted)))
+
+    def merge_moments(self):
+        _check(self.lib.diam_merge_moments(self.ctx))
+
+    def update_proposal(self):
+        j = ctypes.c_int32()
+        st = self.lib.diam_update_proposal(self.ctx, ctypes.byref(j))
+        if st not in (OK, E_NOT_PD):
+            _check(st)
+        return st, j.value
+
+    def seed_moments(self, S0, m0, N0):
+        torch = self.torch
+        assert S0.dtype == torch.float64 and S0.is_cuda and S0.numel() == self.d * self.d and S0.is_contiguous()
+        assert m0.dtype == torch.float64 and m0.is_cuda and m0.numel() == self.d
+        self._keep += [S0, m0]
+        j = ctypes.c_int32()
+        st = self.lib.diam_seed_moments(self.ctx, _ptr(S0), _ptr(m0), float(N0), ctypes.byref(j))
+        if st not in (OK, E_NOT_PD):
+            _check(st)
+        return st, j.value
+
+    def set_trace(self, proj, trace):
+        """proj: d x n_proj f64 (column-major, i.e. a (n_proj, d) C-ordered tensor)
+        or None; trace: (capacity, 1 + n_proj, P) f64 or None."""
+        nproj = 0 if proj is None else proj.numel() // self.d
+        cap = 0 if trace is None else trace.shape[0]
+        self._trace_keep = (proj, trace)
+        _check(self.lib.diam_set_trace(self.ctx, _ptr(proj), nproj, _ptr(trace), cap))
+
+    # -- reading back ------------------------------------------------------------
+    def field_bytes(self, field):
+        n = ctypes.c_size_t()
+        _check(self.lib.diam_field_bytes(self.ctx, field, ctypes.byref(n)))
+        return n.value
+
+    def get(self, field):
+        """A fresh CUDA uint8 tensor holding the field's bytes (view it with .view(dtype))."""
+        torch = self.torch
+        n = self.field_bytes(field)
+        out = torch.empty(n, dtype=torch.uint8, device=self.ws.device)
+        _check(self.lib.diam_get(self.ctx, field, _ptr(out), n))
+        return out
+
+    def get_f64(self, field, shape):
+        return self.get(field).view(self.torch.float64).reshape(shape)
+
+    def stats(self):
+        s = Stats()
+        _check(self.lib.diam_get_stats(self.ctx, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def profile(self, on=True):
+        _check(self.lib.diam_profile_enable(self.ctx, 1 if on else 0))
+
+    def profile_read(self, reset=False):
+        """{stage: (total_ms, regions)} since the last reset."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self.lib.diam_profile_read(self.ctx, ms, cnt, 1 if reset else 0))
+        return {STAGES[k]: (ms[k], cnt[k]) for k in range(n)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.diam_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""The C-ABI library loads on the host and exports every symbol the header
+declares; host-only calls validate their arguments.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1506_05741_amd import diam
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "diam.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(diam_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(diam.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(diam.EXPORTED) == names
+
+
+def test_binding_loads():
+    lib = diam.load()
+    assert lib.diam_last_error() is not None
+
+
+def test_workspace_bytes_scales_with_precision():
+    big = diam.workspace_bytes(diam.make_config(4096, 256, 256, "fp64"))
+    mix = diam.workspace_bytes(diam.make_config(4096, 256, 256, "mixed"))
+    assert 6 * 2 ** 30 < big < 8 * 2 ** 30
+    assert mix < 0.6 * big
+    assert diam.workspace_bytes(diam.make_config(1, 1, 1)) > 0
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(d=0), "d, P and n_lag"),
+    (dict(beta=1.5), "beta"),
+    (dict(beta=0.0), "beta"),
+    (dict(alpha=0.5), "alpha"),
+    (dict(precision=7), "precision"),
+    (dict(jitter0=-1.0), "jitter0"),
+])
+def test_bad_config_is_rejected(kw, msg):
+    base = dict(d=8, P=2, n_lag=4, precision="fp64", beta=0.3, alpha=1.0)
+    base.update(kw)
+    cfg = diam.make_config(**base)
+    with pytest.raises(diam.DiamError) as e:
+        diam.workspace_bytes(cfg)
+    assert e.value.status == diam.E_ARG and msg in str(e.value)
+
+
+def test_null_arguments_are_rejected():
+    lib = diam.load()
+    ctx = ctypes.c_void_p()
+    cfg = diam.make_config(8, 2, 4)
+    st = lib.diam_init(ctypes.byref(ctx), ctypes.byref(cfg), None, None, 0, None, None)
+    assert st == diam.E_ARG
+    assert lib.diam_step_batch(None, 1, None, None, None) == diam.E_ARG
+    assert lib.diam_merge_moments(None) == diam.E_ARG
+    assert lib.diam_update_proposal(None, None) == diam.E_ARG
+    assert b"null" in lib.diam_last_error()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    saved = diam._lib
+    diam._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="missing"):
+            diam.load(str(tmp_path / "libdiam.so"))
+    finally:
+        diam._lib = saved
+
+
+def test_philox_reference_matches_published_kat():
+    from tests.philox_ref import philox4x32_10
+    path = os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = philox4x32_10(*v[:6])
+        assert [int(o) for o in out] == v[6:]
