@@ -231,7 +231,8 @@ def main():
     }
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],
-                       "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"]}
+                       "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"],
+                       "stage_ms_per_window": {k: v[0] / args.steps for k, v in ref["profile"].items()}}
         out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],
                                   "ess": res["ess_per_s"] / ref["ess_per_s"]}
     if not args.no_cpu:

@@ -39,7 +39,7 @@ struct Status {  // device-side status words, read back by update_proposal
 
 struct Layout {
   size_t X, Z, V, lp, zq, lpp_part, zq_part, nacc, la, acc, U, W, Wlo, Xi, win, wint, xr, S, m, L, Lnew, Llow, h,
-      syrk, status, proj_part, total;
+      syrk, status, proj_part, linv, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -79,11 +79,12 @@ Layout make_layout(const diam_config& c) {
   L.m = take(d * 8);
   L.L = take(dd * 8);
   L.Lnew = take(dd * 8);
-  L.Llow = take(c.precision == DIAM_FP64 ? 0 : dd * (c.precision == DIAM_MIXED ? 2 : 4));
+  L.Llow = take(c.precision == DIAM_FP64 ? 0 : dd * 4);  // f32, or bf16 hi + lo
   L.h = take(d * 8);
-  L.syrk = take(dk::syrk_scratch_bytes(c.d, (long)P * nl));
+  L.syrk = take(dk::syrk_scratch_bytes(c.precision, c.d, (long)P * nl));
   L.status = take(sizeof(Status));
   L.proj_part = take(nl * (size_t)nch * 4 * P * 8);
+  L.linv = take(dk::chol_scratch_bytes(c.d));
   L.total = o;
   return L;
 }
@@ -98,7 +99,7 @@ struct diam_ctx {
   char* ws;
   Layout lay;
   // device pointers
-  double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part;
+  double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part, *linv;
   void *V, *W, *Wlo, *Xi, *win, *wint, *Llow, *syrk;
   int32_t* nacc;
   uint8_t* acc;
@@ -294,6 +295,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->syrk = c->ws + lay.syrk;
   c->status = (Status*)(c->ws + lay.status);
   c->proj_part = dptr(c, lay.proj_part);
+  c->linv = dptr(c, lay.linv);
   c->nrb = dk::tgt_row_blocks(cfg->d);
   c->nch = dk::step_chunks(cfg->d);
   c->cur = 0;
@@ -490,7 +492,7 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
   int ps = prof_begin(c, DIAM_ST_CHOL);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
   HIPCHK(dk::cov_assemble(c->S, c->m, 0.0, c->Lnew, &c->status->trace, d, s));
-  HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, s));
+  HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
   prof_end(c, ps);
   int r = read_status(c, &st);
   if (r) return r;
@@ -510,7 +512,7 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
       ps = prof_begin(c, DIAM_ST_CHOL);
       hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
       HIPCHK(dk::cov_assemble(c->S, c->m, eps, c->Lnew, nullptr, d, s));
-      HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, s));
+      HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
       prof_end(c, ps);
       r = read_status(c, &st);
       if (r) return r;
@@ -530,7 +532,7 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
   ps = prof_begin(c, DIAM_ST_WHITEN);
   HIPCHK(dk::round_factor(c->prec, c->L, c->Llow, d, s));
   HIPCHK(hipMemcpyAsync(c->xr, c->m, d * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(dk::trsm_whiten(c->L, c->X, c->xr, c->Z, c->zq + (long)c->cur * P, d, P, s));
+  HIPCHK(dk::trsm_whiten(c->L, c->X, c->xr, c->Z, c->zq + (long)c->cur * P, c->linv, d, P, s));
   prof_end(c, ps);
   return DIAM_OK;
 }

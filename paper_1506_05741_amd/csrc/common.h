@@ -16,6 +16,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16;
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 #define DEV static __device__ __forceinline__
 #define DEVM __device__ __forceinline__

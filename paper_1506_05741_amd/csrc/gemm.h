@@ -29,38 +29,68 @@ template <typename T> DEVM typename EAcc<T>::V mfma_e(T a, T b, typename EAcc<T>
 template <> DEVM d4_t mfma_e<double>(double a, double b, d4_t c) { return mfma_f64(a, b, c); }
 template <> DEVM f4_t mfma_e<float>(float a, float b, f4_t c) { return mfma_f32(a, b, c); }
 
+// LDS layout of an operand slice: row r holds its BK values in the order
+// k' = (k % 4) * (BK / 4) + k / 4, so the BK/4 values one lane feeds to the
+// MFMA (k = lk, lk + 4, ...) are contiguous and load as 16-byte vectors.
+// The row stride ELD() is BK plus 16 bytes of padding, which makes the 16
+// rows read by a quarter-wavefront land on distinct banks.
+template <typename T, int BK>
+constexpr int eld() { return BK + 16 / (int)sizeof(T); }
+template <int BK>
+DEV int eperm(int k) { return (k & 3) * (BK / 4) + (k >> 2); }
+
+// Staging registers of one operand slice (ROWS x BK) for one thread of a
+// 256-thread k-group: NV vectors of VEC elements (16 bytes each).
 template <typename T, int ROWS, int BK>
 struct EStage {
-  // per-thread staging registers for one operand slice of ROWS x BK
-  static constexpr int PER = ROWS * BK / NT;
-  T v[PER];
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  static constexpr int NV = ROWS * BK / VEC / NT;
+  static_assert(NV >= 1 && BK % VEC == 0 && ROWS % VEC == 0, "tile too small for 16-byte staging");
+  T v[NV * VEC];
 };
 
-// Load an operand slice [r0, r0+ROWS) x [k0, k0+BK) into registers.
-template <typename T, int ROWS, int BK, bool KC>
-DEV void e_load(EStage<T, ROWS, BK>& s, const T* __restrict__ p, long ld, int nrows, int r0, int k0, int kend) {
-  const int t = threadIdx.x;
+// Load an operand slice [r0, r0+ROWS) x [k0, k0+BK) into registers.  Each
+// thread moves 16-byte vectors along the operand's contiguous direction.
+// FAST: the slice lies inside the operand and is aligned (no guards, so the
+// compiler keeps the loads in flight across the MFMA work); otherwise every
+// element is range-checked and read as zero outside.
+template <typename T, int ROWS, int BK, bool KC, bool FAST>
+DEV void e_load(EStage<T, ROWS, BK>& s, int t, const T* __restrict__ p, long ld, int nrows, int r0, int k0, int kend) {
+  constexpr int VEC = EStage<T, ROWS, BK>::VEC;
 #pragma unroll
-  for (int e = 0; e < EStage<T, ROWS, BK>::PER; ++e) {
-    int idx = t + e * NT;
+  for (int e = 0; e < EStage<T, ROWS, BK>::NV; ++e) {
+    const int c = t + e * NT;
     int r, k;
-    if (KC) { r = idx / BK; k = idx % BK; } else { k = idx / ROWS; r = idx % ROWS; }
-    int gr = r0 + r, gk = k0 + k;
-    T val = T(0);
-    if (gr < nrows && gk < kend) val = KC ? p[(long)gr * ld + gk] : p[gr + (long)gk * ld];
-    s.v[e] = val;
+    if (KC) { r = c / (BK / VEC); k = (c % (BK / VEC)) * VEC; } else { k = c / (ROWS / VEC); r = (c % (ROWS / VEC)) * VEC; }
+    const int gr = r0 + r, gk = k0 + k;
+    T* dst = &s.v[e * VEC];
+    const T* q = KC ? p + (long)gr * ld + gk : p + gr + (long)gk * ld;
+    if (FAST) {
+      *(u32x4_t*)dst = *(const u32x4_t*)q;
+    } else {
+#pragma unroll
+      for (int x = 0; x < VEC; ++x) {
+        const bool ok = KC ? (gr < nrows && gk + x < kend) : (gr + x < nrows && gk < kend);
+        dst[x] = ok ? q[x] : T(0);
+      }
+    }
   }
 }
 
 template <typename T, int ROWS, int BK, bool KC>
-DEV void e_store(const EStage<T, ROWS, BK>& s, T* lds) {
-  const int t = threadIdx.x;
+DEV void e_store(const EStage<T, ROWS, BK>& s, int t, T* lds) {
+  constexpr int VEC = EStage<T, ROWS, BK>::VEC;
+  constexpr int LD = eld<T, BK>();
 #pragma unroll
-  for (int e = 0; e < EStage<T, ROWS, BK>::PER; ++e) {
-    int idx = t + e * NT;
+  for (int e = 0; e < EStage<T, ROWS, BK>::NV; ++e) {
+    const int c = t + e * NT;
     int r, k;
-    if (KC) { r = idx / BK; k = idx % BK; } else { k = idx / ROWS; r = idx % ROWS; }
-    lds[r * (BK + 1) + k] = s.v[e];
+    if (KC) { r = c / (BK / VEC); k = (c % (BK / VEC)) * VEC; } else { k = c / (ROWS / VEC); r = (c % (ROWS / VEC)) * VEC; }
+#pragma unroll
+    for (int x = 0; x < VEC; ++x) {
+      if (KC) lds[r * LD + eperm<BK>(k + x)] = s.v[e * VEC + x];
+      else lds[(r + x) * LD + eperm<BK>(k)] = s.v[e * VEC + x];
+    }
   }
 }
 
@@ -79,57 +109,135 @@ struct EFrag {
   }
 };
 
-// Wave (wm, wn) owns rows [wm*BM/2, +BM/2) and columns [wn*BN/2, +BN/2).
+// Wave (wm, wn) of a k-group owns rows [wm*BM/2, +BM/2) and columns
+// [wn*BN/2, +BN/2) of the tile.  Each lane reads its BK/4 operand values per
+// block row as 16-byte vectors, then issues BK/4 MFMAs per block pair.
 template <typename T, int BM, int BN, int BK>
 DEV void e_compute(EFrag<T, BM, BN>& f, const T* As, const T* Bs) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int FM = EFrag<T, BM, BN>::FM, FN = EFrag<T, BM, BN>::FN, Q = BK / 4;
+  constexpr int LD = eld<T, BK>();
+  const int lane = threadIdx.x & 63, w = (threadIdx.x & (NT - 1)) >> 6;
   const int wm = w & 1, wn = w >> 1;
   const int lr = lane & 15, lk = lane >> 4;
+  T a[FM][Q], b[FN][Q];
 #pragma unroll
-  for (int ks = 0; ks < BK; ks += 4) {
-    T a[EFrag<T, BM, BN>::FM], b[EFrag<T, BM, BN>::FN];
+  for (int m = 0; m < FM; ++m) {
+    const T* src = As + (wm * (BM / 2) + m * 16 + lr) * LD + lk * Q;
 #pragma unroll
-    for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
-      a[m] = As[(wm * (BM / 2) + m * 16 + lr) * (BK + 1) + ks + lk];
+    for (int v = 0; v < Q; v += 16 / (int)sizeof(T)) *(u32x4_t*)&a[m][v] = *(const u32x4_t*)(src + v);
+  }
 #pragma unroll
-    for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n)
-      b[n] = Bs[(wn * (BN / 2) + n * 16 + lr) * (BK + 1) + ks + lk];
+  for (int n = 0; n < FN; ++n) {
+    const T* src = Bs + (wn * (BN / 2) + n * 16 + lr) * LD + lk * Q;
 #pragma unroll
-    for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+    for (int v = 0; v < Q; v += 16 / (int)sizeof(T)) *(u32x4_t*)&b[n][v] = *(const u32x4_t*)(src + v);
+  }
 #pragma unroll
-      for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n) f.c[m][n] = mfma_e<T>(a[m], b[n], f.c[m][n]);
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+      for (int n = 0; n < FN; ++n) f.c[m][n] = mfma_e<T>(a[m][q], b[n][q], f.c[m][n]);
+}
+
+// LDS footprint of one k-group in elements (two buffers per operand).
+template <typename T, int BM, int BN, int BK>
+constexpr int e_lds_elems() { return 2 * (BM + BN) * eld<T, BK>(); }
+
+template <typename T, int BM, int BN, int BK, bool AKC, bool BKC, bool FAST>
+DEV void e_loop(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, const T* __restrict__ B, long ldb,
+                int N, int i0, int j0, int kbeg, int kend, T* base, int g, int t, int KG, int nit) {
+  constexpr int LD = eld<T, BK>();
+  // the two buffers are fixed offsets from the shared array (the loop is
+  // unrolled by two), so every access compiles to an LDS instruction
+  T* const A0 = base;
+  T* const A1 = base + BM * LD;
+  T* const B0 = base + 2 * BM * LD;
+  T* const B1 = base + 2 * BM * LD + BN * LD;
+  EStage<T, BM, BK> sa;
+  EStage<T, BN, BK> sb;
+  e_load<T, BM, BK, AKC, FAST>(sa, t, A, lda, M, i0, kbeg + g * BK, kend);
+  e_load<T, BN, BK, BKC, FAST>(sb, t, B, ldb, N, j0, kbeg + g * BK, kend);
+  e_store<T, BM, BK, AKC>(sa, t, A0);
+  e_store<T, BN, BK, BKC>(sb, t, B0);
+  __syncthreads();
+  for (int it = 0; it < nit; it += 2) {
+    {
+      const int kn = kbeg + ((it + 1) * KG + g) * BK;
+      const bool more = it + 1 < nit;
+      if (more) {
+        e_load<T, BM, BK, AKC, FAST>(sa, t, A, lda, M, i0, kn, kend);
+        e_load<T, BN, BK, BKC, FAST>(sb, t, B, ldb, N, j0, kn, kend);
+      }
+      e_compute<T, BM, BN, BK>(f, A0, B0);
+      if (more) {
+        e_store<T, BM, BK, AKC>(sa, t, A1);
+        e_store<T, BN, BK, BKC>(sb, t, B1);
+      }
+      __syncthreads();
+      if (!more) break;
+    }
+    {
+      const int kn = kbeg + ((it + 2) * KG + g) * BK;
+      const bool more = it + 2 < nit;
+      if (more) {
+        e_load<T, BM, BK, AKC, FAST>(sa, t, A, lda, M, i0, kn, kend);
+        e_load<T, BN, BK, BKC, FAST>(sb, t, B, ldb, N, j0, kn, kend);
+      }
+      e_compute<T, BM, BN, BK>(f, A1, B1);
+      if (more) {
+        e_store<T, BM, BK, AKC>(sa, t, A0);
+        e_store<T, BN, BK, BKC>(sb, t, B0);
+      }
+      __syncthreads();
+    }
   }
 }
 
-// LDS footprint in elements (two buffers per operand)
-template <int BM, int BN, int BK>
-constexpr int e_lds_elems() { return 2 * (BM + BN) * (BK + 1); }
-
-// Full K loop over [kbeg, kend).  lds must hold e_lds_elems<BM,BN,BK>() T's.
-template <typename T, int BM, int BN, int BK, bool AKC, bool BKC>
+// K loop over [kbeg, kend) by a workgroup of KG k-groups of 256 threads.
+// k-group g takes the BK-slices g, g + KG, g + 2 KG, ... with its own double
+// buffer, so each SIMD runs KG wavefronts; at the end the groups' partial
+// accumulators are added into group 0 in fixed order (deterministic).  Only
+// group 0's accumulators hold the result.  lds: KG * e_lds_elems elements.
+// Tiles that lie inside both operands with whole, aligned BK-slices take the
+// unguarded fast loop.
+template <typename T, int BM, int BN, int BK, bool AKC, bool BKC, int KG = 1>
 DEV void e_gemm(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, const T* __restrict__ B, long ldb,
                 int N, int i0, int j0, int kbeg, int kend, T* lds) {
-  T* As[2] = {lds, lds + BM * (BK + 1)};
-  T* Bs[2] = {lds + 2 * BM * (BK + 1), lds + 2 * BM * (BK + 1) + BN * (BK + 1)};
-  EStage<T, BM, BK> sa;
-  EStage<T, BN, BK> sb;
+  static_assert(KG == 1 || (KG - 1) * BM * BN <= KG * e_lds_elems<T, BM, BN, BK>(), "exchange does not fit");
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int g = threadIdx.x / NT, t = threadIdx.x % NT;
+  T* base = lds + g * e_lds_elems<T, BM, BN, BK>();
   const int nk = (kend - kbeg + BK - 1) / BK;
-  if (nk <= 0) return;
-  e_load<T, BM, BK, AKC>(sa, A, lda, M, i0, kbeg, kend);
-  e_load<T, BN, BK, BKC>(sb, B, ldb, N, j0, kbeg, kend);
-  e_store<T, BM, BK, AKC>(sa, As[0]);
-  e_store<T, BN, BK, BKC>(sb, Bs[0]);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      e_load<T, BM, BK, AKC>(sa, A, lda, M, i0, kbeg + (kt + 1) * BK, kend);
-      e_load<T, BN, BK, BKC>(sb, B, ldb, N, j0, kbeg + (kt + 1) * BK, kend);
+  const int nit = (nk + KG - 1) / KG;
+  const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % VEC == 0) && ((uintptr_t)B % 16 == 0) &&
+                       (ldb % VEC == 0) && (kbeg % VEC == 0);
+  const bool fast = aligned && (i0 + BM <= M) && (j0 + BN <= N) && ((kend - kbeg) % (BK * KG) == 0);
+  if (nit > 0) {
+    if (fast) e_loop<T, BM, BN, BK, AKC, BKC, true>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kend, base, g, t, KG, nit);
+    else e_loop<T, BM, BN, BK, AKC, BKC, false>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kend, base, g, t, KG, nit);
+  }
+  if (KG > 1) {
+    constexpr int FM = EFrag<T, BM, BN>::FM, FN = EFrag<T, BM, BN>::FN;
+    const int lane = threadIdx.x & 63, w = t >> 6;
+    if (g > 0) {
+#pragma unroll
+      for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lds[(((((g - 1) * 4 + w) * FM + m) * FN + n) * 4 + r) * 64 + lane] = f.c[m][n][r];
     }
-    e_compute<T, BM, BN, BK>(f, As[cur], Bs[cur]);
-    if (kt + 1 < nk) {
-      e_store<T, BM, BK, AKC>(sa, As[cur ^ 1]);
-      e_store<T, BN, BK, BKC>(sb, Bs[cur ^ 1]);
+    __syncthreads();
+    if (g == 0) {
+      for (int gg = 1; gg < KG; ++gg)
+#pragma unroll
+        for (int m = 0; m < FM; ++m)
+#pragma unroll
+          for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              f.c[m][n][r] += lds[(((((gg - 1) * 4 + w) * FM + m) * FN + n) * 4 + r) * 64 + lane];
     }
     __syncthreads();
   }
@@ -141,7 +249,7 @@ DEV void e_gemm(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, c
 //   f64 MFMA:        c[r] = C[4*r + lane/16][lane%16]
 template <int BM, int BN, typename ACC = float>
 DEV void frag_coords(int m, int n, int r, int& ti, int& tj) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x & (NT - 1)) >> 6;
   const int wm = w & 1, wn = w >> 1;
   const int rr = (sizeof(ACC) == 8) ? (4 * r + (lane >> 4)) : (4 * (lane >> 4) + r);
   ti = wm * (BM / 2) + m * 16 + rr;
@@ -240,29 +348,98 @@ constexpr int b_lds_elems() { return 2 * (BM + BN) * (BBK + BPAD); }
 template <int BM, int BN>
 DEV void b_gemm(BFrag<BM, BN>& f, const u16* __restrict__ A, long lda, int M, bool avec, const u16* __restrict__ B,
                 long ldb, int N, bool bvec, int i0, int j0, int kbeg, int kend, u16* lds) {
-  u16* As[2] = {lds, lds + BM * (BBK + BPAD)};
-  u16* Bs[2] = {lds + 2 * BM * (BBK + BPAD), lds + 2 * BM * (BBK + BPAD) + BN * (BBK + BPAD)};
+  // fixed buffer offsets, loop unrolled by two: LDS instructions throughout
+  u16* const A0 = lds;
+  u16* const A1 = lds + BM * (BBK + BPAD);
+  u16* const B0 = lds + 2 * BM * (BBK + BPAD);
+  u16* const B1 = lds + 2 * BM * (BBK + BPAD) + BN * (BBK + BPAD);
   BStage<BM> sa;
   BStage<BN> sb;
   const int nk = (kend - kbeg + BBK - 1) / BBK;
   if (nk <= 0) return;
   b_load<BM>(sa, A, lda, M, i0, kbeg, kend, avec);
   b_load<BN>(sb, B, ldb, N, j0, kbeg, kend, bvec);
-  b_store<BM>(sa, As[0]);
-  b_store<BN>(sb, Bs[0]);
+  b_store<BM>(sa, A0);
+  b_store<BN>(sb, B0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      b_load<BM>(sa, A, lda, M, i0, kbeg + (kt + 1) * BBK, kend, avec);
-      b_load<BN>(sb, B, ldb, N, j0, kbeg + (kt + 1) * BBK, kend, bvec);
+  for (int kt = 0; kt < nk; kt += 2) {
+    {
+      const bool more = kt + 1 < nk;
+      if (more) {
+        b_load<BM>(sa, A, lda, M, i0, kbeg + (kt + 1) * BBK, kend, avec);
+        b_load<BN>(sb, B, ldb, N, j0, kbeg + (kt + 1) * BBK, kend, bvec);
+      }
+      b_compute<BM, BN>(f, A0, B0);
+      if (more) {
+        b_store<BM>(sa, A1);
+        b_store<BN>(sb, B1);
+      }
+      __syncthreads();
+      if (!more) break;
     }
-    b_compute<BM, BN>(f, As[cur], Bs[cur]);
-    if (kt + 1 < nk) {
-      b_store<BM>(sa, As[cur ^ 1]);
-      b_store<BN>(sb, Bs[cur ^ 1]);
+    {
+      const bool more = kt + 2 < nk;
+      if (more) {
+        b_load<BM>(sa, A, lda, M, i0, kbeg + (kt + 2) * BBK, kend, avec);
+        b_load<BN>(sb, B, ldb, N, j0, kbeg + (kt + 2) * BBK, kend, bvec);
+      }
+      b_compute<BM, BN>(f, A1, B1);
+      if (more) {
+        b_store<BM>(sa, A0);
+        b_store<BN>(sb, B0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  }
+}
+
+// Segmented K loop for the bf16 engine: nseg segments each covering
+// [0, kend) of K, segment s reading A + (s & 1) * dA and B + (s >> 1) * dB.
+// With hi/lo operand pairs laid out at fixed element offsets this forms
+// (A_hi + A_lo)(B_hi + B_lo) in one pipelined loop.
+template <int BM, int BN>
+DEV void b_gemm_seg(BFrag<BM, BN>& f, const u16* __restrict__ A, long dA, long lda, int M, const u16* __restrict__ B,
+                    long dB, long ldb, int N, bool vec, int i0, int j0, int kend, int nseg, u16* lds) {
+  u16* const A0 = lds;
+  u16* const A1 = lds + BM * (BBK + BPAD);
+  u16* const B0 = lds + 2 * BM * (BBK + BPAD);
+  u16* const B1 = lds + 2 * BM * (BBK + BPAD) + BN * (BBK + BPAD);
+  BStage<BM> sa;
+  BStage<BN> sb;
+  const int nks = (kend + BBK - 1) / BBK;
+  const int nk = nks * nseg;
+  if (nks <= 0) return;
+  auto load = [&](int kt) {
+    const int sgm = kt / nks, k0 = (kt - sgm * nks) * BBK;
+    b_load<BM>(sa, A + (sgm & 1) * dA, lda, M, i0, k0, kend, vec);
+    b_load<BN>(sb, B + (sgm >> 1) * dB, ldb, N, j0, k0, kend, vec);
+  };
+  load(0);
+  b_store<BM>(sa, A0);
+  b_store<BN>(sb, B0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    {
+      const bool more = kt + 1 < nk;
+      if (more) load(kt + 1);
+      b_compute<BM, BN>(f, A0, B0);
+      if (more) {
+        b_store<BM>(sa, A1);
+        b_store<BN>(sb, B1);
+      }
+      __syncthreads();
+      if (!more) break;
+    }
+    {
+      const bool more = kt + 2 < nk;
+      if (more) load(kt + 2);
+      b_compute<BM, BN>(f, A1, B1);
+      if (more) {
+        b_store<BM>(sa, A0);
+        b_store<BN>(sb, B0);
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -10,7 +10,7 @@ enum Prec { P64 = 0, P32 = 1, PMIX = 2 };
 // Tile of the Gaussian target contraction (rows of R per partial sum).
 constexpr int TGT_BM = 64;
 // Rows of the state matrices handled by one step-kernel workgroup.
-constexpr int STEP_RCH = 512;
+constexpr int STEP_RCH = 128;
 // Cholesky / triangular-solve block size.
 constexpr int CHOL_NB = 64;
 
@@ -21,13 +21,15 @@ inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
 
 // Xi = c L W over ncols columns; L lower (d x d): f64/f32 column-major,
-// bf16 row-major; W: f64/f32 column-major, bf16 as hi and lo arrays.
+// bf16 as hi then lo row-major copies; W: f64/f32 column-major, bf16 as hi
+// and lo arrays.
 hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, void* Xi, int d, long ncols, double c,
                    hipStream_t s);
 
-// Scatter of the shifted window Xs (d x K, FP64 result G lower, plus row sums h).
+// Scatter of the shifted window Xs (d x K): FP64 result G stored in the upper
+// triangle (G(i,j), i >= j, at row j, column i), plus row sums h.
 // f64/f32: column-major Xs (ld = d); bf16: row-major transposed window (ld = K).
-size_t syrk_scratch_bytes(int d, long K);
+size_t syrk_scratch_bytes(int prec, int d, long K);
 hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s);
 hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipStream_t s);
 
@@ -37,13 +39,16 @@ hipError_t fold_moments(const double* G, const double* h, const double* sft, dou
 // Cov = S - m m^T + eps I into the lower triangle of C (upper zeroed); trace -> *tr.
 hipError_t cov_assemble(const double* S, const double* m, double eps, double* C, double* tr, int d, hipStream_t s);
 // In-place lower Cholesky; *info = 0 on success, else 1 + first failing column.
-hipError_t potrf(double* A, int d, int* info, hipStream_t s);
+// Linv: chol_scratch_bytes(d) of scratch (inverses of the diagonal blocks).
+size_t chol_scratch_bytes(int d);
+hipError_t potrf(double* A, int d, int* info, double* Linv, hipStream_t s);
 // Round the factor to the working precision in place and emit the low-precision
-// copy (f32 column-major or bf16 row-major); no-op for P64.
+// copy (f32 column-major, or bf16 hi and lo row-major: L~ = hi + lo); no-op
+// for P64.
 hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s);
 // Z = L^-1 (X - xr) in place of Z (d x P); then zq[p] = ||z_p||^2.
-hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, int d, int P,
-                       hipStream_t s);
+hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, double* Linv, int d,
+                       int P, hipStream_t s);
 
 // Normals for steps [s0, s0 + n) of P chains; layout per step d x P column-major.
 hipError_t normals(Prec prec, uint64_t seed, long s0, int n, int d, int P, void* W, void* Wlo, hipStream_t s);

@@ -18,29 +18,32 @@ DEV double propose1(double xr, double x, double rho, double xi) { return __fma_r
 // of Y^2 in FP64 per 64-row block (the caller adds the blocks in order).
 // ============================================================================
 template <typename T, int BK>
-__global__ __launch_bounds__(256) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
+__global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
                                                    double* __restrict__ part) {
-  constexpr int BM = 64, BN = 64;
-  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  constexpr int BM = 64, BN = 64, KG = 2;
+  __shared__ T lds[KG * e_lds_elems<T, BM, BN, BK>()];
   __shared__ double red[2][BN];
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
   EFrag<T, BM, BN> f;
   f.zero();
-  e_gemm<T, BM, BN, BK, true, true>(f, R, d, d, V, d, P, i0, j0, 0, d, lds);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
+  e_gemm<T, BM, BN, BK, true, true, KG>(f, R, d, d, V, d, P, i0, j0, 0, d, lds);
+  const bool g0 = threadIdx.x < NT;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x & (NT - 1)) >> 6, wm = w & 1, wn = w >> 1;
+  if (g0) {
 #pragma unroll
-  for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n) {
-    double s = 0.0;
+    for (int n = 0; n < EFrag<T, BM, BN>::FN; ++n) {
+      double s = 0.0;
 #pragma unroll
-    for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
+      for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double y = (double)f.c[m][n][r];
-        s = __fma_rn(y, y, s);
-      }
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    if (lane < 16) red[wm][wn * (BN / 2) + n * 16 + lane] = s;
+        for (int r = 0; r < 4; ++r) {
+          double y = (double)f.c[m][n][r];
+          s = __fma_rn(y, y, s);
+        }
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      if (lane < 16) red[wm][wn * (BN / 2) + n * 16 + lane] = s;
+    }
   }
   __syncthreads();
   if (threadIdx.x < BN) {
@@ -52,9 +55,9 @@ __global__ __launch_bounds__(256) void k_tgt_gauss(const T* __restrict__ R, cons
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
   dim3 grid(cdiv(d, TGT_BM), cdiv(P, 64));
   if (prec == P64)
-    hipLaunchKernelGGL((k_tgt_gauss<double, 16>), grid, dim3(256), 0, s, (const double*)R, (const double*)V, d, P, part);
+    hipLaunchKernelGGL((k_tgt_gauss<double, 16>), grid, dim3(512), 0, s, (const double*)R, (const double*)V, d, P, part);
   else
-    hipLaunchKernelGGL((k_tgt_gauss<float, 32>), grid, dim3(256), 0, s, (const float*)R, (const float*)V, d, P, part);
+    hipLaunchKernelGGL((k_tgt_gauss<float, 32>), grid, dim3(512), 0, s, (const float*)R, (const float*)V, d, P, part);
   return hipGetLastError();
 }
 
@@ -66,7 +69,7 @@ template <typename T, int BK>
 __global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, const T* __restrict__ W, T* __restrict__ Xi,
                                                    int d, int ncols, double c) {
   constexpr int BM = 64, BN = 64;
-  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  __shared__ T lds[e_lds_elems<T, BM, BN, BK>()];
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
   const int kend = min(d, i0 + BM);
   EFrag<T, BM, BN> f;
@@ -85,27 +88,38 @@ __global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, cons
       }
 }
 
-// bf16: A = L~ row-major (k-contiguous); B = W hi and lo, column-major; the
-// two passes accumulate into the same fp32 registers.
-__global__ __launch_bounds__(256) void k_trigemm_bf16(const u16* __restrict__ L, const u16* __restrict__ Whi,
-                                                      const u16* __restrict__ Wlo, float* __restrict__ Xi, int d,
-                                                      int ncols, float c, int vec_ok) {
-  constexpr int BM = 64, BN = 64;
+// bf16: Xi^T = W~^T L~^T with the roles swapped so that lanes run along the
+// rows i of Xi (coalesced stores): A operand = W (rows = columns j of W,
+// k-contiguous), B operand = L~ (rows i, k-contiguous, row-major factor).
+// W~ = W_hi + W_lo and L~ = L_hi + L_lo; the four bf16 products run as one
+// segmented, pipelined K loop into the same fp32 registers.
+// Tile order: workgroup ids are dealt round-robin to the 8 XCDs, so ids
+// xcd + 8 k on one XCD take the ni row blocks of one column block of W
+// (longest K range first): that slice of W is fetched into the XCD's L2 once.
+constexpr int TRI_BM = 256, TRI_BN = 128;
+
+__global__ __launch_bounds__(256) void k_trigemm_bf16(const u16* __restrict__ Lhi, const u16* __restrict__ Whi,
+                                                      long dW, float* __restrict__ Xi, int d, int ncols, float c,
+                                                      int vec_ok, int nj, int ni) {
+  constexpr int BM = TRI_BM, BN = TRI_BN;
   __shared__ u16 lds[b_lds_elems<BM, BN>()];
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
-  const int kend = min(d, i0 + BM);
+  const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int jb = (k / ni) * 8 + xcd;
+  if (jb >= nj) return;
+  const int ib = ni - 1 - (k % ni);
+  const int j0 = jb * BM, i0 = ib * BN;
+  const int kend = min(d, i0 + BN);
   BFrag<BM, BN> f;
   f.zero();
-  b_gemm<BM, BN>(f, L, d, d, vec_ok, Whi, d, ncols, vec_ok, i0, j0, 0, kend, lds);
-  b_gemm<BM, BN>(f, L, d, d, vec_ok, Wlo, d, ncols, vec_ok, i0, j0, 0, kend, lds);
+  b_gemm_seg<BM, BN>(f, Whi, dW, d, ncols, Lhi, (long)d * d, d, d, vec_ok, j0, i0, kend, 4, lds);
 #pragma unroll
   for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
 #pragma unroll
     for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int ti, tj;
-        frag_coords<BM, BN>(m, n, r, ti, tj);
+        int tj, ti;
+        frag_coords<BM, BN>(m, n, r, tj, ti);
         const int i = i0 + ti, j = j0 + tj;
         if (i < d && j < ncols) Xi[i + (long)j * d] = c * f.c[m][n][r];
       }
@@ -122,9 +136,13 @@ hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, voi
     hipLaunchKernelGGL((k_trigemm_e<float, 32>), grid, dim3(256), 0, s, (const float*)L, (const float*)W, (float*)Xi,
                        d, (int)ncols, c);
   else {
+    const u16* Lhi = (const u16*)L;
+    const long dW = (const u16*)Wlo - (const u16*)W;
     const int vec_ok = (d % 8 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)W % 16 == 0) && ((uintptr_t)Wlo % 16 == 0);
-    hipLaunchKernelGGL(k_trigemm_bf16, grid, dim3(256), 0, s, (const u16*)L, (const u16*)W, (const u16*)Wlo,
-                       (float*)Xi, d, (int)ncols, (float)c, vec_ok);
+    const int nj = cdiv(ncols, TRI_BM), ni = cdiv(d, TRI_BN);
+    const int groups = (nj + 7) / 8;
+    hipLaunchKernelGGL(k_trigemm_bf16, dim3(groups * 8 * ni), dim3(256), 0, s, Lhi, (const u16*)W, dW, (float*)Xi, d,
+                       (int)ncols, (float)c, vec_ok, nj, ni);
   }
   return hipGetLastError();
 }
@@ -147,7 +165,7 @@ template <typename T, int BK>
 __global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d, int K, int kchunk,
                                                 double* __restrict__ Gpart) {
   constexpr int BM = 64, BN = 64;
-  __shared__ T lds[e_lds_elems<BM, BN, BK>()];
+  __shared__ T lds[e_lds_elems<T, BM, BN, BK>()];
   int bi, bj;
   tile_pair(blockIdx.x, bi, bj);
   const int i0 = bi * BM, j0 = bj * BN;
@@ -181,17 +199,34 @@ __global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d,
         int ti, tj;
         frag_coords<BM, BN, T>(m, n, r, ti, tj);
         const int i = i0 + ti, j = j0 + tj;
-        if (i < d && j < d) G[i + (long)j * d] = acc[m][n][r];
+        if (i < d && j < d) G[j + (long)i * d] = acc[m][n][r];  // G(i,j) at (row j, col i): upper
       }
 }
 
-// bf16: Xt is the transposed window (d x K row-major, ld = K).
+// bf16: Xt is the transposed window (d x K row-major, ld = K).  Tiles are
+// 128 rows (i) x 64 columns (j) covering the lower triangle: in row block bi
+// the column blocks bj < 2 (bi + 1).  fp32 accumulation is folded into fp64
+// every FOLD_BF16 columns of K.
+constexpr int FOLD_BF16 = 2048;
+
+DEV void syrk_tile_128x64(int t, int nbj, int& bi, int& bj) {
+  int b = 0, c0 = 0;
+  for (;;) {
+    const int n = min(2 * b + 2, nbj);
+    if (t < c0 + n) break;
+    c0 += n;
+    ++b;
+  }
+  bi = b;
+  bj = t - c0;
+}
+
 __global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, int d, int K, int kchunk, int vec_ok,
                                                    double* __restrict__ Gpart) {
-  constexpr int BM = 64, BN = 64;
+  constexpr int BM = 128, BN = 64;
   __shared__ u16 lds[b_lds_elems<BM, BN>()];
   int bi, bj;
-  tile_pair(blockIdx.x, bi, bj);
+  syrk_tile_128x64(blockIdx.x, (d + 63) / 64, bi, bj);
   const int i0 = bi * BM, j0 = bj * BN;
   const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
   double acc[BFrag<BM, BN>::FM][BFrag<BM, BN>::FN][4];
@@ -201,10 +236,10 @@ __global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, i
     for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[m][n][r] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += FOLD_K) {
+  for (int k0 = kb; k0 < ke; k0 += FOLD_BF16) {
     BFrag<BM, BN> f;
     f.zero();
-    b_gemm<BM, BN>(f, Xt, K, d, vec_ok, Xt, K, d, vec_ok, i0, j0, k0, min(ke, k0 + FOLD_K), lds);
+    b_gemm<BM, BN>(f, Xt, K, d, vec_ok, Xt, K, d, vec_ok, i0, j0, k0, min(ke, k0 + FOLD_BF16), lds);
 #pragma unroll
     for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
 #pragma unroll
@@ -222,7 +257,7 @@ __global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, i
         int ti, tj;
         frag_coords<BM, BN>(m, n, r, ti, tj);
         const int i = i0 + ti, j = j0 + tj;
-        if (i < d && j < d) G[i + (long)j * d] = acc[m][n][r];
+        if (i < d && j < d) G[j + (long)i * d] = acc[m][n][r];  // G(i,j) at (row j, col i): upper
       }
 }
 
@@ -281,8 +316,8 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict_
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   const long dd = (long)d * d;
   if (e < dd) {
-    const int i = (int)(e % d), j = (int)(e / d);
-    if (i >= j) {
+    const int r = (int)(e % d), c = (int)(e / d);
+    if (r <= c) {  // the scatter is stored in the upper triangle
       double g = 0.0;
       for (int q = 0; q < ns; ++q) g += Gpart[q * dd + e];
       G[e] = g;
@@ -295,10 +330,20 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict_
   }
 }
 
+// Output tiles of the scatter: 64 x 64 lower pairs (f64/f32) or 128 x 64
+// lower-covering tiles (bf16).
+static int syrk_tiles(int prec, int d) {
+  if (prec != PMIX) return cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
+  const int nbi = cdiv(d, 128), nbj = cdiv(d, 64);
+  int n = 0;
+  for (int b = 0; b < nbi; ++b) n += min(2 * b + 2, nbj);
+  return n;
+}
+
 // K is split so that at least ~512 workgroups run; chunks are whole
 // multiples of 64 columns (keeps the bf16 vector loads 16-byte aligned).
-static long syrk_kchunk(int d, long K) {
-  const int nt = cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
+static long syrk_kchunk(int prec, int d, long K) {
+  const int nt = syrk_tiles(prec, d);
   int ns = cdiv(512, nt);
   const int maxs = (int)((K + 2047) / 2048);
   if (ns > maxs) ns = maxs;
@@ -306,23 +351,23 @@ static long syrk_kchunk(int d, long K) {
   long kc = (K + ns - 1) / ns;
   return ((kc + 63) / 64) * 64;
 }
-static int syrk_splits(int d, long K) {
-  const long kc = syrk_kchunk(d, K);
+static int syrk_splits(int prec, int d, long K) {
+  const long kc = syrk_kchunk(prec, d, K);
   const long ns = (K + kc - 1) / kc;
   return ns < 1 ? 1 : (int)ns;
 }
 
-size_t syrk_scratch_bytes(int d, long K) {
-  const int ns = syrk_splits(d, K);
+size_t syrk_scratch_bytes(int prec, int d, long K) {
+  const int ns = syrk_splits(prec, d, K);
   return (size_t)ns * d * d * sizeof(double) + (size_t)64 * d * sizeof(double);
 }
 
 hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s) {
-  const int ns = syrk_splits(d, K);
-  const int kchunk = (int)syrk_kchunk(d, K);
+  const int ns = syrk_splits(prec, d, K);
+  const int kchunk = (int)syrk_kchunk(prec, d, K);
   double* Gpart = (double*)scratch;
   double* hpart = Gpart + (size_t)ns * d * d;
-  const int nt = cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
+  const int nt = syrk_tiles(prec, d);
   dim3 grid(nt, ns);
   if (prec == P64)
     hipLaunchKernelGGL((k_syrk_e<double, 16>), grid, dim3(256), 0, s, (const double*)Xs, d, (int)K, kchunk, Gpart);
@@ -373,7 +418,7 @@ __global__ __launch_bounds__(256) void k_fold_S(const double* __restrict__ G, co
   if (e >= (long)d * d) return;
   const int i = (int)(e % d), j = (int)(e / d);
   const int a = i > j ? i : j, b = i > j ? j : i;
-  const double g = G[a + (long)b * d];
+  const double g = G[b + (long)a * d];  // upper storage
   const double sxx = g + sft[a] * h[b] + h[a] * sft[b] + n * sft[a] * sft[b];
   S[e] = (N * S[e] + sxx) / (N + n);
 }
@@ -419,73 +464,121 @@ hipError_t cov_assemble(const double* S, const double* m, double eps, double* C,
 }
 
 // ============================================================================
-// (e) blocked right-looking Cholesky, FP64.  Per block column: one kernel
-// factors the diagonal block in LDS (every workgroup redundantly) and solves
-// the panel rows below it; one MFMA kernel updates the trailing lower tiles.
+// (e) blocked right-looking Cholesky, FP64, block 64.  Per block column:
+//   k_chol_diag   one wavefront factors the 64 x 64 diagonal block with its
+//                 rows in registers and forms the block's inverse;
+//   k_chol_panel  MFMA: A_ij <- A_ij L_jj^-T as a product with that inverse;
+//   k_chol_update MFMA: trailing lower tiles A_ik -= A_ij A_kj^T.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_potrf_panel(double* __restrict__ A, int d, int j0, int jn,
-                                                     int* __restrict__ info) {
-  __shared__ double Ld[CHOL_NB][CHOL_NB + 1];
-  __shared__ double Pn[CHOL_NB][CHOL_NB + 1];
-  __shared__ int fail;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < jn * jn; idx += 256) {
-    const int r = idx % jn, c = idx / jn;
-    Ld[r][c] = (r >= c) ? A[(j0 + r) + (long)(j0 + c) * d] : 0.0;
+
+// Inverse of the lower-triangular 64 x 64 block held in Ls (row-major, LDS):
+// lane c forms column c of L^-1 by forward substitution; x[] stays in
+// registers (the loops are fully unrolled), Ls reads are broadcasts.
+DEV void tri_inverse_col(const double (*Ls)[CHOL_NB + 1], double* x, int c) {
+#pragma unroll
+  for (int rr = 0; rr < CHOL_NB; ++rr) {
+    double s = (rr == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < rr; ++q) s = __fma_rn(-Ls[rr][q], x[q], s);
+    x[rr] = s / Ls[rr][rr];
   }
-  if (tid == 0) fail = 0;
-  __syncthreads();
-  for (int c = 0; c < jn; ++c) {
-    if (tid == 0) {
-      const double p = Ld[c][c];
-      if (!(p > 0.0) && fail == 0) fail = c + 1;
-      Ld[c][c] = sqrt(p);
+}
+
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
+                                                  double* __restrict__ Linv, int* __restrict__ info) {
+  __shared__ double colv[CHOL_NB];
+  __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
+  const int r = threadIdx.x;
+  double a[CHOL_NB];
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) {
+    double v = 0.0;
+    if (r < jn && c < jn) {
+      if (c <= r) v = A[(j0 + r) + (long)(j0 + c) * d];
+    } else if (c == r) {
+      v = 1.0;  // identity padding beyond the matrix edge
     }
+    a[c] = v;
+  }
+  int fail = 0;
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) {
+    if (r == c) colv[c] = a[c];
     __syncthreads();
-    const double piv = Ld[c][c];
-    for (int r = c + 1 + tid; r < jn; r += 256) Ld[r][c] /= piv;
+    const double piv = colv[c];
+    if (!(piv > 0.0) && fail == 0) fail = c + 1;
+    const double sq = sqrt(piv);
     __syncthreads();
-    const int mm = jn - c - 1;
-    for (int idx = tid; idx < mm * mm; idx += 256) {
-      const int rr = idx % mm, qq = idx / mm;
-      if (rr >= qq) Ld[c + 1 + rr][c + 1 + qq] -= Ld[c + 1 + rr][c] * Ld[c + 1 + qq][c];
-    }
+    double l = a[c];
+    if (r == c) l = sq;
+    else if (r > c) l = a[c] / sq;
+    a[c] = l;
+    colv[r] = (r >= c) ? l : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int q = c + 1; q < CHOL_NB; ++q)
+      if (r >= q) a[q] = __fma_rn(-l, colv[q], a[q]);
     __syncthreads();
   }
-  if (blockIdx.x == 0) {
-    for (int idx = tid; idx < jn * jn; idx += 256) {
-      const int r = idx % jn, c = idx / jn;
-      A[(j0 + r) + (long)(j0 + c) * d] = (r >= c) ? Ld[r][c] : 0.0;
-    }
-    if (tid == 0 && fail && *info == 0) *info = j0 + fail;
-    return;
+  if (r < jn) {
+#pragma unroll
+    for (int c = 0; c < CHOL_NB; ++c)
+      if (c < jn) A[(j0 + r) + (long)(j0 + c) * d] = (c <= r) ? a[c] : 0.0;
   }
-  const int i0 = j0 + jn + (blockIdx.x - 1) * CHOL_NB;
-  const int ni = min(CHOL_NB, d - i0);
-  for (int idx = tid; idx < ni * jn; idx += 256) {
-    const int r = idx % ni, c = idx / ni;
-    Pn[r][c] = A[(i0 + r) + (long)(j0 + c) * d];
+  if (r == 0 && fail && fail <= jn && *info == 0) *info = j0 + fail;
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) Ls[r][c] = (c <= r) ? a[c] : 0.0;
+  __syncthreads();
+  tri_inverse_col(Ls, a, r);
+#pragma unroll
+  for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
+}
+
+// Inverses of all (already factored) diagonal blocks of L, one wave per block.
+__global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ L, int d, double* __restrict__ Linv) {
+  __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
+  const int r = threadIdx.x, j0 = blockIdx.x * CHOL_NB, jn = min(CHOL_NB, d - j0);
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) {
+    double v = (c == r) ? 1.0 : 0.0;
+    if (r < jn && c < jn) v = (c <= r) ? L[(j0 + r) + (long)(j0 + c) * d] : 0.0;
+    Ls[r][c] = v;
   }
   __syncthreads();
-  if (tid < ni) {
-    for (int c = 0; c < jn; ++c) {
-      double x = Pn[tid][c];
-      for (int q = 0; q < c; ++q) x -= Pn[tid][q] * Ld[c][q];
-      Pn[tid][c] = x / Ld[c][c];
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < ni * jn; idx += 256) {
-    const int r = idx % ni, c = idx / ni;
-    A[(i0 + r) + (long)(j0 + c) * d] = Pn[r][c];
-  }
+  double x[CHOL_NB];
+  tri_inverse_col(Ls, x, r);
+  double* out = Linv + (long)blockIdx.x * CHOL_NB * CHOL_NB;
+#pragma unroll
+  for (int q = 0; q < CHOL_NB; ++q) out[q + r * CHOL_NB] = x[q];
+}
+
+// Panel rows below the diagonal block: A(i, j0 + c) <- sum_q A(i, j0 + q) Linv(c, q)
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int d, int j0, int jn,
+                                                    const double* __restrict__ Linv) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
+  const int i0 = j0 + jn + blockIdx.x * BM;
+  EFrag<double, BM, BN> f;
+  f.zero();
+  e_gemm<double, BM, BN, BK, false, false>(f, A + (long)j0 * d, d, d, Linv, CHOL_NB, jn, i0, 0, 0, jn, lds);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, double>(m, n, r, ti, tj);
+        const int i = i0 + ti;
+        if (i < d && tj < jn) A[i + (long)(j0 + tj) * d] = f.c[m][n][r];
+      }
 }
 
 // Trailing update A(i, k) -= sum_c A(i, c) A(k, c) over the panel columns,
 // for the lower tiles of block rows/cols >= t0.
-__global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ double lds[e_lds_elems<BM, BN, BK>()];
+  __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
   int bi, bk;
   tile_pair(blockIdx.x, bi, bk);
   const int i0 = (t0 + bi) * BM, k0 = (t0 + bk) * BN;
@@ -506,13 +599,19 @@ __global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ A, in
       }
 }
 
-hipError_t potrf(double* A, int d, int* info, hipStream_t s) {
+size_t chol_scratch_bytes(int d) { return (size_t)cdiv(d, CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double); }
+
+hipError_t potrf(double* A, int d, int* info, double* Linv, hipStream_t s) {
   const int nb = cdiv(d, CHOL_NB);
   for (int jb = 0; jb < nb; ++jb) {
     const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
-    hipLaunchKernelGGL(k_potrf_panel, dim3(nb - jb), dim3(256), 0, s, A, d, j0, jn, info);
+    double* Li = Linv + (long)jb * CHOL_NB * CHOL_NB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, d, j0, jn, Li, info);
     const int m = nb - jb - 1;
-    if (m > 0) hipLaunchKernelGGL(k_potrf_update, dim3(m * (m + 1) / 2), dim3(256), 0, s, A, d, j0, jn, jb + 1);
+    if (m > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3(m), dim3(256), 0, s, A, d, j0, jn, (const double*)Li);
+      hipLaunchKernelGGL(k_chol_update, dim3(m * (m + 1) / 2), dim3(256), 0, s, A, d, j0, jn, jb + 1);
+    }
   }
   return hipGetLastError();
 }
@@ -527,9 +626,13 @@ __global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restri
     L[e] = (double)f;
     ((float*)Llow)[e] = f;
   } else {
-    const u16 h = f32_to_bf16_bits((float)v);
-    L[e] = (double)bf16_bits_to_f32(h);
-    ((u16*)Llow)[(long)i * d + j] = h;
+    // L~ = hi + lo, both bf16, row-major copies (k-contiguous for the MFMA)
+    const u16 hi = f32_to_bf16_bits((float)v);
+    const double rem = v - (double)bf16_bits_to_f32(hi);
+    const u16 lo = f32_to_bf16_bits((float)rem);
+    L[e] = (double)bf16_bits_to_f32(hi) + (double)bf16_bits_to_f32(lo);
+    ((u16*)Llow)[(long)i * d + j] = hi;
+    ((u16*)Llow)[(long)d * d + (long)i * d + j] = lo;
   }
 }
 
@@ -546,42 +649,34 @@ __global__ __launch_bounds__(256) void k_sub_ref(const double* __restrict__ X, c
   if (e < (long)d * P) Z[e] = X[e] - xr[e % d];
 }
 
-// Z_j <- L_jj^-1 Z_j for 64 columns per block (one thread per column).
-__global__ __launch_bounds__(64) void k_trsm_diag(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
-                                                  int j0, int jn) {
-  __shared__ double Ld[CHOL_NB][CHOL_NB + 1];
-  __shared__ double Zs[CHOL_NB][CHOL_NB + 1];
-  const int tid = threadIdx.x;
-  const int p0 = blockIdx.x * 64;
-  for (int idx = tid; idx < jn * jn; idx += 64) {
-    const int r = idx % jn, c = idx / jn;
-    Ld[r][c] = L[(j0 + r) + (long)(j0 + c) * d];
-  }
-  for (int q = 0; q < 64; ++q) {
-    const int p = p0 + q;
-    if (tid < jn) Zs[q][tid] = (p < P) ? Z[(j0 + tid) + (long)p * d] : 0.0;
-  }
-  __syncthreads();
-  const int p = p0 + tid;
-  if (p < P) {
-    for (int r = 0; r < jn; ++r) {
-      double x = Zs[tid][r];
-      for (int q = 0; q < r; ++q) x -= Ld[r][q] * Zs[tid][q];
-      Zs[tid][r] = x / Ld[r][r];
-    }
-  }
-  __syncthreads();
-  for (int q = 0; q < 64; ++q) {
-    const int pp = p0 + q;
-    if (tid < jn && pp < P) Z[(j0 + tid) + (long)pp * d] = Zs[q][tid];
-  }
+// Z_j <- Linv_jj Z_j (in place: each workgroup reads its 64 x 64 column
+// block completely before writing it back)
+__global__ __launch_bounds__(256) void k_trsm_diag(const double* __restrict__ Linv, double* __restrict__ Z, int d, int P,
+                                                   int j0, int jn) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
+  const int p0 = blockIdx.x * BN;
+  EFrag<double, BM, BN> f;
+  f.zero();
+  e_gemm<double, BM, BN, BK, false, true>(f, Linv, CHOL_NB, jn, Z + j0, d, P, 0, p0, 0, jn, lds);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<BM, BN, double>(m, n, r, ti, tj);
+        const int p = p0 + tj;
+        if (ti < jn && p < P) Z[(j0 + ti) + (long)p * d] = f.c[m][n][r];
+      }
 }
 
 // Z_i -= L_ij Z_j for row blocks below j
 __global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
                                                      int j0, int jn) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ double lds[e_lds_elems<BM, BN, BK>()];
+  __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
   const int i0 = j0 + jn + blockIdx.x * BM, p0 = blockIdx.y * BN;
   EFrag<double, BM, BN> f;
   f.zero();
@@ -616,13 +711,15 @@ __global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ Z, i
   if (threadIdx.x == 0) zq[p] = red[0];
 }
 
-hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, int d, int P,
-                       hipStream_t s) {
+hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, double* Linv, int d,
+                       int P, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_ref, dim3(cdiv((long)d * P, 256)), dim3(256), 0, s, X, xr, Z, d, P);
   const int nb = cdiv(d, CHOL_NB);
+  hipLaunchKernelGGL(k_tri_inv, dim3(nb), dim3(64), 0, s, L, d, Linv);
   for (int jb = 0; jb < nb; ++jb) {
     const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
-    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(P, 64)), dim3(64), 0, s, L, Z, d, P, j0, jn);
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(P, 64)), dim3(256), 0, s, (const double*)(Linv + (long)jb * CHOL_NB * CHOL_NB),
+                       Z, d, P, j0, jn);
     const int rem = d - (j0 + jn);
     if (rem > 0)
       hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(rem, 64), cdiv(P, 64)), dim3(256), 0, s, L, Z, d, P, j0, jn);
@@ -764,13 +861,42 @@ template <int PR>
 __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   typedef typename StepT<PR>::XI XI;
   typedef typename StepT<PR>::VT VT;
+  constexpr int RPL = STEP_RCH / 64;  // rows per lane
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int p = blockIdx.y * 4 + w;
   const int ch = blockIdx.x;
   if (p >= a.P) return;
   const int d = a.d, P = a.P;
   const int nch = gridDim.x;
-  const int r0 = ch * STEP_RCH, r1 = min(d, r0 + STEP_RCH);
+  const int r0 = ch * STEP_RCH;
+  const XI* xi_cur = (const XI*)a.xi_cur;
+  const XI* xi_nxt = (const XI*)a.xi_nxt;
+  VT* V = (VT*)a.V;
+  // issue every row load of this lane first; the chain's decision (which
+  // needs two reductions and a log) overlaps their latency
+  double x[RPL], z[RPL], xr[RPL], xc[RPL], wc[RPL], xn[RPL], wn[RPL], mu[RPL];
+  bool in[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int i = r0 + q * 64 + lane;
+    in[q] = i < d;
+    const long e = i + (long)p * d;
+    x[q] = z[q] = xr[q] = xc[q] = wc[q] = xn[q] = wn[q] = mu[q] = 0.0;
+    if (in[q]) {
+      x[q] = a.X[e];
+      z[q] = a.Z[e];
+      xr[q] = a.xr[i];
+      if (a.do_accept) {
+        xc[q] = (double)xi_cur[e];
+        wc[q] = load_w<PR>(a.w_cur, a.wlo_cur, e);
+      }
+      if (a.do_propose) {
+        xn[q] = (double)xi_nxt[e];
+        wn[q] = load_w<PR>(a.w_nxt, a.wlo_nxt, e);
+        mu[q] = a.mu[i];
+      }
+    }
+  }
   bool acc = false;
   if (a.do_accept) {
     double s = 0.0;
@@ -795,27 +921,26 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   }
   double zacc = 0.0;
   double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
-  const XI* xi_cur = (const XI*)a.xi_cur;
-  const XI* xi_nxt = (const XI*)a.xi_nxt;
-  VT* V = (VT*)a.V;
-  for (int i = r0 + lane; i < r1; i += 64) {
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    if (!in[q]) continue;
+    const int i = r0 + q * 64 + lane;
     const long e = i + (long)p * d;
-    double x = a.X[e], z = a.Z[e];
-    const double xr = a.xr[i];
+    double xv = x[q], zv = z[q];
     if (a.do_accept) {
       if (acc) {
-        x = propose1(xr, x, a.rho, (double)xi_cur[e]);
-        z = __fma_rn(a.c, load_w<PR>(a.w_cur, a.wlo_cur, e), a.rho * z);
-        a.X[e] = x;
-        a.Z[e] = z;
+        xv = propose1(xr[q], xv, a.rho, xc[q]);
+        zv = __fma_rn(a.c, wc[q], a.rho * zv);
+        a.X[e] = xv;
+        a.Z[e] = zv;
       }
-      store_win<PR>(a.win, i + (a.win_col0 + p) * (long)d, x - xr);
-      for (int k = 0; k < a.nproj; ++k) pacc[k] = __fma_rn(a.proj[i + (long)k * d], x, pacc[k]);
+      store_win<PR>(a.win, i + (a.win_col0 + p) * (long)d, xv - xr[q]);
+      for (int k = 0; k < a.nproj; ++k) pacc[k] = __fma_rn(a.proj[i + (long)k * d], xv, pacc[k]);
     }
     if (a.do_propose) {
-      const double xp = propose1(xr, x, a.rho, (double)xi_nxt[e]);
-      V[e] = (VT)(xp - a.mu[i]);
-      const double zp = __fma_rn(a.c, load_w<PR>(a.w_nxt, a.wlo_nxt, e), a.rho * z);
+      const double xp = propose1(xr[q], xv, a.rho, xn[q]);
+      V[e] = (VT)(xp - mu[q]);
+      const double zp = __fma_rn(a.c, wn[q], a.rho * zv);
       zacc = __fma_rn(zp, zp, zacc);
     }
   }

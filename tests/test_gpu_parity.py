@@ -3,11 +3,14 @@
 Bar (FP64): accept decisions identical up to the first near-tie, log alpha
 within the near-tie threshold, states within 1e-12 relative, merged moments,
 factor and pivot within a bound set by the conditioning of the covariance.
-The near-tie threshold is |log alpha - log u| < max(1e-9, 10 kappa(C) u d):
-two correct FP64 Cholesky factorisations of C differ by about kappa(C) u
-relative, and |z|^2 ~ d carries that difference into log alpha, so at
-d = 1024 (kappa ~ 1e6) two exact implementations legitimately disagree at
-the 1e-7 level; at d = 32 the threshold is the fixed 1e-9.  Sizes span several 64-row tiles with
+The near-tie threshold is |log alpha - log u| < max(1e-9, 10 kappa(C) u d)
+and the state tolerance max(1e-12, kappa(C) u): two correct FP64 Cholesky
+factorisations of C differ by about kappa(C) u relative, and |z|^2 ~ d
+carries that into log alpha, so at d = 1024 (kappa ~ 1e6) two exact
+implementations legitimately disagree at the 1e-7 level in log alpha and
+1e-12..1e-10 in the states.  At d = 32 both bars are the fixed 1e-9 and
+1e-12, and a shared-factor run at d = 1024 (the oracle adopts the GPU's
+factor after each update) holds them too.  Sizes span several 64-row tiles with
 ragged tails, a degenerate d = 1 chain and the d = 32 / P = 4 / n_lag = 50
 configuration from a literal cold start.
 """
@@ -42,9 +45,15 @@ def host(t):
 
 
 class Pair:
-    """A GPU sampler and an oracle sampler on the same target and start."""
+    """A GPU sampler and an oracle sampler on the same target and start.
 
-    def __init__(self, d, P, n_lag, tseed, prec="fp64", warm=False, beta=0.3, seed=1234, x0=None, N0=None):
+    share_factor: after every factorisation the oracle adopts the GPU's factor
+    (and recomputes its z), which takes the legitimate rounding differences
+    between two FP64 Cholesky implementations out of the step comparison."""
+
+    def __init__(self, d, P, n_lag, tseed, prec="fp64", warm=False, beta=0.3, seed=1234, x0=None, N0=None,
+                 share_factor=False):
+        self.share = share_factor
         self.t = t = synth.gaussian_target(d, tseed)
         self.d, self.P, self.n_lag = d, P, n_lag
         if x0 is None:
@@ -60,6 +69,13 @@ class Pair:
             assert st == diam.OK
             assert self.o.seed_moments(S, m, n0) == od.OK
             assert j == self.o.last_jitter
+            self.adopt()
+
+    def adopt(self):
+        if self.share:
+            d = self.d
+            self.o.A = host(self.s.get_f64(diam.F_L, (d, d))).T.copy()
+            self.o.Z = od.whiten(self.o.A, self.o.x_ref, self.o.X)
 
     def gx(self):
         return host(self.s.get_f64(diam.F_X, (self.P, self.d))).T
@@ -70,8 +86,19 @@ def rel(a, b):
 
 
 def tie_threshold(pr):
+    if pr.share:
+        return NEAR_TIE
     kappa = np.linalg.cond(pr.o.A) ** 2
     return max(NEAR_TIE, 10.0 * kappa * np.finfo(float).eps * pr.d)
+
+
+def state_tolerance(pr):
+    """1e-12 relative; where the factors are computed independently and C is
+    ill-conditioned, kappa(C) u (the agreement two FP64 factorisations allow)."""
+    if pr.share:
+        return 1e-12
+    kappa = np.linalg.cond(pr.o.A) ** 2
+    return max(1e-12, kappa * np.finfo(float).eps)
 
 
 def run_window(pr, W, U, split=None):
@@ -103,12 +130,17 @@ def run_window(pr, W, U, split=None):
     return upto, first_tie
 
 
-def check_states(pr, tol=1e-12):
+def check_states(pr):
+    tol = state_tolerance(pr)
     Xg = pr.gx()
     for p in range(pr.P):
         assert rel(Xg[:, p], pr.o.X[:, p]) <= tol, (p, rel(Xg[:, p], pr.o.X[:, p]))
+    # the cached log density is the target's value at the state the GPU holds
     lp = host(pr.s.get_f64(diam.F_LOGP, (pr.P,)))
-    assert np.allclose(lp, pr.o.lp, rtol=1e-10, atol=1e-10)
+    lp_ref = ot.gaussian_logpdf(pr.t.R, pr.t.mu, Xg)
+    assert np.allclose(lp, lp_ref, rtol=1e-10, atol=1e-10)
+    if tol <= 1e-12:
+        assert np.allclose(lp, pr.o.lp, rtol=1e-10, atol=1e-10)
 
 
 def check_merge_update(pr, cond_tol=True):
@@ -132,6 +164,7 @@ def check_merge_update(pr, cond_tol=True):
     assert rel(xr, pr.o.x_ref) <= 1e-12
     Z = host(pr.s.get_f64(diam.F_Z, (pr.P, d))).T
     assert rel(Z, pr.o.Z) <= max(1e-10, tol * 10), rel(Z, pr.o.Z)
+    pr.adopt()
     return kappa
 
 
@@ -142,11 +175,14 @@ def check_merge_update(pr, cond_tol=True):
     (130, 3, 7, 5, True, 3, [3, 4]),     # several calls per window
     (1, 1, 5, 6, False, 4, None),        # degenerate d = 1, one chain
     (1024, 64, 10, 1, True, 2, None),    # the d = 1024, P = 64 configuration, short windows
+    (1024, 64, 10, 1, True, 2, "share"), # same, oracle adopts the GPU factor: the strict bar
 ])
 def test_fp64_decision_parity(case):
     d, P, n_lag, tseed, warm, windows, split = case
-    log(f"parity d={d} P={P} n_lag={n_lag} warm={warm} windows={windows}")
-    pr = Pair(d, P, n_lag, tseed, warm=warm)
+    share = split == "share"
+    split = None if share else split
+    log(f"parity d={d} P={P} n_lag={n_lag} warm={warm} windows={windows} shared factor={share}")
+    pr = Pair(d, P, n_lag, tseed, warm=warm, share_factor=share)
     lp0 = host(pr.s.get_f64(diam.F_LOGP, (P,)))
     assert np.allclose(lp0, pr.o.lp, rtol=1e-12, atol=1e-12)
     W = synth.draw_normals(d, P, windows * n_lag, 100 + d)

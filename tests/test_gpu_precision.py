@@ -48,8 +48,9 @@ def make(d, P, n_lag, prec, tseed=3, seed=99, N0=None):
     return t, x0, s
 
 
-# bounds: fp32 contractions ~ 1e-7 relative; bf16 factor ~ 2^-9 per entry
-XI_TOL = {"fp32": 1e-5, "mixed": 8e-3}
+# bounds: fp32 contractions ~ 1e-7 relative; the mixed factor and normals are
+# bf16 hi + lo pairs (~2^-17 relative per entry) with fp32 accumulation
+XI_TOL = {"fp32": 1e-5, "mixed": 1e-4}
 LP_TOL = {"fp32": 1e-4, "mixed": 1e-4}
 S_TOL = {"fp32": 1e-5, "mixed": 5e-3}
 
@@ -99,7 +100,7 @@ def test_per_stage_error_against_fp64(prec):
     assert e_xi < XI_TOL[prec]
     assert e_lp < LP_TOL[prec]
     assert e_S < S_TOL[prec] and e_m < S_TOL[prec]
-    assert e_L < (1e-5 if prec == "fp32" else 8e-3)
+    assert e_L < (1e-5 if prec == "fp32" else 1e-4)
 
 
 def _moments_ok(t, X, k_sigma=4.0):
