@@ -115,6 +115,104 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
     }
 
 
+def learned_experiment(args, torch, diam):
+    """Learned-part form on the logistic-regression posterior (n = 200000,
+    d = 512, P = 128, n_lag = 200): the plain sampler against two-stage
+    delayed acceptance with the MLP surrogate trained on the first 5e4 chain
+    states.  Both runs start from the same warm start (Laplace mode and
+    covariance, host-computed) and run the same collection phase, then the
+    same number of timed windows; ESS/s is over the timed windows."""
+    from paper_1506_05741_amd import synth
+    dev = torch.device("cuda:0")
+    d, P, nl = 512, args.learned_P, 200
+    t0 = time.perf_counter()
+    data = synth.logreg_data()
+    mode, C = synth.logreg_laplace(data)
+    rng = np.random.default_rng(17)
+    Lc = np.linalg.cholesky(C)
+    x0 = mode[:, None] + Lc @ rng.standard_normal((d, P))
+    ev, V = np.linalg.eigh(C)
+    log(f"logistic data + Laplace warm start in {time.perf_counter() - t0:.1f} s")
+    A = torch.as_tensor(data.A, device=dev)
+    y = torch.as_tensor(data.y, device=dev)
+    S0 = torch.as_tensor(C + np.outer(mode, mode), device=dev)
+    m0 = torch.as_tensor(mode, device=dev)
+    proj = torch.as_tensor(np.stack([V[:, -1], V[:, 0]]), device=dev).contiguous()
+    n_pairs = 50000
+    collect = -(-n_pairs // P)                            # steps whose states train the surrogate
+    out = {"workload": f"Bayesian logistic regression n=200000 d={d} (A ~ N(0, 1/d), prior N(0, 10 I)), "
+                       f"P={P}, n_lag={nl}, beta={args.learned_beta}, Laplace warm start",
+           "precision": args.learned_precision}
+    for use_da in (False, True):
+        cfg = diam.make_config(d, P, nl, args.learned_precision, beta=args.learned_beta, seed=91,
+                               surrogate=use_da, train_max=n_pairs)
+        s = diam.Sampler(cfg, None, None, torch.as_tensor(np.ascontiguousarray(x0.T), device=dev), A=A, y=y,
+                         prior_var=data.prior_var)
+        assert s.seed_moments(S0, m0, 10 * P * nl)[0] == diam.OK
+        Xtr = torch.empty((collect * P, d), dtype=torch.float64, device=dev)
+        ltr = torch.empty(collect * P, dtype=torch.float64, device=dev)
+        done = 0
+        while done < collect:                             # collection phase, identical in both runs
+            k = min(collect - done, nl - s.stats()["steps_in_window"])
+            for _ in range(k):
+                s.step_batch(1)
+                Xtr[done * P:(done + 1) * P] = s.get_f64(diam.F_X, (P, d))
+                ltr[done * P:(done + 1) * P] = s.get_f64(diam.F_LOGP, (P,))
+                done += 1
+            if s.stats()["steps_in_window"] == nl:
+                s.merge_moments()
+                assert s.update_proposal()[0] == diam.OK
+        rest = nl - s.stats()["steps_in_window"]          # finish the window
+        if rest:
+            s.step_batch(rest)
+            s.merge_moments()
+            assert s.update_proposal()[0] == diam.OK
+        train_s = None
+        if use_da:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss = s.surrogate_train(Xtr[:n_pairs], ltr[:n_pairs], steps=args.train_steps, batch=256, lr=1e-3,
+                                     seed=5)
+            s.set_delayed_acceptance(True)
+            torch.cuda.synchronize()
+            train_s = time.perf_counter() - t1
+            out["surrogate"] = {"pairs": n_pairs, "adam_steps": args.train_steps, "batch": 256,
+                                "final_loss": loss, "train_seconds": train_s}
+        n_timed = args.learned_windows * nl
+        trace = torch.empty((n_timed, 3, P), dtype=torch.float64, device=dev)
+        s.set_trace(proj, trace)
+        nacc0 = s.get(diam.F_NACC).view(torch.int32).sum().item()
+        s.profile(True)
+        s.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.learned_windows):
+            s.step_batch(nl)
+            s.merge_moments()
+            assert s.update_proposal()[0] == diam.OK
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t1
+        prof = s.profile_read(reset=True)
+        tr = trace.cpu().numpy()
+        ess = {name: ess_per_chain(tr[:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
+        nacc = s.get(diam.F_NACC).view(torch.int32).sum().item() - nacc0
+        r = {"seconds": T, "chain_steps_per_s": P * n_timed / T, "ess": ess, "ess_per_s": min(ess.values()) / T,
+             "acceptance": nacc / (P * n_timed),
+             "stage_ms_per_window": {k: v[0] / args.learned_windows for k, v in prof.items() if v[1]}}
+        if use_da:
+            npass = s.get(diam.F_NPASS).view(torch.int32).sum().item()
+            r["stage1_pass_rate"] = npass / (P * n_timed)
+            r["ess_per_s_incl_training"] = min(ess.values()) / (T + train_s)
+        out["delayed_acceptance" if use_da else "plain"] = r
+        log(f"logistic {'DA' if use_da else 'plain'}: {r['chain_steps_per_s']:.4g} chain-steps/s, "
+            f"ESS/s {r['ess_per_s']:.4g}, acceptance {r['acceptance']:.3f}"
+            + (f", stage-1 pass {r['stage1_pass_rate']:.3f}" if use_da else ""))
+        s.close()
+        del Xtr, ltr, trace
+    out["ess_per_s_gain"] = out["delayed_acceptance"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    return out
+
+
 def cpu_baseline(tgt, args):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: a few steps of all P chains, one merge of those steps and one
@@ -166,6 +264,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-part (logistic) experiment")
+    ap.add_argument("--learned-only", action="store_true", help="run only the learned-part experiment")
+    ap.add_argument("--learned-P", dest="learned_P", type=int, default=128)
+    ap.add_argument("--learned-beta", dest="learned_beta", type=float, default=0.5)
+    ap.add_argument("--learned-windows", dest="learned_windows", type=int, default=4)
+    ap.add_argument("--learned-precision", dest="learned_precision", default="fp32", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--train-steps", dest="train_steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -174,6 +279,10 @@ def main():
     import torch
     from paper_1506_05741_amd import diam, synth
     diam.load()
+
+    if args.learned_only:
+        print(json.dumps({"learned": learned_experiment(args, torch, diam)}), flush=True)
+        return
 
     # -- synthetic workload (host), seeded as the d = 4096 configuration ------
     t0 = time.perf_counter()
@@ -235,6 +344,8 @@ def main():
                        "stage_ms_per_window": {k: v[0] / args.steps for k, v in ref["profile"].items()}}
         out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],
                                   "ess": res["ess_per_s"] / ref["ess_per_s"]}
+    if not args.no_learned:
+        out["learned"] = learned_experiment(args, torch, diam)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(tgt, args)

@@ -66,7 +66,7 @@ typedef enum {
 
 typedef enum { DIAM_FP64 = 0, DIAM_FP32 = 1, DIAM_MIXED = 2 } diam_precision;
 
-typedef enum { DIAM_TGT_GAUSS = 0 } diam_target_kind;
+typedef enum { DIAM_TGT_GAUSS = 0, DIAM_TGT_LOGREG = 1 } diam_target_kind;
 
 /* Sampler configuration (host struct, copied by diam_init). */
 typedef struct {
@@ -79,7 +79,8 @@ typedef struct {
   uint64_t seed;        /* Philox4x32-10 key for internally drawn W and U */
   double jitter0;       /* Cholesky retry: eps_j = 10^j jitter0 s, s = tr(C)/d (1 if not > 0) */
   int32_t jitter_tries; /* number of retry levels j = 0 .. jitter_tries-1 */
-  int32_t reserved;
+  int32_t surrogate;    /* 1: reserve the learned-part buffers (MLP d-256-256-1, delayed acceptance) */
+  int64_t train_max;    /* most (x, log pi(x)) pairs diam_surrogate_train will be given */
 } diam_config;
 
 /* Target log density (Section 2.1: only the unnormalised density is needed).
@@ -87,12 +88,22 @@ typedef struct {
  * R^T R = Sigma^-1 (any square root of the precision).  R is FP64 for
  * DIAM_FP64 and FP32 otherwise; mu is FP64.  Evaluating it costs one dense
  * d x d by d x P contraction per step, the cost model of the paper's test
- * targets (Section 3.1). */
+ * targets (Section 3.1).
+ * DIAM_TGT_LOGREG: Bayesian logistic regression (eq. bayes with a Bernoulli
+ * likelihood and a N(0, prior_var I) prior):
+ *   log pi(w) = sum_j [ y_j t_j - softplus(t_j) ] - |w|^2 / (2 prior_var),
+ *   t = A w, A n_obs x d row-major FP32, y in {0, 1} FP32.
+ * The contraction runs on FP32 MFMA (the data are FP32) with the per-row
+ * terms summed in FP64; the prior is FP64. */
 typedef struct {
   int32_t kind;
   int32_t reserved;
-  const double* mu;
-  const void* R;
+  const double* mu;     /* Gaussian */
+  const void* R;        /* Gaussian */
+  const float* A;       /* logistic */
+  const float* y;       /* logistic */
+  int64_t n_obs;        /* logistic */
+  double prior_var;     /* logistic */
 } diam_target;
 
 /* Fields readable with diam_get (device-to-device copy, asynchronous). */
@@ -114,7 +125,14 @@ typedef enum {
   DIAM_F_W = 12,      /* d x P n    normals drawn by the last call when W was NULL:
                                     f64 (FP64), f32 (FP32), bf16 hi part (MIXED) */
   DIAM_F_WLO = 13,    /* d x P n    bf16 lo part of those normals (MIXED only) */
-  DIAM_F_U = 14       /* n x P f64  uniforms drawn by the last call when U was NULL */
+  DIAM_F_U = 14,      /* n x P (x2 under delayed acceptance) f64: uniforms drawn by
+                                    the last call when U was NULL */
+  DIAM_F_SURR = 15,   /* P f64      surrogate log density of the current states */
+  DIAM_F_NPASS = 16,  /* P int32    stage-1 survivors since delayed acceptance was enabled */
+  DIAM_F_MLP_PARAMS = 17, /* nparam f32 master weights W1 (256 x d), b1, W2 (256 x 256), b2, W3 (256), b3 */
+  DIAM_F_MLP_GRAD = 18,   /* nparam f32 gradient of the last training step */
+  DIAM_F_MLP_BATCH = 19,  /* batch int32 training-pair indices of the last training step */
+  DIAM_F_MLP_STATS = 20   /* 2d + 2 f32: input mean, input 1/std, output mean, output std */
 } diam_field;
 
 typedef struct {
@@ -127,8 +145,9 @@ typedef struct {
 } diam_stats;
 
 /* Bytes of workspace diam_init needs for cfg (host).  Returns DIAM_E_ARG on a
- * bad configuration. */
-int diam_workspace_bytes(const diam_config* cfg, size_t* bytes);
+ * bad configuration or target (the logistic target sizes its partial sums
+ * by n_obs). */
+int diam_workspace_bytes(const diam_config* cfg, const diam_target* tgt, size_t* bytes);
 
 /* Create a sampler.  x0: d x P initial states (copied).  Initial proposal:
  * A = I, x_ref = 0 (Algorithm 1 initialisation, x_ref zero until the first
@@ -144,7 +163,8 @@ int diam_init(diam_ctx** out, const diam_config* cfg, const diam_target* tgt, vo
  *    column-major block), or NULL to draw them with Philox4x32-10 from the
  *    configured seed.  In FP32/MIXED they are rounded to FP32 (MIXED: split
  *    into bf16 hi + lo) and the acceptance uses the rounded values.
- * U: P x n_steps f64 uniforms in (0, 1) (step-major), or NULL for Philox.
+ * U: P x n_steps f64 uniforms in (0, 1) (step-major; 2P per step under
+ *    delayed acceptance), or NULL for Philox.
  *    Accept iff log u < log alpha; a NaN log alpha rejects (Section 2.2).
  * n_accepted: P int32 counters incremented per accepted proposal, or NULL.
  * The batch of search directions beta alpha A W for the n_steps steps is
@@ -178,6 +198,32 @@ int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double 
  * recording stops when full.  trace == NULL disables. */
 int diam_set_trace(diam_ctx* ctx, const double* proj, int32_t n_proj, double* trace, int64_t capacity);
 
+/* ---- learned-part form (requires cfg.surrogate = 1) ----------------------
+ * Surrogate of log pi: s(x) = sd * (W3 h2 + b3) + mean, h2 = gelu(W2 h1 + b2),
+ * h1 = gelu(W1 xs + b1), xs = (x - in_mean) / in_std, exact GELU a Phi(a);
+ * hidden widths 256 and 256.  The forward pass uses the bf16 roundings of FP32
+ * master weights with FP32 MFMA accumulation; training (FP32 MFMA forward and
+ * backward, Adam) runs on the GPU.
+ *
+ * Train on n pairs (X: d x n f64, lp: n f64, n <= cfg.train_max): input and
+ * output standardisation from the pairs, He-normal initialisation from seed,
+ * then `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on
+ * minibatches of `batch` pairs drawn with replacement by Philox; mean squared
+ * error on the standardised log density.  loss (host, may be NULL): the mean
+ * loss of the last 50 steps.  Synchronises the stream. */
+int diam_surrogate_train(diam_ctx* ctx, const double* X, const double* lp, int64_t n, int32_t steps, int32_t batch,
+                         double lr, uint64_t seed, double* loss);
+/* Surrogate log density of n states (X: d x n f64, n <= max(P, 512)) into out (n f64). */
+int diam_surrogate_eval(diam_ctx* ctx, const double* X, int32_t n, double* out);
+/* Two-stage delayed acceptance (Christen & Fox 2005) in later steps when
+ * on != 0: stage 1 accepts with log u1 < s(x') - s(x) + (|z'|^2 - |z|^2)/(2 alpha^2);
+ * only stage-1 survivors are evaluated exactly (packed, so the target
+ * contraction shrinks with them) and accepted with
+ * log u2 < (log pi(x') - log pi(x)) - (s(x') - s(x)), so pi stays invariant.
+ * The surrogate must stay fixed while it is on.  U per step then holds two
+ * rows of P uniforms (stage 1, stage 2). */
+int diam_set_delayed_acceptance(diam_ctx* ctx, int32_t on);
+
 /* Bytes of a field (host). */
 int diam_field_bytes(diam_ctx* ctx, int32_t field, size_t* bytes);
 /* Copy a field into dst (device); bytes must equal diam_field_bytes. */
@@ -196,7 +242,9 @@ enum {
   DIAM_ST_MERGE = 4,    /* window transpose, scatter (SYRK), row sums, fold */
   DIAM_ST_CHOL = 5,     /* covariance assembly + blocked Cholesky (every try) */
   DIAM_ST_WHITEN = 6,   /* factor rounding, pivot copy, z = A^-1 (x - x_ref) */
-  DIAM_NSTAGES = 7
+  DIAM_ST_SURROGATE = 7, /* surrogate forward pass + stage-1 screen and survivor packing (per step) */
+  DIAM_ST_TRAIN = 8,    /* surrogate standardisation, initialisation and Adam steps */
+  DIAM_NSTAGES = 9
 };
 /* Enable (on != 0) or disable event timing.  Enabling creates the events. */
 int diam_profile_enable(diam_ctx* ctx, int32_t on);

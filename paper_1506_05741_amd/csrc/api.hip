@@ -38,18 +38,31 @@ struct Status {  // device-side status words, read back by update_proposal
 };
 
 struct Layout {
-  size_t X, Z, V, lp, zq, lpp_part, zq_part, nacc, la, acc, U, W, Wlo, Xi, win, wint, xr, S, m, L, Lnew, Llow, h,
-      syrk, status, proj_part, linv, total;
+  size_t X, Z, V, lp, zq, lpp_part, zq_part, pq_part, nacc, la, acc, U, W, Wlo, Xi, win, wint, xr, S, m, L, Lnew, Llow,
+      h, syrk, status, proj_part, linv;
+  // learned-part form
+  size_t mlp_master, mlp_eff, mlp_grad, mlp_m, mlp_in_mean, mlp_in_scale, mlp_stats, mlp_Xs, mlp_ts, mlp_xb, mlp_tb,
+      mlp_a1, mlp_h1, mlp_a2, mlp_h2, mlp_ga1, mlp_ga2, mlp_out, mlp_gout, mlp_loss, mlp_bidx, s_cur, s_new, pass1,
+      slot, idx, nsurv, npass, Vs;
+  size_t total;
 };
+
+constexpr int MLP_H = 256;      // hidden widths of the surrogate
+constexpr int MLP_NMIN = 512;   // activation buffers hold max(P, MLP_NMIN) samples
+constexpr int LOSS_HIST = 64;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int elem_bytes_ctr(int prec) { return prec == DIAM_FP64 ? 8 : 4; }
 
-Layout make_layout(const diam_config& c) {
+int target_row_blocks(const diam_config& c, const diam_target& t) {
+  return t.kind == DIAM_TGT_LOGREG ? dk::logreg_row_blocks(t.n_obs) : dk::tgt_row_blocks(c.d);
+}
+
+Layout make_layout(const diam_config& c, const diam_target& tg) {
   const size_t d = c.d, P = c.P, nl = c.n_lag;
   const size_t dP = d * P, dd = d * d, win = d * P * nl;
-  const int nrb = dk::tgt_row_blocks(c.d), nch = dk::step_chunks(c.d);
+  const int nrb = target_row_blocks(c, tg), nch = dk::step_chunks(c.d);
   const int eb = elem_bytes_ctr(c.precision);
   Layout L{};
   size_t o = 0;
@@ -65,6 +78,7 @@ Layout make_layout(const diam_config& c) {
   L.zq = take(2 * P * 8);
   L.lpp_part = take((size_t)nrb * P * 8);
   L.zq_part = take(2 * (size_t)nch * P * 8);
+  L.pq_part = take(2 * (size_t)nch * P * 8);
   L.nacc = take(P * 4);
   L.la = take(nl * P * 8);
   L.acc = take(nl * P);
@@ -85,6 +99,40 @@ Layout make_layout(const diam_config& c) {
   L.status = take(sizeof(Status));
   L.proj_part = take(nl * (size_t)nch * 4 * P * 8);
   L.linv = take(dk::chol_scratch_bytes(c.d));
+  if (c.surrogate) {
+    const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
+    const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
+    L.mlp_master = take(np * 4);
+    L.mlp_eff = take(np * 4);
+    L.mlp_grad = take(np * 4);
+    L.mlp_m = take(2 * np * 4);
+    // input mean, input 1/std, output mean and std in one block (one field)
+    L.mlp_in_mean = take((2 * d + 2) * 4);
+    L.mlp_in_scale = L.mlp_in_mean + d * 4;
+    L.mlp_stats = L.mlp_in_mean + 2 * d * 4;
+    L.mlp_Xs = take(d * nt * 4);
+    L.mlp_ts = take(nt * 4);
+    L.mlp_xb = take(d * nmax * 4);
+    L.mlp_tb = take(nmax * 4);
+    L.mlp_a1 = take(H * nmax * 4);
+    L.mlp_h1 = take(H * nmax * 4);
+    L.mlp_a2 = take(H * nmax * 4);
+    L.mlp_h2 = take(H * nmax * 4);
+    L.mlp_ga1 = take(H * nmax * 4);
+    L.mlp_ga2 = take(H * nmax * 4);
+    L.mlp_out = take(nmax * 4);
+    L.mlp_gout = take(nmax * 4);
+    L.mlp_loss = take(LOSS_HIST * 4);
+    L.mlp_bidx = take(nmax * 4);
+    L.s_cur = take(2 * P * 8);
+    L.s_new = take(P * 8);
+    L.pass1 = take(P);
+    L.slot = take(P * 4);
+    L.idx = take(P * 4);
+    L.nsurv = take(4);
+    L.npass = take(P * 4);
+    L.Vs = take(dP * 4);
+  }
   L.total = o;
   return L;
 }
@@ -99,7 +147,18 @@ struct diam_ctx {
   char* ws;
   Layout lay;
   // device pointers
-  double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part, *linv;
+  double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *pq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part, *linv;
+  // target
+  int logreg;
+  double prior_w;
+  // learned-part form
+  dk::MlpBufs mlp;
+  double *s_cur, *s_new;
+  uint8_t* pass1;
+  int *slot, *idx, *nsurv, *npass;
+  float* Vs;
+  int trained, da_on;
+  int32_t last_batch;
   void *V, *W, *Wlo, *Xi, *win, *wint, *Llow, *syrk;
   int32_t* nacc;
   uint8_t* acc;
@@ -113,6 +172,7 @@ struct diam_ctx {
   double N;
   int64_t windows;
   int64_t last_call_steps;
+  int last_call_stages;
   int last_call_caller_w;   // last call's Xi is at Xi offset 0
   // event timing
   bool prof_on;
@@ -139,14 +199,31 @@ static int check_cfg(const diam_config* c) {
   // 32-bit tile indices: the window holds P * n_lag columns of d rows
   if ((long)c->P * c->n_lag > (1L << 30) || c->d > (1 << 20)) return fail(DIAM_E_ARG, "problem too large");
   if ((long)c->d * c->d > (1L << 34)) return fail(DIAM_E_ARG, "d too large");
+  if (c->surrogate != 0 && c->surrogate != 1) return fail(DIAM_E_ARG, "surrogate must be 0 or 1");
+  if (c->train_max < 0 || c->train_max > (1L << 31)) return fail(DIAM_E_ARG, "train_max out of range");
   return DIAM_OK;
 }
 
-extern "C" int diam_workspace_bytes(const diam_config* cfg, size_t* bytes) {
+static int check_target(const diam_config* c, const diam_target* t) {
+  if (!t) return fail(DIAM_E_ARG, "null target");
+  if (t->kind == DIAM_TGT_GAUSS) {
+    if (!t->mu || !t->R) return fail(DIAM_E_ARG, "Gaussian target needs mu and R");
+  } else if (t->kind == DIAM_TGT_LOGREG) {
+    if (!t->A || !t->y || t->n_obs < 1 || t->n_obs > (1L << 30)) return fail(DIAM_E_ARG, "logistic target needs A, y, n_obs >= 1");
+    if (!(t->prior_var > 0.0)) return fail(DIAM_E_ARG, "prior_var must be > 0");
+  } else {
+    return fail(DIAM_E_ARG, "unknown target kind %d", t->kind);
+  }
+  return DIAM_OK;
+}
+
+extern "C" int diam_workspace_bytes(const diam_config* cfg, const diam_target* tgt, size_t* bytes) {
   int r = check_cfg(cfg);
   if (r) return r;
+  r = check_target(cfg, tgt);
+  if (r) return r;
   if (!bytes) return fail(DIAM_E_ARG, "null bytes");
-  *bytes = make_layout(*cfg).total;
+  *bytes = make_layout(*cfg, *tgt).total;
   return DIAM_OK;
 }
 
@@ -213,7 +290,7 @@ static void prof_release(diam_ctx* c) {
 extern "C" int diam_profile_enable(diam_ctx* c, int32_t on) {
   if (!c) return fail(DIAM_E_ARG, "null context");
   if (on && !c->prof_on) {
-    const int n = 2 * (c->cfg.n_lag * 2 + 64);
+    const int n = 2 * (c->cfg.n_lag * 3 + 64);
     c->ev.resize(n);
     c->ev_tag.assign(n, 0);
     for (int i = 0; i < n; ++i) {
@@ -256,10 +333,11 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   *out = nullptr;
   int r = check_cfg(cfg);
   if (r) return r;
-  if (!tgt || tgt->kind != DIAM_TGT_GAUSS || !tgt->mu || !tgt->R) return fail(DIAM_E_ARG, "bad target");
+  r = check_target(cfg, tgt);
+  if (r) return r;
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(DIAM_E_ARG, "workspace null or not 256-byte aligned");
   if (!x0) return fail(DIAM_E_ARG, "null x0");
-  Layout lay = make_layout(*cfg);
+  Layout lay = make_layout(*cfg, *tgt);
   if (ws_bytes < lay.total) return fail(DIAM_E_ARG, "workspace too small: %zu < %zu", ws_bytes, lay.total);
   diam_ctx* c = new (std::nothrow) diam_ctx();
   if (!c) return fail(DIAM_E_ARG, "host allocation failed");
@@ -276,6 +354,54 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->zq = dptr(c, lay.zq);
   c->lpp_part = dptr(c, lay.lpp_part);
   c->zq_part = dptr(c, lay.zq_part);
+  c->pq_part = dptr(c, lay.pq_part);
+  c->logreg = tgt->kind == DIAM_TGT_LOGREG;
+  c->prior_w = c->logreg ? 1.0 / (2.0 * tgt->prior_var) : 0.0;
+  c->trained = 0;
+  c->da_on = 0;
+  c->last_batch = 0;
+  if (cfg->surrogate) {
+    dk::MlpBufs& b = c->mlp;
+    b.D = cfg->d;
+    b.H = MLP_H;
+    b.d_state = cfg->d;
+    auto fp = [&](size_t off) { return (float*)(c->ws + off); };
+    b.master = fp(lay.mlp_master);
+    b.eff = fp(lay.mlp_eff);
+    b.grad = fp(lay.mlp_grad);
+    b.m = fp(lay.mlp_m);
+    b.in_mean = fp(lay.mlp_in_mean);
+    b.in_scale = fp(lay.mlp_in_scale);
+    b.stats = fp(lay.mlp_stats);
+    b.Xs = fp(lay.mlp_Xs);
+    b.ts = fp(lay.mlp_ts);
+    b.xb = fp(lay.mlp_xb);
+    b.tb = fp(lay.mlp_tb);
+    b.a1 = fp(lay.mlp_a1);
+    b.h1 = fp(lay.mlp_h1);
+    b.a2 = fp(lay.mlp_a2);
+    b.h2 = fp(lay.mlp_h2);
+    b.ga1 = fp(lay.mlp_ga1);
+    b.ga2 = fp(lay.mlp_ga2);
+    b.out = fp(lay.mlp_out);
+    b.gout = fp(lay.mlp_gout);
+    b.loss = fp(lay.mlp_loss);
+    b.bidx = (int*)(c->ws + lay.mlp_bidx);
+    c->s_cur = dptr(c, lay.s_cur);
+    c->s_new = dptr(c, lay.s_new);
+    c->pass1 = (uint8_t*)(c->ws + lay.pass1);
+    c->slot = (int*)(c->ws + lay.slot);
+    c->idx = (int*)(c->ws + lay.idx);
+    c->nsurv = (int*)(c->ws + lay.nsurv);
+    c->npass = (int*)(c->ws + lay.npass);
+    c->Vs = fp(lay.Vs);
+  } else {
+    c->mlp = dk::MlpBufs{};
+    c->s_cur = c->s_new = nullptr;
+    c->pass1 = nullptr;
+    c->slot = c->idx = c->nsurv = c->npass = nullptr;
+    c->Vs = nullptr;
+  }
   c->nacc = (int32_t*)(c->ws + lay.nacc);
   c->la = dptr(c, lay.la);
   c->acc = (uint8_t*)(c->ws + lay.acc);
@@ -296,7 +422,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->status = (Status*)(c->ws + lay.status);
   c->proj_part = dptr(c, lay.proj_part);
   c->linv = dptr(c, lay.linv);
-  c->nrb = dk::tgt_row_blocks(cfg->d);
+  c->nrb = target_row_blocks(*cfg, *tgt);
   c->nch = dk::step_chunks(cfg->d);
   c->cur = 0;
   c->steps = 0;
@@ -305,6 +431,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->N = 0.0;
   c->windows = 0;
   c->last_call_steps = 0;
+  c->last_call_stages = 1;
   c->proj = nullptr;
   c->nproj = 0;
   c->trace = nullptr;
@@ -338,9 +465,15 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   HIPCHK_INIT(hipGetLastError());
   HIPCHK_INIT(dk::round_factor(c->prec, c->L, c->Llow, d, s));
   // log pi(x0) and z0 = x0 (A = I, x_ref = 0)
-  HIPCHK_INIT(dk::init_eval(c->prec, c->X, tgt->mu, c->V, c->Z, d, P, s));
-  HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s));
-  HIPCHK_INIT(dk::init_finish(c->lpp_part, c->nrb, c->Z, c->lp, c->zq, d, P, s));
+  if (c->logreg) {
+    HIPCHK_INIT(dk::init_eval(0, c->X, nullptr, c->V, c->Z, d, P, s));
+    HIPCHK_INIT(dk::tgt_logreg(tgt->A, tgt->y, tgt->n_obs, (const float*)c->V, d, P, nullptr, c->lpp_part, s));
+  } else {
+    HIPCHK_INIT(dk::init_eval(c->prec == dk::P64, c->X, tgt->mu, c->V, c->Z, d, P, s));
+    HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s));
+  }
+  HIPCHK_INIT(dk::init_finish(c->lpp_part, c->nrb, c->Z, c->X, c->prior_w, c->lp, c->zq, d, P, s));
+  if (cfg->surrogate) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->npass, (long)P);
 #undef HIPCHK_INIT
   *out = c;
   return DIAM_OK;
@@ -369,9 +502,10 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   } else {
     HIPCHK(dk::normals(prec, c->cfg.seed, c->steps, n, d, P, c->W, c->Wlo, s));
   }
+  const int stages = c->da_on ? 2 : 1;
   const double* Up = U;
   if (!Up) {
-    HIPCHK(dk::uniforms(c->cfg.seed, c->steps, n, P, 1, c->U, s));
+    HIPCHK(dk::uniforms(c->cfg.seed, c->steps, n, P, stages, c->U, s));
     Up = c->U;
   }
   prof_end(c, ps);
@@ -395,7 +529,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.c = cc;
   a.inv2a2 = 1.0 / (2.0 * alpha * alpha);
   a.xr = c->xr;
-  a.mu = c->tgt.mu;
+  a.mu = c->logreg ? nullptr : c->tgt.mu;
   a.X = c->X;
   a.Z = c->Z;
   a.V = c->V;
@@ -403,6 +537,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.nacc = n_accepted ? n_accepted : c->nacc;
   a.win = c->win;
   a.err = &c->status->err;
+  a.v32 = c->logreg;
+  a.prior_w = c->prior_w;
   a.proj = c->proj;
   a.nproj = tracing ? c->nproj : 0;
   // proposal of the first step
@@ -412,14 +548,29 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.w_nxt = Wp;
   a.wlo_nxt = Wlop;
   a.zq_part_nxt = c->zq_part + (long)c->cur * c->nch * P;
+  a.pq_part_nxt = c->pq_part + (long)c->cur * c->nch * P;
   ps = prof_begin(c, DIAM_ST_STEP);
   HIPCHK(dk::step(a, s));
   prof_end(c, ps);
   for (int t = 0; t < n; ++t) {
-    ps = prof_begin(c, DIAM_ST_TARGET);
-    HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s));
-    prof_end(c, ps);
     const int cu = c->cur, nx = cu ^ 1;
+    const double* u_t = Up + (long)t * stages * P;
+    if (c->da_on) {
+      // stage 1 on the surrogate, then the exact target on the survivors only
+      ps = prof_begin(c, DIAM_ST_SURROGATE);
+      HIPCHK(dk::mlp_eval(c->mlp, nullptr, (const float*)c->V, P, c->s_new, s));
+      HIPCHK(dk::da_stage1(P, c->nch, c->s_new, c->s_cur + (long)cu * P, c->zq_part + (long)cu * c->nch * P,
+                           c->zq + (long)cu * P, u_t, a.inv2a2, c->pass1, c->slot, c->idx, c->nsurv, c->npass,
+                           (const float*)c->V, d, c->Vs, s));
+      prof_end(c, ps);
+    }
+    ps = prof_begin(c, DIAM_ST_TARGET);
+    if (c->logreg)
+      HIPCHK(dk::tgt_logreg(c->tgt.A, c->tgt.y, c->tgt.n_obs, c->da_on ? c->Vs : (const float*)c->V, d, P,
+                            c->da_on ? c->nsurv : nullptr, c->lpp_part, s));
+    else
+      HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s));
+    prof_end(c, ps);
     a.do_accept = 1;
     a.xi_cur = at(c->Xi, (long)t * dP, eb);
     a.w_cur = at(Wp, (long)t * dP, wb);
@@ -430,7 +581,19 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     a.zq_cur = c->zq + (long)cu * P;
     a.lp_nxt = c->lp + (long)nx * P;
     a.zq_nxt = c->zq + (long)nx * P;
-    a.u = Up + (long)t * P;
+    a.u = u_t;
+    a.pq_part_cur = c->pq_part + (long)cu * c->nch * P;
+    a.pq_part_nxt = c->pq_part + (long)nx * c->nch * P;
+    a.da = c->da_on;
+    if (c->da_on) {
+      a.pass1 = c->pass1;
+      // target partials of survivors are packed by stage-1 slot
+      a.slot = c->slot;
+      a.s_new = c->s_new;
+      a.s_in = c->s_cur + (long)cu * P;
+      a.s_out = c->s_cur + (long)nx * P;
+      a.u2 = u_t + P;
+    }
     a.la_out = c->la + (long)t * P;
     a.acc_out = c->acc + (long)t * P;
     a.win_col0 = (long)(c->siw + t) * P;
@@ -452,6 +615,79 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   c->siw += n;
   c->steps += n;
   c->last_call_steps = n;
+  c->last_call_stages = stages;
+  return DIAM_OK;
+}
+
+// ---- learned-part form -------------------------------------------------------
+static int need_surrogate(diam_ctx* c) {
+  if (!c) return fail(DIAM_E_ARG, "null context");
+  if (!c->cfg.surrogate) return fail(DIAM_E_STATE, "the context was created without surrogate buffers");
+  return DIAM_OK;
+}
+
+extern "C" int diam_surrogate_train(diam_ctx* c, const double* X, const double* lp, int64_t n, int32_t steps,
+                                    int32_t batch, double lr, uint64_t seed, double* loss) {
+  int r = need_surrogate(c);
+  if (r) return r;
+  if (c->da_on) return fail(DIAM_E_STATE, "surrogate must stay fixed while delayed acceptance is on");
+  if (!X || !lp) return fail(DIAM_E_ARG, "null training data");
+  if (n < 2 || n > c->cfg.train_max) return fail(DIAM_E_ARG, "n = %ld outside [2, train_max = %ld]", (long)n,
+                                                 (long)c->cfg.train_max);
+  const int nmax = c->cfg.P > MLP_NMIN ? c->cfg.P : MLP_NMIN;
+  if (steps < 0 || batch < 1 || batch > nmax) return fail(DIAM_E_ARG, "steps >= 0, 1 <= batch <= %d", nmax);
+  if (!(lr > 0.0)) return fail(DIAM_E_ARG, "lr must be > 0");
+  hipStream_t s = c->stream;
+  const int ps = prof_begin(c, DIAM_ST_TRAIN);
+  HIPCHK(dk::mlp_prepare(c->mlp, X, lp, n, seed, s));
+  dk::MlpBufs b = c->mlp;
+  for (int t = 0; t < steps; ++t) {
+    b.loss = c->mlp.loss + (t % LOSS_HIST);
+    HIPCHK(dk::mlp_train_step(b, n, batch, t, seed, (float)lr, s));
+  }
+  prof_end(c, ps);
+  c->trained = 1;
+  c->last_batch = batch;
+  if (loss) {
+    float h[LOSS_HIST];
+    HIPCHK(hipMemcpyAsync(h, c->mlp.loss, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int k = steps < 50 ? steps : 50;
+    double acc = 0.0;
+    for (int t = steps - k; t < steps; ++t) acc += h[t % LOSS_HIST];
+    *loss = k ? acc / k : NAN;
+  } else {
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return DIAM_OK;
+}
+
+extern "C" int diam_surrogate_eval(diam_ctx* c, const double* X, int32_t n, double* out) {
+  int r = need_surrogate(c);
+  if (r) return r;
+  if (!c->trained) return fail(DIAM_E_STATE, "surrogate not trained");
+  const int nmax = c->cfg.P > MLP_NMIN ? c->cfg.P : MLP_NMIN;
+  if (!X || !out || n < 0 || n > nmax) return fail(DIAM_E_ARG, "need X, out and 0 <= n <= %d", nmax);
+  if (n == 0) return DIAM_OK;
+  HIPCHK(dk::mlp_eval(c->mlp, X, nullptr, n, out, c->stream));
+  return DIAM_OK;
+}
+
+extern "C" int diam_set_delayed_acceptance(diam_ctx* c, int32_t on) {
+  int r = need_surrogate(c);
+  if (r) return r;
+  if (!on) {
+    c->da_on = 0;
+    return DIAM_OK;
+  }
+  if (!c->logreg) return fail(DIAM_E_STATE, "delayed acceptance needs the logistic target");
+  if (!c->trained) return fail(DIAM_E_STATE, "surrogate not trained");
+  if (c->da_on) return DIAM_OK;
+  // surrogate at the current states; survivor counters restart
+  HIPCHK(dk::mlp_eval(c->mlp, c->X, nullptr, c->cfg.P, c->s_cur + (long)c->cur * c->cfg.P, c->stream));
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(c->cfg.P)), dim3(256), 0, c->stream, c->npass, (long)c->cfg.P);
+  HIPCHK(hipGetLastError());
+  c->da_on = 1;
   return DIAM_OK;
 }
 
@@ -580,7 +816,32 @@ static int field_info(diam_ctx* c, int32_t f, const void** src, size_t* bytes) {
     case DIAM_F_WLO:
       if (c->prec != dk::PMIX) return fail(DIAM_E_ARG, "DIAM_F_WLO exists only in DIAM_MIXED");
       *src = c->Wlo; *bytes = d * P * n * 2; break;
-    case DIAM_F_U: *src = c->U; *bytes = n * P * 8; break;
+    case DIAM_F_U: *src = c->U; *bytes = n * P * 8 * c->last_call_stages; break;
+    case DIAM_F_SURR:
+    case DIAM_F_NPASS:
+    case DIAM_F_MLP_PARAMS:
+    case DIAM_F_MLP_GRAD:
+    case DIAM_F_MLP_BATCH:
+    case DIAM_F_MLP_STATS: {
+      if (!c->cfg.surrogate) return fail(DIAM_E_ARG, "field %d needs surrogate buffers", f);
+      const size_t np = dk::mlp_nparam(c->cfg.d, MLP_H);
+      if (f == DIAM_F_SURR) {
+        if (!c->da_on) return fail(DIAM_E_STATE, "DIAM_F_SURR is kept only under delayed acceptance");
+        *src = c->s_cur + (long)c->cur * P;
+        *bytes = P * 8;
+      } else if (f == DIAM_F_NPASS) {
+        *src = c->npass; *bytes = P * 4;
+      } else if (f == DIAM_F_MLP_PARAMS) {
+        *src = c->mlp.master; *bytes = np * 4;
+      } else if (f == DIAM_F_MLP_GRAD) {
+        *src = c->mlp.grad; *bytes = np * 4;
+      } else if (f == DIAM_F_MLP_BATCH) {
+        *src = c->mlp.bidx; *bytes = (size_t)c->last_batch * 4;
+      } else {
+        *src = c->mlp.in_mean; *bytes = (2 * d + 2) * 4;
+      }
+      break;
+    }
     default: return fail(DIAM_E_ARG, "unknown field %d", f);
   }
   return DIAM_OK;

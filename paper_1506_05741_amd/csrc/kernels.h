@@ -17,8 +17,38 @@ constexpr int CHOL_NB = 64;
 inline int tgt_row_blocks(int d) { return (d + TGT_BM - 1) / TGT_BM; }
 inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 
-// Gaussian target: part[rb][p] = sum over rows of block rb of (R (x_p - mu))_i^2.
+// Target contractions write per-row-block partial sums of log-density
+// contributions: log pi(x_p) = sum_rb part[rb][p] (+ the prior, for the
+// logistic target, added by the step kernel).
+// Gaussian: part[rb][p] = -1/2 sum over rows of block rb of (R (x_p - mu))_i^2.
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
+// Logistic: part[rb][p] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
+// (A n_obs x d row-major FP32, V d x P FP32); columns >= *nact skipped.
+int logreg_row_blocks(long n_obs);
+hipError_t tgt_logreg(const float* A, const float* y, long n_obs, const float* V, int d, int P, const int* nact,
+                      double* part, hipStream_t s);
+
+// Buffers of the MLP surrogate (all device, FP32 unless noted).
+struct MlpBufs {
+  int D, H, d_state;
+  float *master, *eff, *grad, *m;        // nparam each (m holds Adam m then v: 2 nparam)
+  float *in_mean, *in_scale, *stats;      // D, D, 2 (out mean, out std)
+  float *Xs, *ts;                         // standardised training pairs (D x ntrain, ntrain)
+  float *xb, *tb;                         // minibatch / evaluation input (D x nmax, nmax)
+  float *a1, *h1, *a2, *h2, *ga1, *ga2;   // H x nmax
+  float *out, *gout, *loss;               // nmax, nmax, 1
+  int* bidx;                              // nmax (minibatch indices)
+};
+size_t mlp_nparam(int D, int H);
+hipError_t mlp_prepare(const MlpBufs& b, const double* X, const double* lp, long n, uint64_t seed, hipStream_t s);
+hipError_t mlp_train_step(const MlpBufs& b, long n, int nb, long tau, uint64_t seed, float lr, hipStream_t s);
+hipError_t mlp_forward(const MlpBufs& b, const float* xs, int n, hipStream_t s);
+// s_out[j] = surrogate log density of column j of X64 (FP64) or X32 (FP32), d x n
+hipError_t mlp_eval(const MlpBufs& b, const double* X64, const float* X32, int n, double* s_out, hipStream_t s);
+// Delayed acceptance stage 1 and survivor packing.
+hipError_t da_stage1(int P, int nch, const double* s_new, const double* s_cur, const double* zq_part, const double* zq,
+                     const double* u1, double inv2a2, uint8_t* pass, int* slot, int* idx, int* nsurv, int* npass,
+                     const float* V, int d, float* Vs, hipStream_t s);
 
 // Xi = c L W over ncols columns; L lower (d x d): f64/f32 column-major,
 // bf16 as hi then lo row-major copies; W: f64/f32 column-major, bf16 as hi
@@ -86,14 +116,26 @@ struct StepArgs {
   const void* xi_nxt;
   const void* w_nxt; const void* wlo_nxt;
   double* zq_part_nxt;                    // nch x P
+  // target variants
+  int v32;                                // write V as FP32 whatever the precision
+  double prior_w;                         // > 0: add -prior_w |x|^2 to log pi (pq partials)
+  const double* pq_part_cur;              // nch x P
+  double* pq_part_nxt;                    // nch x P
+  // delayed acceptance (second stage on stage-1 survivors)
+  int da;
+  const uint8_t* pass1;                   // P
+  const int* slot;                        // P: survivor slot (column of lpp_part) or -1
+  const double* s_new;                    // P: surrogate at the proposals
+  const double* s_in; double* s_out;      // P: surrogate at the current states
+  const double* u2;                       // P
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
 
-// V = X - mu (working precision), Z = X, for the initial evaluation.
-hipError_t init_eval(int prec, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);
-// lp[p] = -1/2 sum_rb part[rb][p]; zq[p] = ||Z_p||^2.
-hipError_t init_finish(const double* part, int nrb, const double* Z, double* lp, double* zq, int d, int P,
-                       hipStream_t s);
+// V = X - mu (mu may be null; FP64 or FP32 V), Z = X, for the initial evaluation.
+hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);
+// lp[p] = sum_rb part[rb][p] - prior_w |x_p|^2; zq[p] = ||Z_p||^2.
+hipError_t init_finish(const double* part, int nrb, const double* Z, const double* X, double prior_w, double* lp,
+                       double* zq, int d, int P, hipStream_t s);
 // trace[t][1 + k][p] = sum_ch proj_part[t][ch][k][p]
 hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P, double* trace, int nfun,
                        hipStream_t s);

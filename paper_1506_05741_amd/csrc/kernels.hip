@@ -48,7 +48,7 @@ __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, cons
   __syncthreads();
   if (threadIdx.x < BN) {
     const int j = j0 + threadIdx.x;
-    if (j < P) part[(long)blockIdx.x * P + j] = red[0][threadIdx.x] + red[1][threadIdx.x];
+    if (j < P) part[(long)blockIdx.x * P + j] = -0.5 * (red[0][threadIdx.x] + red[1][threadIdx.x]);
   }
 }
 
@@ -893,33 +893,52 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
       if (a.do_propose) {
         xn[q] = (double)xi_nxt[e];
         wn[q] = load_w<PR>(a.w_nxt, a.wlo_nxt, e);
-        mu[q] = a.mu[i];
+        mu[q] = a.mu ? a.mu[i] : 0.0;
       }
     }
   }
   bool acc = false;
   if (a.do_accept) {
+    // exact log density of the proposal: target partials (of this chain, or
+    // of its survivor slot under delayed acceptance) plus the prior
+    const bool live = !a.da || a.pass1[p];
+    const int col = a.da ? a.slot[p] : p;
     double s = 0.0;
-    for (int q = lane; q < a.nrb; q += 64) s += a.lpp_part[(long)q * P + p];
+    if (live)
+      for (int q = lane; q < a.nrb; q += 64) s += a.lpp_part[(long)q * P + col];
     s = wave_sum_f64(s);
-    const double lpp = -0.5 * s;
+    if (a.prior_w > 0.0) {
+      double pq = 0.0;
+      for (int q = lane; q < nch; q += 64) pq += a.pq_part_cur[(long)q * P + p];
+      pq = wave_sum_f64(pq);
+      s = __fma_rn(-a.prior_w, pq, s);
+    }
+    const double lpp = s;
     double zs = 0.0;
     for (int q = lane; q < nch; q += 64) zs += a.zq_part_cur[(long)q * P + p];
     zs = wave_sum_f64(zs);
     const double lp = a.lp_cur[p], zq = a.zq_cur[p];
-    const double la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
-    acc = log(a.u[p]) < la;  // NaN compares false: rejected
+    double la;
+    if (!a.da) {
+      la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
+      acc = log(a.u[p]) < la;  // NaN compares false: rejected
+    } else {
+      // second stage: log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x))
+      la = live ? (lpp - lp) - (a.s_new[p] - a.s_in[p]) : -INFINITY;
+      acc = live && (log(a.u2[p]) < la);
+    }
     if (ch == 0 && lane == 0) {
       a.lp_nxt[p] = acc ? lpp : lp;
       a.zq_nxt[p] = acc ? zs : zq;
       a.nacc[p] += acc ? 1 : 0;
       a.la_out[p] = la;
       a.acc_out[p] = acc ? 1 : 0;
+      if (a.da) a.s_out[p] = acc ? a.s_new[p] : a.s_in[p];
       if (a.trace_lp) a.trace_lp[p] = acc ? lpp : lp;
-      if (isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
+      if (live && isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
     }
   }
-  double zacc = 0.0;
+  double zacc = 0.0, xacc = 0.0;
   double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
@@ -939,14 +958,20 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
     }
     if (a.do_propose) {
       const double xp = propose1(xr[q], xv, a.rho, xn[q]);
-      V[e] = (VT)(xp - mu[q]);
+      if (a.v32) ((float*)a.V)[e] = (float)(xp - mu[q]);
+      else V[e] = (VT)(xp - mu[q]);
       const double zp = __fma_rn(a.c, wn[q], a.rho * zv);
       zacc = __fma_rn(zp, zp, zacc);
+      xacc = __fma_rn(xp, xp, xacc);
     }
   }
   if (a.do_propose) {
     zacc = wave_sum_f64(zacc);
     if (lane == 0) a.zq_part_nxt[(long)ch * P + p] = zacc;
+    if (a.prior_w > 0.0) {
+      xacc = wave_sum_f64(xacc);
+      if (lane == 0) a.pq_part_nxt[(long)ch * P + p] = xacc;
+    }
   }
   if (a.do_accept && a.nproj > 0) {
     for (int k = 0; k < a.nproj; ++k) {
@@ -964,35 +989,52 @@ hipError_t step(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_init_eval(int prec, const double* __restrict__ X, const double* __restrict__ mu,
+__global__ __launch_bounds__(256) void k_init_eval(int v64, const double* __restrict__ X, const double* __restrict__ mu,
                                                    void* __restrict__ V, double* __restrict__ Z, int d, long n) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   const double x = X[e];
-  const double v = x - mu[e % d];
-  if (prec == P64) ((double*)V)[e] = v;
+  const double v = x - (mu ? mu[e % d] : 0.0);
+  if (v64) ((double*)V)[e] = v;
   else ((float*)V)[e] = (float)v;
   Z[e] = x;
 }
 
-hipError_t init_eval(int prec, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s) {
+hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s) {
   const long n = (long)d * P;
-  hipLaunchKernelGGL(k_init_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prec, X, mu, V, Z, d, n);
+  hipLaunchKernelGGL(k_init_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v64, X, mu, V, Z, d, n);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(64) void k_init_finish(const double* __restrict__ part, int nrb, int P,
-                                                    double* __restrict__ lp) {
+// lp[p] = sum_rb part[rb][p] - prior_w |x_p|^2 (one block per chain)
+__global__ __launch_bounds__(256) void k_init_finish(const double* __restrict__ part, int nrb, int P,
+                                                     const double* __restrict__ X, int d, double prior_w,
+                                                     double* __restrict__ lp) {
+  __shared__ double red[2][256];
   const int p = blockIdx.x;
-  double s = 0.0;
-  for (int q = threadIdx.x; q < nrb; q += 64) s += part[(long)q * P + p];
-  s = wave_sum_f64(s);
-  if (threadIdx.x == 0) lp[p] = -0.5 * s;
+  double s = 0.0, q = 0.0;
+  for (int k = threadIdx.x; k < nrb; k += 256) s += part[(long)k * P + p];
+  if (prior_w > 0.0)
+    for (int i = threadIdx.x; i < d; i += 256) {
+      const double x = X[i + (long)p * d];
+      q = __fma_rn(x, x, q);
+    }
+  red[0][threadIdx.x] = s;
+  red[1][threadIdx.x] = q;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lp[p] = (prior_w > 0.0) ? __fma_rn(-prior_w, red[1][0], red[0][0]) : red[0][0];
 }
 
-hipError_t init_finish(const double* part, int nrb, const double* Z, double* lp, double* zq, int d, int P,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_init_finish, dim3(P), dim3(64), 0, s, part, nrb, P, lp);
+hipError_t init_finish(const double* part, int nrb, const double* Z, const double* X, double prior_w, double* lp,
+                       double* zq, int d, int P, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_finish, dim3(P), dim3(256), 0, s, part, nrb, P, X, d, prior_w, lp);
   hipLaunchKernelGGL(k_colnorm, dim3(P), dim3(256), 0, s, Z, d, zq);
   return hipGetLastError();
 }

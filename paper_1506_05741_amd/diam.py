@@ -18,27 +18,34 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 
 OK, E_ARG, E_STATE, E_HIP, E_NOT_PD, E_TARGET = 0, -1, -2, -3, -4, -5
 
-F_X, F_Z, F_LOGP, F_ZQ, F_XREF, F_L, F_S, F_M, F_XI, F_LA, F_ACC, F_NACC, F_W, F_WLO, F_U = range(15)
+(F_X, F_Z, F_LOGP, F_ZQ, F_XREF, F_L, F_S, F_M, F_XI, F_LA, F_ACC, F_NACC, F_W, F_WLO, F_U,
+ F_SURR, F_NPASS, F_MLP_PARAMS, F_MLP_GRAD, F_MLP_BATCH, F_MLP_STATS) = range(21)
+
+TGT_GAUSS, TGT_LOGREG = 0, 1
+MLP_HIDDEN = 256
 
 EXPORTED = (
     "diam_workspace_bytes", "diam_init", "diam_step_batch", "diam_merge_moments", "diam_update_proposal",
     "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
+    "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
 )
-STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten")
+STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten", "surrogate", "train")
 
 
 class Config(ctypes.Structure):
     _fields_ = [
         ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("n_lag", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("jitter0", ctypes.c_double), ("jitter_tries", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("jitter0", ctypes.c_double), ("jitter_tries", ctypes.c_int32), ("surrogate", ctypes.c_int32),
+        ("train_max", ctypes.c_int64),
     ]
 
 
 class Target(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_void_p),
-                ("R", ctypes.c_void_p)]
+                ("R", ctypes.c_void_p), ("A", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_obs", ctypes.c_int64),
+                ("prior_var", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -65,7 +72,7 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     sig = {
-        "diam_workspace_bytes": ([ctypes.POINTER(Config), ctypes.POINTER(sz)], ctypes.c_int),
+        "diam_workspace_bytes": ([ctypes.POINTER(Config), ctypes.POINTER(Target), ctypes.POINTER(sz)], ctypes.c_int),
         "diam_init": ([ctypes.POINTER(vp), ctypes.POINTER(Config), ctypes.POINTER(Target), vp, sz, vp, vp],
                       ctypes.c_int),
         "diam_step_batch": ([vp, i32, vp, vp, vp], ctypes.c_int),
@@ -80,6 +87,10 @@ def load(path: str = LIB_PATH):
         "diam_destroy": ([vp], None),
         "diam_profile_enable": ([vp, i32], ctypes.c_int),
         "diam_profile_read": ([vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32], ctypes.c_int),
+        "diam_surrogate_train": ([vp, vp, vp, i64, i32, i32, dbl, ctypes.c_uint64, ctypes.POINTER(dbl)],
+                                 ctypes.c_int),
+        "diam_surrogate_eval": ([vp, vp, i32, vp], ctypes.c_int),
+        "diam_set_delayed_acceptance": ([vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -99,37 +110,62 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13):
+def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13,
+                surrogate=False, train_max=0):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, 0)
+    return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, 1 if surrogate else 0, int(train_max))
 
 
-def workspace_bytes(cfg: Config) -> int:
+def gauss_target(mu, R):
+    return Target(TGT_GAUSS, 0, _addr(mu), _addr(R), None, None, 0, 0.0)
+
+
+def logreg_target(A, y, prior_var):
+    n_obs = 0 if A is None else A.shape[0]
+    return Target(TGT_LOGREG, 0, None, None, _addr(A), _addr(y), n_obs, float(prior_var))
+
+
+def _addr(t):
+    return None if t is None else t.data_ptr()
+
+
+def workspace_bytes(cfg: Config, tgt: Target) -> int:
     lib = load()
     n = ctypes.c_size_t()
-    _check(lib.diam_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    _check(lib.diam_workspace_bytes(ctypes.byref(cfg), ctypes.byref(tgt), ctypes.byref(n)))
     return n.value
 
 
 class Sampler:
     """P DIAM chains on the GPU.  Tensors passed in must be CUDA tensors of the
-    documented dtype and shape (contiguous); the sampler keeps references."""
+    documented dtype and shape (contiguous); the sampler keeps references.
 
-    def __init__(self, cfg: Config, mu, R, x0, stream=None):
+    Gaussian target: ``Sampler(cfg, mu, R, x0)``.  Logistic regression:
+    ``Sampler(cfg, None, None, x0, A=A, y=y, prior_var=v)`` with A (n_obs, d)
+    and y (n_obs,) FP32."""
+
+    def __init__(self, cfg: Config, mu, R, x0, stream=None, A=None, y=None, prior_var=None):
         import torch
         lib = load()
         self.torch = torch
         self.cfg = cfg
         self.d, self.P = cfg.d, cfg.P
-        rdt = torch.float64 if cfg.precision == FP64 else torch.float32
-        assert mu.dtype == torch.float64 and mu.is_cuda and mu.numel() == cfg.d and mu.is_contiguous()
-        assert R.dtype == rdt and R.is_cuda and R.shape == (cfg.d, cfg.d) and R.is_contiguous()
+        self.da_on = False
         assert x0.dtype == torch.float64 and x0.is_cuda and x0.numel() == cfg.d * cfg.P and x0.is_contiguous()
-        self._keep = [mu, R, x0]
-        nbytes = workspace_bytes(cfg)
+        if A is None:
+            rdt = torch.float64 if cfg.precision == FP64 else torch.float32
+            assert mu.dtype == torch.float64 and mu.is_cuda and mu.numel() == cfg.d and mu.is_contiguous()
+            assert R.dtype == rdt and R.is_cuda and R.shape == (cfg.d, cfg.d) and R.is_contiguous()
+            self._keep = [mu, R, x0]
+            self.tgt = gauss_target(mu, R)
+        else:
+            assert A.dtype == torch.float32 and A.is_cuda and A.dim() == 2 and A.shape[1] == cfg.d
+            assert A.is_contiguous() and y.dtype == torch.float32 and y.is_cuda and y.numel() == A.shape[0]
+            self._keep = [A, y, x0]
+            self.tgt = logreg_target(A, y, prior_var)
+        nbytes = workspace_bytes(cfg, self.tgt)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=x0.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(x0.device)
-        self.tgt = Target(0, 0, mu.data_ptr(), R.data_ptr())
         ctx = ctypes.c_void_p()
         _check(lib.diam_init(ctypes.byref(ctx), ctypes.byref(cfg), ctypes.byref(self.tgt), _ptr(self.ws),
                              nbytes, _ptr(x0), ctypes.c_void_p(self.stream.cuda_stream)))
@@ -144,7 +180,9 @@ class Sampler:
             assert W.dtype == torch.float64 and W.is_cuda and W.is_contiguous()
             assert W.numel() == self.d * self.P * n_steps
         if U is not None:
-            assert U.dtype == torch.float64 and U.is_cuda and U.is_contiguous() and U.numel() == self.P * n_steps
+            stages = 2 if self.da_on else 1
+            assert U.dtype == torch.float64 and U.is_cuda and U.is_contiguous()
+            assert U.numel() == self.P * n_steps * stages
         if n_accepted is not None:
             assert n_accepted.dtype == torch.int32 and n_accepted.is_cuda and n_accepted.numel() == self.P
         _check(self.lib.diam_step_batch(self.ctx, int(n_steps), _ptr(W), _ptr(U), _ptr(n_accepted)))
@@ -177,6 +215,29 @@ class Sampler:
         cap = 0 if trace is None else trace.shape[0]
         self._trace_keep = (proj, trace)
         _check(self.lib.diam_set_trace(self.ctx, _ptr(proj), nproj, _ptr(trace), cap))
+
+    # -- learned-part form -------------------------------------------------------
+    def surrogate_train(self, X, lp, steps, batch=256, lr=1e-3, seed=0):
+        """Train the MLP surrogate on pairs X (n, d) f64 CUDA, lp (n,) f64 CUDA;
+        returns the mean minibatch loss of the last 50 steps."""
+        torch = self.torch
+        assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.shape[1] == self.d
+        assert lp.dtype == torch.float64 and lp.is_cuda and lp.numel() == X.shape[0]
+        loss = ctypes.c_double()
+        _check(self.lib.diam_surrogate_train(self.ctx, _ptr(X), _ptr(lp), X.shape[0], int(steps), int(batch),
+                                             float(lr), int(seed), ctypes.byref(loss)))
+        return loss.value
+
+    def surrogate_eval(self, X):
+        torch = self.torch
+        assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.shape[1] == self.d
+        out = torch.empty(X.shape[0], dtype=torch.float64, device=X.device)
+        _check(self.lib.diam_surrogate_eval(self.ctx, _ptr(X), X.shape[0], _ptr(out)))
+        return out
+
+    def set_delayed_acceptance(self, on=True):
+        _check(self.lib.diam_set_delayed_acceptance(self.ctx, 1 if on else 0))
+        self.da_on = bool(on)
 
     # -- reading back ------------------------------------------------------------
     def field_bytes(self, field):

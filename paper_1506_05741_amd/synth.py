@@ -118,6 +118,27 @@ def logreg_data(n: int = 200000, d: int = 512, seed: int = 4, prior_var: float =
     return LogRegData(A=A, y=y, w_true=w, prior_var=prior_var)
 
 
+def logreg_laplace(data: LogRegData, iters: int = 8):
+    """Laplace approximation of the logistic posterior (warm start only):
+    the mode by Newton's method from w = 0 and the inverse Hessian there.
+    Returns (mode, covariance)."""
+    A = data.A.astype(np.float64)
+    y = data.y.astype(np.float64)
+    d = A.shape[1]
+    w = np.zeros(d)
+    for _ in range(iters):
+        t = A @ w
+        s = 1.0 / (1.0 + np.exp(-t))
+        g = A.T @ (y - s) - w / data.prior_var
+        Hm = (A * (s * (1.0 - s))[:, None]).T @ A + np.eye(d) / data.prior_var
+        w = w + np.linalg.solve(Hm, g)
+    t = A @ w
+    s = 1.0 / (1.0 + np.exp(-t))
+    Hm = (A * (s * (1.0 - s))[:, None]).T @ A + np.eye(d) / data.prior_var
+    C = np.linalg.inv(Hm)
+    return w, 0.5 * (C + C.T)
+
+
 def batch_dims(n_targets: int = 48, lo: int = 128, hi: int = 3072) -> np.ndarray:
     rng = np.random.default_rng(999)
     u = rng.uniform(math.log(lo), math.log(hi), size=n_targets)

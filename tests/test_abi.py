@@ -33,12 +33,47 @@ def test_binding_loads():
     assert lib.diam_last_error() is not None
 
 
+# host-only size queries check that the target's pointers are set, never
+# dereference them: placeholders stand in for device buffers
+GAUSS = diam.Target(diam.TGT_GAUSS, 0, 256, 512, None, None, 0, 0.0)
+
+
+def logreg(n_obs=1000, prior_var=10.0):
+    return diam.Target(diam.TGT_LOGREG, 0, None, None, 256, 512, n_obs, prior_var)
+
+
 def test_workspace_bytes_scales_with_precision():
-    big = diam.workspace_bytes(diam.make_config(4096, 256, 256, "fp64"))
-    mix = diam.workspace_bytes(diam.make_config(4096, 256, 256, "mixed"))
+    big = diam.workspace_bytes(diam.make_config(4096, 256, 256, "fp64"), GAUSS)
+    mix = diam.workspace_bytes(diam.make_config(4096, 256, 256, "mixed"), GAUSS)
     assert 6 * 2 ** 30 < big < 8 * 2 ** 30
     assert mix < 0.6 * big
-    assert diam.workspace_bytes(diam.make_config(1, 1, 1)) > 0
+    assert diam.workspace_bytes(diam.make_config(1, 1, 1), GAUSS) > 0
+
+
+def test_workspace_bytes_of_the_learned_form():
+    cfg = diam.make_config(512, 256, 64, "fp32")
+    base = diam.workspace_bytes(cfg, logreg(200000))
+    # the logistic target's partial sums take one FP64 row per 64 observations
+    assert diam.workspace_bytes(cfg, logreg(200064)) - base in range(256 * 8, 256 * 8 + 512)
+    sur = diam.workspace_bytes(diam.make_config(512, 256, 64, "fp32", surrogate=True, train_max=10000), logreg(200000))
+    big = diam.workspace_bytes(diam.make_config(512, 256, 64, "fp32", surrogate=True, train_max=20000), logreg(200000))
+    # training pairs are held standardised in FP32: d + 1 floats each
+    assert abs((big - sur) - 10000 * 513 * 4) < 4096
+    nparam = 256 * 512 + 256 + 256 * 256 + 256 + 256 + 1
+    assert sur - base > 5 * nparam * 4 + 10000 * 513 * 4
+
+
+@pytest.mark.parametrize("tgt,msg", [
+    (logreg(n_obs=0), "n_obs"),
+    (logreg(prior_var=0.0), "prior_var"),
+    (diam.Target(diam.TGT_LOGREG, 0, None, None, None, 512, 10, 1.0), "needs A"),
+    (diam.Target(diam.TGT_GAUSS, 0, None, 512, None, None, 0, 0.0), "needs mu"),
+    (diam.Target(9, 0, 256, 512, None, None, 0, 0.0), "unknown target"),
+])
+def test_bad_target_is_rejected(tgt, msg):
+    with pytest.raises(diam.DiamError) as e:
+        diam.workspace_bytes(diam.make_config(8, 2, 4), tgt)
+    assert e.value.status == diam.E_ARG and msg in str(e.value)
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -48,13 +83,14 @@ def test_workspace_bytes_scales_with_precision():
     (dict(alpha=0.5), "alpha"),
     (dict(precision=7), "precision"),
     (dict(jitter0=-1.0), "jitter0"),
+    (dict(train_max=-5), "train_max"),
 ])
 def test_bad_config_is_rejected(kw, msg):
     base = dict(d=8, P=2, n_lag=4, precision="fp64", beta=0.3, alpha=1.0)
     base.update(kw)
     cfg = diam.make_config(**base)
     with pytest.raises(diam.DiamError) as e:
-        diam.workspace_bytes(cfg)
+        diam.workspace_bytes(cfg, GAUSS)
     assert e.value.status == diam.E_ARG and msg in str(e.value)
 
 
@@ -67,6 +103,9 @@ def test_null_arguments_are_rejected():
     assert lib.diam_step_batch(None, 1, None, None, None) == diam.E_ARG
     assert lib.diam_merge_moments(None) == diam.E_ARG
     assert lib.diam_update_proposal(None, None) == diam.E_ARG
+    assert lib.diam_surrogate_train(None, None, None, 0, 0, 0, 0.0, 0, None) == diam.E_ARG
+    assert lib.diam_surrogate_eval(None, None, 0, None) == diam.E_ARG
+    assert lib.diam_set_delayed_acceptance(None, 1) == diam.E_ARG
     assert b"null" in lib.diam_last_error()
 
 
