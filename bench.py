@@ -140,12 +140,13 @@ def learned_experiment(args, torch, diam):
     proj = torch.as_tensor(np.stack([V[:, -1], V[:, 0]]), device=dev).contiguous()
     n_pairs = 50000
     collect = -(-n_pairs // P)                            # steps whose states train the surrogate
+    betas = [float(b) for b in args.learned_betas.split(",")]
     out = {"workload": f"Bayesian logistic regression n=200000 d={d} (A ~ N(0, 1/d), prior N(0, 10 I)), "
-                       f"P={P}, n_lag={nl}, beta={args.learned_beta}, Laplace warm start",
-           "precision": args.learned_precision}
-    for use_da in (False, True):
-        cfg = diam.make_config(d, P, nl, args.learned_precision, beta=args.learned_beta, seed=91,
-                               surrogate=use_da, train_max=n_pairs)
+                       f"P={P}, n_lag={nl}, Laplace warm start; surrogate form {args.surrogate_form}",
+           "precision": args.learned_precision, "runs": []}
+    for beta, use_da in [(b, u) for b in betas for u in (False, True)]:
+        cfg = diam.make_config(d, P, nl, args.learned_precision, beta=beta, seed=91,
+                               surrogate=args.surrogate_form if use_da else 0, train_max=n_pairs)
         s = diam.Sampler(cfg, None, None, torch.as_tensor(np.ascontiguousarray(x0.T), device=dev), A=A, y=y,
                          prior_var=data.prior_var)
         assert s.seed_moments(S0, m0, 10 * P * nl)[0] == diam.OK
@@ -176,8 +177,8 @@ def learned_experiment(args, torch, diam):
             s.set_delayed_acceptance(True)
             torch.cuda.synchronize()
             train_s = time.perf_counter() - t1
-            out["surrogate"] = {"pairs": n_pairs, "adam_steps": args.train_steps, "batch": 256,
-                                "final_loss": loss, "train_seconds": train_s}
+            surr = {"pairs": n_pairs, "adam_steps": args.train_steps, "batch": 256, "final_loss": loss,
+                    "train_seconds": train_s}
         n_timed = args.learned_windows * nl
         trace = torch.empty((n_timed, 3, P), dtype=torch.float64, device=dev)
         s.set_trace(proj, trace)
@@ -196,20 +197,30 @@ def learned_experiment(args, torch, diam):
         tr = trace.cpu().numpy()
         ess = {name: ess_per_chain(tr[:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
         nacc = s.get(diam.F_NACC).view(torch.int32).sum().item() - nacc0
-        r = {"seconds": T, "chain_steps_per_s": P * n_timed / T, "ess": ess, "ess_per_s": min(ess.values()) / T,
+        r = {"beta": beta, "delayed_acceptance": use_da,
+             "seconds": T, "chain_steps_per_s": P * n_timed / T, "ess": ess, "ess_per_s": min(ess.values()) / T,
              "acceptance": nacc / (P * n_timed),
              "stage_ms_per_window": {k: v[0] / args.learned_windows for k, v in prof.items() if v[1]}}
         if use_da:
             npass = s.get(diam.F_NPASS).view(torch.int32).sum().item()
             r["stage1_pass_rate"] = npass / (P * n_timed)
+            r["stage2_accept_rate"] = nacc / max(npass, 1)
             r["ess_per_s_incl_training"] = min(ess.values()) / (T + train_s)
-        out["delayed_acceptance" if use_da else "plain"] = r
-        log(f"logistic {'DA' if use_da else 'plain'}: {r['chain_steps_per_s']:.4g} chain-steps/s, "
+            r["surrogate"] = surr
+        out["runs"].append(r)
+        log(f"logistic beta={beta} {'DA' if use_da else 'plain'}: {r['chain_steps_per_s']:.4g} chain-steps/s, "
             f"ESS/s {r['ess_per_s']:.4g}, acceptance {r['acceptance']:.3f}"
             + (f", stage-1 pass {r['stage1_pass_rate']:.3f}" if use_da else ""))
         s.close()
         del Xtr, ltr, trace
-    out["ess_per_s_gain"] = out["delayed_acceptance"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    plain = {r["beta"]: r for r in out["runs"] if not r["delayed_acceptance"]}
+    da = {r["beta"]: r for r in out["runs"] if r["delayed_acceptance"]}
+    out["ess_per_s_gain_at_beta"] = {str(b): da[b]["ess_per_s"] / plain[b]["ess_per_s"] for b in betas}
+    best_plain = max(r["ess_per_s"] for r in plain.values())
+    best_da = max(r["ess_per_s"] for r in da.values())
+    out["best_plain_ess_per_s"] = best_plain
+    out["best_da_ess_per_s"] = best_da
+    out["ess_per_s_gain"] = best_da / best_plain
     return out
 
 
@@ -265,9 +276,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-part (logistic) experiment")
+    ap.add_argument("--copy-calibration", dest="copy_calibration", type=int, default=0,
+                    help="first run 3 device copies of this many bytes (counter calibration)")
     ap.add_argument("--learned-only", action="store_true", help="run only the learned-part experiment")
     ap.add_argument("--learned-P", dest="learned_P", type=int, default=128)
-    ap.add_argument("--learned-beta", dest="learned_beta", type=float, default=0.5)
+    ap.add_argument("--learned-betas", dest="learned_betas", default="0.5,1.0")
+    ap.add_argument("--surrogate-form", dest="surrogate_form", type=int, default=2, choices=[1, 2])
     ap.add_argument("--learned-windows", dest="learned_windows", type=int, default=4)
     ap.add_argument("--learned-precision", dest="learned_precision", default="fp32", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--train-steps", dest="train_steps", type=int, default=3000)
@@ -279,6 +293,17 @@ def main():
     import torch
     from paper_1506_05741_amd import diam, synth
     diam.load()
+    if args.copy_calibration:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the kernel's HBM traffic figures
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {n * 4} bytes")
+        del src, dst
 
     if args.learned_only:
         print(json.dumps({"learned": learned_experiment(args, torch, diam)}), flush=True)

@@ -79,7 +79,9 @@ typedef struct {
   uint64_t seed;        /* Philox4x32-10 key for internally drawn W and U */
   double jitter0;       /* Cholesky retry: eps_j = 10^j jitter0 s, s = tr(C)/d (1 if not > 0) */
   int32_t jitter_tries; /* number of retry levels j = 0 .. jitter_tries-1 */
-  int32_t surrogate;    /* 1: reserve the learned-part buffers (MLP d-256-256-1, delayed acceptance) */
+  int32_t surrogate;    /* learned part (MLP d-256-256-1, delayed acceptance): 0 none; 1 the
+                           surrogate is the network; 2 residual form, the surrogate is
+                           network(x) - |A^-1 (x - x_ref)|^2 / (2 alpha^2) */
   int64_t train_max;    /* most (x, log pi(x)) pairs diam_surrogate_train will be given */
 } diam_config;
 
@@ -127,7 +129,7 @@ typedef enum {
   DIAM_F_WLO = 13,    /* d x P n    bf16 lo part of those normals (MIXED only) */
   DIAM_F_U = 14,      /* n x P (x2 under delayed acceptance) f64: uniforms drawn by
                                     the last call when U was NULL */
-  DIAM_F_SURR = 15,   /* P f64      surrogate log density of the current states */
+  DIAM_F_SURR = 15,   /* P f64      network output r at the current states (delayed acceptance on) */
   DIAM_F_NPASS = 16,  /* P int32    stage-1 survivors since delayed acceptance was enabled */
   DIAM_F_MLP_PARAMS = 17, /* nparam f32 master weights W1 (256 x d), b1, W2 (256 x 256), b2, W3 (256), b3 */
   DIAM_F_MLP_GRAD = 18,   /* nparam f32 gradient of the last training step */
@@ -198,31 +200,101 @@ int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double 
  * recording stops when full.  trace == NULL disables. */
 int diam_set_trace(diam_ctx* ctx, const double* proj, int32_t n_proj, double* trace, int64_t capacity);
 
-/* ---- learned-part form (requires cfg.surrogate = 1) ----------------------
- * Surrogate of log pi: s(x) = sd * (W3 h2 + b3) + mean, h2 = gelu(W2 h1 + b2),
+/* ---- learned-part form (requires cfg.surrogate = 1 or 2) -----------------
+ * Network: r(x) = sd * (W3 h2 + b3) + mean, h2 = gelu(W2 h1 + b2),
  * h1 = gelu(W1 xs + b1), xs = (x - in_mean) / in_std, exact GELU a Phi(a);
  * hidden widths 256 and 256.  The forward pass uses the bf16 roundings of FP32
  * master weights with FP32 MFMA accumulation; training (FP32 MFMA forward and
- * backward, Adam) runs on the GPU.
+ * backward, Adam) runs on the GPU.  Surrogate of log pi: s = r (form 1), or
+ * s(x) = r(x) - |z(x)|^2 / (2 alpha^2), z = A^-1 (x - x_ref) under the current
+ * factor (form 2: the network models what the proposal's Gaussian
+ * N(x_ref, alpha^2 A A^T) leaves out; that Gaussian part of s cancels the
+ * proposal correction in stage 1).
  *
- * Train on n pairs (X: d x n f64, lp: n f64, n <= cfg.train_max): input and
- * output standardisation from the pairs, He-normal initialisation from seed,
- * then `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on
- * minibatches of `batch` pairs drawn with replacement by Philox; mean squared
- * error on the standardised log density.  loss (host, may be NULL): the mean
- * loss of the last 50 steps.  Synchronises the stream. */
+ * Train on n pairs (X: d x n f64, lp: n f64 = log pi(X), n <= cfg.train_max):
+ * regression target lp (form 1) or lp + |z|^2/(2 alpha^2) under the factor
+ * current at the call (form 2); input and output standardisation from the
+ * pairs, He-normal initialisation from seed, then `steps` Adam steps (lr,
+ * beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of `batch` <= max(P, 512)
+ * pairs drawn with replacement by Philox; mean squared error on the
+ * standardised target.  loss (host, may be NULL): the mean loss of the last
+ * 50 steps.  Synchronises the stream.  DIAM_E_STATE while delayed acceptance
+ * is on. */
 int diam_surrogate_train(diam_ctx* ctx, const double* X, const double* lp, int64_t n, int32_t steps, int32_t batch,
                          double lr, uint64_t seed, double* loss);
-/* Surrogate log density of n states (X: d x n f64, n <= max(P, 512)) into out (n f64). */
+/* Network output r of n states (X: d x n f64, n <= max(P, 512)) into out (n f64). */
 int diam_surrogate_eval(diam_ctx* ctx, const double* X, int32_t n, double* out);
 /* Two-stage delayed acceptance (Christen & Fox 2005) in later steps when
- * on != 0: stage 1 accepts with log u1 < s(x') - s(x) + (|z'|^2 - |z|^2)/(2 alpha^2);
- * only stage-1 survivors are evaluated exactly (packed, so the target
- * contraction shrinks with them) and accepted with
+ * on != 0 (logistic target, trained network; else DIAM_E_STATE): stage 1
+ * accepts with log u1 < s(x') - s(x) + (|z'|^2 - |z|^2)/(2 alpha^2), which is
+ * r(x') - r(x) in form 2; only stage-1 survivors are evaluated exactly
+ * (packed, so the target contraction shrinks with them) and accepted with
  * log u2 < (log pi(x') - log pi(x)) - (s(x') - s(x)), so pi stays invariant.
- * The surrogate must stay fixed while it is on.  U per step then holds two
+ * The network must stay fixed while it is on.  U per step then holds two
  * rows of P uniforms (stage 1, stage 2). */
 int diam_set_delayed_acceptance(diam_ctx* ctx, int32_t on);
+
+/* ---- batched form ---------------------------------------------------------
+ * G independent Gaussian problems of dimensions dims[g] (each target as in
+ * diam_target, R FP32), P chains each, one shared n_lag.  Every call serves
+ * all problems: each phase of a window is one grouped launch whose
+ * workgroups are mapped to (problem, tile) by a tile list built at init, and
+ * with graphs on (the default) the whole window, its n_lag-step loop
+ * included, is captured once into a hipGraph and replayed.  Arithmetic is
+ * FP32 on MFMA with FP64 states, moments, Cholesky and log-acceptance, the
+ * same kernels as DIAM_FP32 of the single-problem calls: with the default
+ * target tile shape and the same normals and uniforms, every problem's
+ * states, moments and factor are bitwise those of a separate sampler. */
+typedef struct {
+  int32_t G;            /* number of problems, 1 .. 4096 */
+  int32_t P;            /* chains per problem */
+  int32_t n_lag;        /* even; P * n_lag <= 4096 (one FP32 span of the scatter) */
+  int32_t precision;    /* DIAM_FP32 */
+  double beta, alpha;
+  uint64_t seed;        /* Philox key of the normals and uniforms */
+  double jitter0;
+  int32_t jitter_tries;
+  int32_t reserved;
+} diam_batch_config;
+typedef struct diam_batch diam_batch;
+
+/* Workspace bytes for the problem set (host; dims: host array of G). */
+int diam_batch_workspace_bytes(const diam_batch_config* cfg, const int32_t* dims, size_t* bytes);
+/* Create the batch.  mu, R, x0: host arrays of G device pointers (mu[g]: d_g
+ * f64, R[g]: d_g x d_g f32 row-major, x0[g]: d_g x P f64, copied).  Each
+ * problem starts as diam_init does (A = I, x_ref = 0, log pi(x0)).  Returns
+ * after the initial evaluation (synchronises the stream). */
+int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, const int32_t* dims, const double* const* mu,
+                    const float* const* R, void* workspace, size_t ws_bytes, const double* const* x0,
+                    void* hip_stream);
+/* Warm start of every problem (S0[g], m0[g] device pointers, common N0), then
+ * the refactorisation; jitter (host, G, may be NULL) as diam_update_proposal. */
+int diam_batch_seed_moments(diam_batch* b, const double* const* S0, const double* const* m0, double N0,
+                            int32_t* jitter);
+/* One window of every problem: Philox normals and uniforms, the proposal
+ * contraction, n_lag steps (target contraction + accept/reject), the moment
+ * merge and the refactorisation (failed factorisations retried with the
+ * jitter rule, per problem).  jitter: host array of G or NULL.  Returns
+ * DIAM_E_NOT_PD if some problem failed at every level (it keeps its factor),
+ * DIAM_E_TARGET on +inf from a target.  Synchronises the batch's stream. */
+int diam_batch_window(diam_batch* b, int32_t* jitter);
+/* Target tile shape (0 .. 4: rows x k-groups 32x2, 64x1, 64x2, 128x2, 32x4;
+ * 32 chains per tile).  Default 2, the single-problem kernel's shape. */
+int diam_batch_set_tiles(diam_batch* b, int32_t choice);
+/* Time every target tile shape on this problem set (reps launches each) and
+ * keep the fastest; choice (host, may be NULL) gets it, us (host array of 5,
+ * may be NULL) the microseconds per launch of each. */
+int diam_batch_autotune(diam_batch* b, int32_t reps, int32_t* choice, double* us);
+/* Graph capture of the window on (default) or off (eager launches). */
+int diam_batch_set_graph(diam_batch* b, int32_t on);
+/* Per-problem fields at a window boundary: DIAM_F_X, Z, LOGP, ZQ, XREF, L, S,
+ * M, LA, ACC (last window, n_lag x P), NACC, W (last window's normals, d x
+ * P n_lag f32), U (last window's uniforms, n_lag x P f64). */
+int diam_batch_field_bytes(diam_batch* b, int32_t g, int32_t field, size_t* bytes);
+int diam_batch_get(diam_batch* b, int32_t g, int32_t field, void* dst, size_t bytes);
+/* steps, windows and n_samples of the batch (the other members are not used). */
+int diam_batch_get_stats(diam_batch* b, diam_stats* out);
+void diam_batch_destroy(diam_batch* b);
 
 /* Bytes of a field (host). */
 int diam_field_bytes(diam_ctx* ctx, int32_t field, size_t* bytes);

@@ -15,10 +15,16 @@ using dk::Prec;
 
 static thread_local char g_err[512] = "";
 
+// shared with the batched runtime (batch.hip)
+int diam_fail_v(int code, const char* fmt, va_list ap) {
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  return code;
+}
+
 static int fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  diam_fail_v(code, fmt, ap);
   va_end(ap);
   return code;
 }
@@ -43,7 +49,7 @@ struct Layout {
   // learned-part form
   size_t mlp_master, mlp_eff, mlp_grad, mlp_m, mlp_in_mean, mlp_in_scale, mlp_stats, mlp_Xs, mlp_ts, mlp_xb, mlp_tb,
       mlp_a1, mlp_h1, mlp_a2, mlp_h2, mlp_ga1, mlp_ga2, mlp_out, mlp_gout, mlp_loss, mlp_bidx, s_cur, s_new, pass1,
-      slot, idx, nsurv, npass, Vs;
+      slot, idx, nsurv, npass, Vs, t64, Zs;
   size_t total;
 };
 
@@ -132,6 +138,8 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
     L.nsurv = take(4);
     L.npass = take(P * 4);
     L.Vs = take(dP * 4);
+    L.t64 = take(c.surrogate == 2 ? nt * 8 : 0);
+    L.Zs = take(c.surrogate == 2 ? d * nmax * 8 : 0);
   }
   L.total = o;
   return L;
@@ -157,6 +165,7 @@ struct diam_ctx {
   uint8_t* pass1;
   int *slot, *idx, *nsurv, *npass;
   float* Vs;
+  double *t64, *Zs;
   int trained, da_on;
   int32_t last_batch;
   void *V, *W, *Wlo, *Xi, *win, *wint, *Llow, *syrk;
@@ -199,7 +208,7 @@ static int check_cfg(const diam_config* c) {
   // 32-bit tile indices: the window holds P * n_lag columns of d rows
   if ((long)c->P * c->n_lag > (1L << 30) || c->d > (1 << 20)) return fail(DIAM_E_ARG, "problem too large");
   if ((long)c->d * c->d > (1L << 34)) return fail(DIAM_E_ARG, "d too large");
-  if (c->surrogate != 0 && c->surrogate != 1) return fail(DIAM_E_ARG, "surrogate must be 0 or 1");
+  if (c->surrogate < 0 || c->surrogate > 2) return fail(DIAM_E_ARG, "surrogate must be 0, 1 or 2");
   if (c->train_max < 0 || c->train_max > (1L << 31)) return fail(DIAM_E_ARG, "train_max out of range");
   return DIAM_OK;
 }
@@ -395,12 +404,15 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
     c->nsurv = (int*)(c->ws + lay.nsurv);
     c->npass = (int*)(c->ws + lay.npass);
     c->Vs = fp(lay.Vs);
+    c->t64 = dptr(c, lay.t64);
+    c->Zs = dptr(c, lay.Zs);
   } else {
     c->mlp = dk::MlpBufs{};
     c->s_cur = c->s_new = nullptr;
     c->pass1 = nullptr;
     c->slot = c->idx = c->nsurv = c->npass = nullptr;
     c->Vs = nullptr;
+    c->t64 = c->Zs = nullptr;
   }
   c->nacc = (int32_t*)(c->ws + lay.nacc);
   c->la = dptr(c, lay.la);
@@ -558,10 +570,10 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     if (c->da_on) {
       // stage 1 on the surrogate, then the exact target on the survivors only
       ps = prof_begin(c, DIAM_ST_SURROGATE);
-      HIPCHK(dk::mlp_eval(c->mlp, nullptr, (const float*)c->V, P, c->s_new, s));
-      HIPCHK(dk::da_stage1(P, c->nch, c->s_new, c->s_cur + (long)cu * P, c->zq_part + (long)cu * c->nch * P,
-                           c->zq + (long)cu * P, u_t, a.inv2a2, c->pass1, c->slot, c->idx, c->nsurv, c->npass,
-                           (const float*)c->V, d, c->Vs, s));
+      HIPCHK(dk::da_screen(c->mlp, (const float*)c->V, d, P, c->nch, c->s_cur + (long)cu * P,
+                           c->zq_part + (long)cu * c->nch * P, c->zq + (long)cu * P, u_t, a.inv2a2,
+                           c->cfg.surrogate == 2, c->s_new, c->pass1, c->slot, c->idx, c->nsurv, c->npass, c->Vs,
+                           s));
       prof_end(c, ps);
     }
     ps = prof_begin(c, DIAM_ST_TARGET);
@@ -593,6 +605,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
       a.s_in = c->s_cur + (long)cu * P;
       a.s_out = c->s_cur + (long)nx * P;
       a.u2 = u_t + P;
+      a.da_resid = c->cfg.surrogate == 2;
     }
     a.la_out = c->la + (long)t * P;
     a.acc_out = c->acc + (long)t * P;
@@ -639,7 +652,19 @@ extern "C" int diam_surrogate_train(diam_ctx* c, const double* X, const double* 
   if (!(lr > 0.0)) return fail(DIAM_E_ARG, "lr must be > 0");
   hipStream_t s = c->stream;
   const int ps = prof_begin(c, DIAM_ST_TRAIN);
-  HIPCHK(dk::mlp_prepare(c->mlp, X, lp, n, seed, s));
+  const double* target = lp;
+  if (c->cfg.surrogate == 2) {
+    // residual form: the network learns log pi(x) + |z(x)|^2 / (2 alpha^2)
+    // with z under the current factor and pivot
+    const int d = c->cfg.d, chunk = nmax;
+    for (long k0 = 0; k0 < n; k0 += chunk) {
+      const int nc = (int)(n - k0 < chunk ? n - k0 : chunk);
+      HIPCHK(dk::trsm_whiten(c->L, X + k0 * d, c->xr, c->Zs, c->t64 + k0, c->linv, d, nc, s));
+    }
+    HIPCHK(dk::axpy_f64(lp, c->t64, 1.0 / (2.0 * c->cfg.alpha * c->cfg.alpha), n, c->t64, s));
+    target = c->t64;
+  }
+  HIPCHK(dk::mlp_prepare(c->mlp, X, target, n, seed, s));
   dk::MlpBufs b = c->mlp;
   for (int t = 0; t < steps; ++t) {
     b.loss = c->mlp.loss + (t % LOSS_HIST);

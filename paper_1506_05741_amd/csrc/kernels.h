@@ -45,10 +45,14 @@ hipError_t mlp_train_step(const MlpBufs& b, long n, int nb, long tau, uint64_t s
 hipError_t mlp_forward(const MlpBufs& b, const float* xs, int n, hipStream_t s);
 // s_out[j] = surrogate log density of column j of X64 (FP64) or X32 (FP32), d x n
 hipError_t mlp_eval(const MlpBufs& b, const double* X64, const float* X32, int n, double* s_out, hipStream_t s);
-// Delayed acceptance stage 1 and survivor packing.
-hipError_t da_stage1(int P, int nch, const double* s_new, const double* s_cur, const double* zq_part, const double* zq,
-                     const double* u1, double inv2a2, uint8_t* pass, int* slot, int* idx, int* nsurv, int* npass,
-                     const float* V, int d, float* Vs, hipStream_t s);
+// Delayed acceptance stage 1 from the network's hidden layer h2 (filled by
+// mlp_forward-equivalent GEMMs on V), survivor packing into Vs.
+hipError_t da_screen(const MlpBufs& b, const float* V, int d, int P, int nch, const double* s_cur,
+                     const double* zq_part, const double* zq, const double* u1, double inv2a2, int resid,
+                     double* s_new, uint8_t* pass, int* slot, int* idx, int* nsurv, int* npass, float* Vs,
+                     hipStream_t s);
+// t = lp + c zq
+hipError_t axpy_f64(const double* lp, const double* zq, double c, long n, double* t, hipStream_t s);
 
 // Xi = c L W over ncols columns; L lower (d x d): f64/f32 column-major,
 // bf16 as hi then lo row-major copies; W: f64/f32 column-major, bf16 as hi
@@ -128,6 +132,7 @@ struct StepArgs {
   const double* s_new;                    // P: surrogate at the proposals
   const double* s_in; double* s_out;      // P: surrogate at the current states
   const double* u2;                       // P
+  int da_resid;                           // residual surrogate r(x) - |z|^2/(2 alpha^2)
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
 
@@ -139,5 +144,47 @@ hipError_t init_finish(const double* part, int nrb, const double* Z, const doubl
 // trace[t][1 + k][p] = sum_ch proj_part[t][ch][k][p]
 hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P, double* trace, int nfun,
                        hipStream_t s);
+
+// ---- batched form: G independent Gaussian problems, FP32 path ----------------
+// Per-problem device buffers (FP64 state and moments, FP32 operands).
+struct BProb {
+  int d, nch, nrb, nb;              // dimension, step chunks, target row blocks, Cholesky blocks
+  const float* R;                   // d x d row-major
+  const double* mu;                 // d
+  double *X, *Z, *xr, *lp, *zq;     // d x P, d x P, d, 2 x P, 2 x P
+  double *zq_part, *lpp_part, *la;  // 2 x nch x P, nrb x P, n x P
+  uint8_t* acc;                     // n x P
+  float *V, *W, *Xi, *win;          // d x P, d x P n (x3)
+  double *S, *m, *L, *C, *Linv, *G, *h;
+  float* Llow;                      // d x d
+  int *nacc, *info;
+};
+struct BTile { int g, a, b; };      // problem, tile coordinates
+struct BStep {
+  int t, n, P;                      // step in the window (-1: first proposal only), n_lag, chains
+  double rho, c, inv2a2;
+  const double* U;                  // (g n + t) P + p
+  int* err;
+};
+constexpr int G_TGT_CONFIGS = 5;    // target tile shapes the autotuner chooses from
+int g_tgt_bm(int cfg);
+hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s);
+hipError_t g_step(const BProb* pr, const BTile* tl, int ntiles, const BStep& st, hipStream_t s);
+hipError_t g_trigemm(const BProb* pr, const BTile* tl, int ntiles, int ncols, double c, hipStream_t s);
+hipError_t g_scatter(const BProb* pr, const BTile* syrk_tl, int nsyrk, const BTile* row_tl, int nrow, int K,
+                     hipStream_t s);
+hipError_t g_fold(const BProb* pr, const BTile* dd_tl, int ndd, const BTile* d_tl, int nd, const double* N, double K,
+                  hipStream_t s);
+hipError_t g_cov(const BProb* pr, const BTile* dd_tl, int ndd, hipStream_t s);
+hipError_t g_chol_step(const BProb* pr, const BTile* diag, int ndiag, const BTile* panel, int npanel,
+                       const BTile* upd, int nupd, int jb, hipStream_t s);
+hipError_t g_adopt(const BProb* pr, const BTile* dd_tl, int ndd, hipStream_t s);
+hipError_t g_sub_ref(const BProb* pr, const BTile* dp_tl, int ndp, int P, hipStream_t s);
+hipError_t g_tri_inv(const BProb* pr, const BTile* tl, int n, hipStream_t s);
+hipError_t g_trsm_step(const BProb* pr, const BTile* diag, int ndiag, const BTile* upd, int nupd, int jb, int P,
+                       hipStream_t s);
+hipError_t g_colnorm(const BProb* pr, const BTile* tl, int n, hipStream_t s);
+hipError_t g_rng(uint64_t seed, const long* win, long nW, long nU, int P, float* W, double* U, hipStream_t s);
+hipError_t g_bump(long* win, double* N, double K, hipStream_t s);
 
 }  // namespace dk

@@ -17,13 +17,14 @@ DEV double propose1(double xr, double x, double rho, double xi) { return __fma_r
 // (b) target log-density: Gaussian, Y = R (x - mu) on MFMA, then column sums
 // of Y^2 in FP64 per 64-row block (the caller adds the blocks in order).
 // ============================================================================
-template <typename T, int BK>
-__global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
-                                                   double* __restrict__ part) {
-  constexpr int BM = 64, BN = 64, KG = 2;
+// One output tile: rows [bx BM, +BM) of Y, chains [by BN, +BN); the tile's
+// FP64 partial sums go to part[bx * ldp + j] (one row per BM rows of R).
+template <typename T, int BK, int BM, int BN, int KG>
+DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d, int P, int bx, int by,
+                        double* __restrict__ part, int ldp) {
   __shared__ T lds[KG * e_lds_elems<T, BM, BN, BK>()];
   __shared__ double red[2][BN];
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int i0 = bx * BM, j0 = by * BN;
   EFrag<T, BM, BN> f;
   f.zero();
   e_gemm<T, BM, BN, BK, true, true, KG>(f, R, d, d, V, d, P, i0, j0, 0, d, lds);
@@ -48,8 +49,14 @@ __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, cons
   __syncthreads();
   if (threadIdx.x < BN) {
     const int j = j0 + threadIdx.x;
-    if (j < P) part[(long)blockIdx.x * P + j] = -0.5 * (red[0][threadIdx.x] + red[1][threadIdx.x]);
+    if (j < P) part[(long)bx * ldp + j] = -0.5 * (red[0][threadIdx.x] + red[1][threadIdx.x]);
   }
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
+                                                   double* __restrict__ part) {
+  tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, P);
 }
 
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
@@ -66,11 +73,11 @@ hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, doub
 // row tile stops at its last row.
 // ============================================================================
 template <typename T, int BK>
-__global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, const T* __restrict__ W, T* __restrict__ Xi,
-                                                   int d, int ncols, double c) {
+DEV void trigemm_tile(const T* __restrict__ L, const T* __restrict__ W, T* __restrict__ Xi, int d, int ncols, double c,
+                      int bx, int by) {
   constexpr int BM = 64, BN = 64;
   __shared__ T lds[e_lds_elems<T, BM, BN, BK>()];
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int i0 = bx * BM, j0 = by * BN;
   const int kend = min(d, i0 + BM);
   EFrag<T, BM, BN> f;
   f.zero();
@@ -86,6 +93,12 @@ __global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, cons
         const int i = i0 + ti, j = j0 + tj;
         if (i < d && j < ncols) Xi[i + (long)j * d] = (T)(c * (double)f.c[m][n][r]);
       }
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, const T* __restrict__ W, T* __restrict__ Xi,
+                                                   int d, int ncols, double c) {
+  trigemm_tile<T, BK>(L, W, Xi, d, ncols, c, blockIdx.x, blockIdx.y);
 }
 
 // bf16: Xi^T = W~^T L~^T with the roles swapped so that lanes run along the
@@ -161,15 +174,15 @@ DEV void tile_pair(int t, int& bi, int& bj) {
 
 constexpr int FOLD_K = 4096;  // fp32 accumulation span before folding into fp64
 
+// lower tile t (row-by-row enumeration) of the scatter over K split ksp
 template <typename T, int BK>
-__global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d, int K, int kchunk,
-                                                double* __restrict__ Gpart) {
+DEV void syrk_tile(const T* __restrict__ Xs, int d, int K, int kchunk, int t, int ksp, double* __restrict__ Gpart) {
   constexpr int BM = 64, BN = 64;
   __shared__ T lds[e_lds_elems<T, BM, BN, BK>()];
   int bi, bj;
-  tile_pair(blockIdx.x, bi, bj);
+  tile_pair(t, bi, bj);
   const int i0 = bi * BM, j0 = bj * BN;
-  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  const int kb = ksp * kchunk, ke = min(K, kb + kchunk);
   double acc[EFrag<T, BM, BN>::FM][EFrag<T, BM, BN>::FN][4];
 #pragma unroll
   for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d,
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[m][n][r] += (double)f.c[m][n][r];
   }
-  double* G = Gpart + (long)blockIdx.y * d * d;
+  double* G = Gpart + (long)ksp * d * d;
 #pragma unroll
   for (int m = 0; m < EFrag<T, BM, BN>::FM; ++m)
 #pragma unroll
@@ -201,6 +214,12 @@ __global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d,
         const int i = i0 + ti, j = j0 + tj;
         if (i < d && j < d) G[j + (long)i * d] = acc[m][n][r];  // G(i,j) at (row j, col i): upper
       }
+}
+
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_syrk_e(const T* __restrict__ Xs, int d, int K, int kchunk,
+                                                double* __restrict__ Gpart) {
+  syrk_tile<T, BK>(Xs, d, K, kchunk, blockIdx.x, blockIdx.y, Gpart);
 }
 
 // bf16: Xt is the transposed window (d x K row-major, ld = K).  Tiles are
@@ -264,30 +283,35 @@ __global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, i
 // Row sums over K of the window.  COLMAJOR: element (i, k) at X[i + k d];
 // otherwise at X[i K + k] (bf16 transposed window).
 template <typename T, bool COLMAJOR>
-__global__ __launch_bounds__(256) void k_rowsum(const T* __restrict__ X, int d, int K, int kchunk,
-                                                double* __restrict__ hpart) {
+DEV void rowsum_block(const T* __restrict__ X, int d, int K, int kchunk, int bx, int by, double* __restrict__ hpart) {
   __shared__ double red[4][64];
-  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  const int kb = by * kchunk, ke = min(K, kb + kchunk);
   if (COLMAJOR) {
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + r;
+    const int i = bx * 64 + r;
     double s = 0.0;
     if (i < d)
       for (int k = kb + q; k < ke; k += 4) s += (double)X[i + (long)k * d];
     red[q][r] = s;
     __syncthreads();
     if (threadIdx.x < 64 && i < d)
-      hpart[(long)blockIdx.y * d + i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+      hpart[(long)by * d + i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
   } else {
     // one row per wavefront, 4 rows per block
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + w;
+    const int i = bx * 4 + w;
     if (i >= d) return;
     double s = 0.0;
     for (int k = kb + lane; k < ke; k += 64) s += (double)bf16_bits_to_f32(((const u16*)X)[(long)i * K + k]);
     s = wave_sum_f64(s);
-    if (lane == 0) hpart[(long)blockIdx.y * d + i] = s;
+    if (lane == 0) hpart[(long)by * d + i] = s;
   }
+}
+
+template <typename T, bool COLMAJOR>
+__global__ __launch_bounds__(256) void k_rowsum(const T* __restrict__ X, int d, int K, int kchunk,
+                                                double* __restrict__ hpart) {
+  rowsum_block<T, COLMAJOR>(X, d, K, kchunk, blockIdx.x, blockIdx.y, hpart);
 }
 
 // col-major d x K bf16 -> row-major d x K (ld K)
@@ -405,22 +429,31 @@ hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipS
 // ============================================================================
 // moment fold (eqs. mom2g / mom1g with sample counts), covariance assembly
 // ============================================================================
+DEV void fold_mean_elem(const double* __restrict__ h, const double* __restrict__ sft, double N, double n,
+                        double* __restrict__ m, int i) {
+  m[i] = (N * m[i] + (h[i] + n * sft[i])) / (N + n);
+}
+
+DEV void fold_S_elem(const double* __restrict__ G, const double* __restrict__ h, const double* __restrict__ sft,
+                     double N, double n, double* __restrict__ S, int d, long e) {
+  const int i = (int)(e % d), j = (int)(e / d);
+  const int a = i > j ? i : j, b = i > j ? j : i;
+  const double g = G[b + (long)a * d];  // upper storage
+  const double sxx = g + sft[a] * h[b] + h[a] * sft[b] + n * sft[a] * sft[b];
+  S[e] = (N * S[e] + sxx) / (N + n);
+}
+
 __global__ __launch_bounds__(256) void k_fold_mean(const double* __restrict__ h, const double* __restrict__ sft, double N,
                                                    double n, double* __restrict__ m, int d) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < d) m[i] = (N * m[i] + (h[i] + n * sft[i])) / (N + n);
+  if (i < d) fold_mean_elem(h, sft, N, n, m, i);
 }
 
 __global__ __launch_bounds__(256) void k_fold_S(const double* __restrict__ G, const double* __restrict__ h,
                                                 const double* __restrict__ sft, double N, double n,
                                                 double* __restrict__ S, int d) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)d * d) return;
-  const int i = (int)(e % d), j = (int)(e / d);
-  const int a = i > j ? i : j, b = i > j ? j : i;
-  const double g = G[b + (long)a * d];  // upper storage
-  const double sxx = g + sft[a] * h[b] + h[a] * sft[b] + n * sft[a] * sft[b];
-  S[e] = (N * S[e] + sxx) / (N + n);
+  if (e < (long)d * d) fold_S_elem(G, h, sft, N, n, S, d, e);
 }
 
 hipError_t fold_moments(const double* G, const double* h, const double* sft, double N, long K, double* S, double* m,
@@ -430,10 +463,8 @@ hipError_t fold_moments(const double* G, const double* h, const double* sft, dou
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_cov(const double* __restrict__ S, const double* __restrict__ m, double eps,
-                                             double* __restrict__ C, int d) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)d * d) return;
+DEV void cov_elem(const double* __restrict__ S, const double* __restrict__ m, double eps, double* __restrict__ C,
+                  int d, long e) {
   const int i = (int)(e % d), j = (int)(e / d);
   double v = 0.0;
   if (i >= j) {
@@ -443,8 +474,13 @@ __global__ __launch_bounds__(256) void k_cov(const double* __restrict__ S, const
   C[e] = v;
 }
 
-__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ S, const double* __restrict__ m, int d,
-                                               double* __restrict__ tr) {
+__global__ __launch_bounds__(256) void k_cov(const double* __restrict__ S, const double* __restrict__ m, double eps,
+                                             double* __restrict__ C, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < (long)d * d) cov_elem(S, m, eps, C, d, e);
+}
+
+DEV void trace_block(const double* __restrict__ S, const double* __restrict__ m, int d, double* __restrict__ tr) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) s += S[i + (long)i * d] - m[i] * m[i];
@@ -455,6 +491,11 @@ __global__ __launch_bounds__(256) void k_trace(const double* __restrict__ S, con
     __syncthreads();
   }
   if (threadIdx.x == 0) *tr = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ S, const double* __restrict__ m, int d,
+                                               double* __restrict__ tr) {
+  trace_block(S, m, d, tr);
 }
 
 hipError_t cov_assemble(const double* S, const double* m, double eps, double* C, double* tr, int d, hipStream_t s) {
@@ -484,8 +525,8 @@ DEV void tri_inverse_col(const double (*Ls)[CHOL_NB + 1], double* x, int c) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
-                                                  double* __restrict__ Linv, int* __restrict__ info) {
+DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
+                         int* __restrict__ info) {
   __shared__ double colv[CHOL_NB];
   __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
   const int r = threadIdx.x;
@@ -534,10 +575,15 @@ __global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d,
   for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
 }
 
+__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
+                                                  double* __restrict__ Linv, int* __restrict__ info) {
+  chol_diag_block(A, d, j0, jn, Linv, info);
+}
+
 // Inverses of all (already factored) diagonal blocks of L, one wave per block.
-__global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ L, int d, double* __restrict__ Linv) {
+DEV void tri_inv_block(const double* __restrict__ L, int d, double* __restrict__ Linv, int bx) {
   __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
-  const int r = threadIdx.x, j0 = blockIdx.x * CHOL_NB, jn = min(CHOL_NB, d - j0);
+  const int r = threadIdx.x, j0 = bx * CHOL_NB, jn = min(CHOL_NB, d - j0);
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
     double v = (c == r) ? 1.0 : 0.0;
@@ -547,17 +593,20 @@ __global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ L, in
   __syncthreads();
   double x[CHOL_NB];
   tri_inverse_col(Ls, x, r);
-  double* out = Linv + (long)blockIdx.x * CHOL_NB * CHOL_NB;
+  double* out = Linv + (long)bx * CHOL_NB * CHOL_NB;
 #pragma unroll
   for (int q = 0; q < CHOL_NB; ++q) out[q + r * CHOL_NB] = x[q];
 }
 
+__global__ __launch_bounds__(64) void k_tri_inv(const double* __restrict__ L, int d, double* __restrict__ Linv) {
+  tri_inv_block(L, d, Linv, blockIdx.x);
+}
+
 // Panel rows below the diagonal block: A(i, j0 + c) <- sum_q A(i, j0 + q) Linv(c, q)
-__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int d, int j0, int jn,
-                                                    const double* __restrict__ Linv) {
+DEV void chol_panel_tile(double* __restrict__ A, int d, int j0, int jn, const double* __restrict__ Linv, int bx) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
-  const int i0 = j0 + jn + blockIdx.x * BM;
+  const int i0 = j0 + jn + bx * BM;
   EFrag<double, BM, BN> f;
   f.zero();
   e_gemm<double, BM, BN, BK, false, false>(f, A + (long)j0 * d, d, d, Linv, CHOL_NB, jn, i0, 0, 0, jn, lds);
@@ -574,13 +623,18 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int 
       }
 }
 
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int d, int j0, int jn,
+                                                    const double* __restrict__ Linv) {
+  chol_panel_tile(A, d, j0, jn, Linv, blockIdx.x);
+}
+
 // Trailing update A(i, k) -= sum_c A(i, c) A(k, c) over the panel columns,
 // for the lower tiles of block rows/cols >= t0.
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
+DEV void chol_update_tile(double* __restrict__ A, int d, int j0, int jn, int t0, int t) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
   int bi, bk;
-  tile_pair(blockIdx.x, bi, bk);
+  tile_pair(t, bi, bk);
   const int i0 = (t0 + bi) * BM, k0 = (t0 + bk) * BN;
   const double* Pc = A + (long)j0 * d;
   EFrag<double, BM, BN> f;
@@ -597,6 +651,10 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
         const int i = i0 + ti, k = k0 + tj;
         if (i < d && k < d) A[i + (long)k * d] -= f.c[m][n][r];
       }
+}
+
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
+  chol_update_tile(A, d, j0, jn, t0, blockIdx.x);
 }
 
 size_t chol_scratch_bytes(int d) { return (size_t)cdiv(d, CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double); }
@@ -616,9 +674,7 @@ hipError_t potrf(double* A, int d, int* info, double* Linv, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restrict__ L, void* __restrict__ Llow, int d) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)d * d) return;
+DEV void round_factor_elem(int prec, double* __restrict__ L, void* __restrict__ Llow, int d, long e) {
   const int i = (int)(e % d), j = (int)(e / d);
   const double v = (i >= j) ? L[e] : 0.0;
   if (prec == P32) {
@@ -636,6 +692,11 @@ __global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restri
   }
 }
 
+__global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restrict__ L, void* __restrict__ Llow, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < (long)d * d) round_factor_elem(prec, L, Llow, d, e);
+}
+
 hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s) {
   if (prec == P64) return hipSuccess;
   hipLaunchKernelGGL(k_round_factor, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, (int)prec, L, Llow, d);
@@ -643,19 +704,23 @@ hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s) 
 }
 
 // ---- whitening Z = L^-1 (X - xr) ------------------------------------------
+DEV void sub_ref_elem(const double* __restrict__ X, const double* __restrict__ xr, double* __restrict__ Z, int d,
+                      long e) {
+  Z[e] = X[e] - xr[e % d];
+}
+
 __global__ __launch_bounds__(256) void k_sub_ref(const double* __restrict__ X, const double* __restrict__ xr,
                                                  double* __restrict__ Z, int d, int P) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e < (long)d * P) Z[e] = X[e] - xr[e % d];
+  if (e < (long)d * P) sub_ref_elem(X, xr, Z, d, e);
 }
 
 // Z_j <- Linv_jj Z_j (in place: each workgroup reads its 64 x 64 column
 // block completely before writing it back)
-__global__ __launch_bounds__(256) void k_trsm_diag(const double* __restrict__ Linv, double* __restrict__ Z, int d, int P,
-                                                   int j0, int jn) {
+DEV void trsm_diag_tile(const double* __restrict__ Linv, double* __restrict__ Z, int d, int P, int j0, int jn, int bx) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
-  const int p0 = blockIdx.x * BN;
+  const int p0 = bx * BN;
   EFrag<double, BM, BN> f;
   f.zero();
   e_gemm<double, BM, BN, BK, false, true>(f, Linv, CHOL_NB, jn, Z + j0, d, P, 0, p0, 0, jn, lds);
@@ -672,12 +737,17 @@ __global__ __launch_bounds__(256) void k_trsm_diag(const double* __restrict__ Li
       }
 }
 
+__global__ __launch_bounds__(256) void k_trsm_diag(const double* __restrict__ Linv, double* __restrict__ Z, int d, int P,
+                                                   int j0, int jn) {
+  trsm_diag_tile(Linv, Z, d, P, j0, jn, blockIdx.x);
+}
+
 // Z_i -= L_ij Z_j for row blocks below j
-__global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
-                                                     int j0, int jn) {
+DEV void trsm_update_tile(const double* __restrict__ L, double* __restrict__ Z, int d, int P, int j0, int jn, int bx,
+                          int by) {
   constexpr int BM = 64, BN = 64, BK = 16;
   __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
-  const int i0 = j0 + jn + blockIdx.x * BM, p0 = blockIdx.y * BN;
+  const int i0 = j0 + jn + bx * BM, p0 = by * BN;
   EFrag<double, BM, BN> f;
   f.zero();
   e_gemm<double, BM, BN, BK, false, true>(f, L + (long)j0 * d, d, d, Z + j0, d, P, i0, p0, 0, jn, lds);
@@ -694,9 +764,13 @@ __global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ 
       }
 }
 
-__global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ Z, int d, double* __restrict__ zq) {
+__global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
+                                                     int j0, int jn) {
+  trsm_update_tile(L, Z, d, P, j0, jn, blockIdx.x, blockIdx.y);
+}
+
+DEV void colnorm_block(const double* __restrict__ Z, int d, double* __restrict__ zq, int p) {
   __shared__ double red[256];
-  const int p = blockIdx.x;
   double s = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) {
     const double z = Z[i + (long)p * d];
@@ -709,6 +783,10 @@ __global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ Z, i
     __syncthreads();
   }
   if (threadIdx.x == 0) zq[p] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_colnorm(const double* __restrict__ Z, int d, double* __restrict__ zq) {
+  colnorm_block(Z, d, zq, blockIdx.x);
 }
 
 hipError_t trsm_whiten(const double* L, const double* X, const double* xr, double* Z, double* zq, double* Linv, int d,
@@ -857,17 +935,16 @@ DEV void store_win(void* win, long e, double v) {
 
 constexpr int MAXPROJ = 4;
 
+// chunk ch of nch (STEP_RCH rows each) of chains 4 pq .. 4 pq + 3, one wave each
 template <int PR>
-__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   typedef typename StepT<PR>::XI XI;
   typedef typename StepT<PR>::VT VT;
   constexpr int RPL = STEP_RCH / 64;  // rows per lane
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int p = blockIdx.y * 4 + w;
-  const int ch = blockIdx.x;
+  const int p = pq * 4 + w;
   if (p >= a.P) return;
   const int d = a.d, P = a.P;
-  const int nch = gridDim.x;
   const int r0 = ch * STEP_RCH;
   const XI* xi_cur = (const XI*)a.xi_cur;
   const XI* xi_nxt = (const XI*)a.xi_nxt;
@@ -923,8 +1000,11 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
       la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
       acc = log(a.u[p]) < la;  // NaN compares false: rejected
     } else {
-      // second stage: log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x))
-      la = live ? (lpp - lp) - (a.s_new[p] - a.s_in[p]) : -INFINITY;
+      // second stage: log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x)),
+      // with s = r - |z|^2/(2 alpha^2) in the residual form (r = network)
+      double l2 = (lpp - lp) - (a.s_new[p] - a.s_in[p]);
+      if (a.da_resid) l2 += (zs - zq) * a.inv2a2;
+      la = live ? l2 : -INFINITY;
       acc = live && (log(a.u2[p]) < la);
     }
     if (ch == 0 && lane == 0) {
@@ -981,6 +1061,11 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   }
 }
 
+template <int PR>
+__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+  step_body<PR>(a, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
 hipError_t step(const StepArgs& a, hipStream_t s) {
   dim3 grid(step_chunks(a.d), cdiv(a.P, 4));
   if (a.prec == P64) hipLaunchKernelGGL(k_step<P64>, grid, dim3(256), 0, s, a);
@@ -989,15 +1074,19 @@ hipError_t step(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_init_eval(int v64, const double* __restrict__ X, const double* __restrict__ mu,
-                                                   void* __restrict__ V, double* __restrict__ Z, int d, long n) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
+DEV void init_eval_elem(int v64, const double* __restrict__ X, const double* __restrict__ mu, void* __restrict__ V,
+                        double* __restrict__ Z, int d, long e) {
   const double x = X[e];
   const double v = x - (mu ? mu[e % d] : 0.0);
   if (v64) ((double*)V)[e] = v;
   else ((float*)V)[e] = (float)v;
   Z[e] = x;
+}
+
+__global__ __launch_bounds__(256) void k_init_eval(int v64, const double* __restrict__ X, const double* __restrict__ mu,
+                                                   void* __restrict__ V, double* __restrict__ Z, int d, long n) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) init_eval_elem(v64, X, mu, V, Z, d, e);
 }
 
 hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s) {
@@ -1007,11 +1096,9 @@ hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double
 }
 
 // lp[p] = sum_rb part[rb][p] - prior_w |x_p|^2 (one block per chain)
-__global__ __launch_bounds__(256) void k_init_finish(const double* __restrict__ part, int nrb, int P,
-                                                     const double* __restrict__ X, int d, double prior_w,
-                                                     double* __restrict__ lp) {
+DEV void init_finish_block(const double* __restrict__ part, int nrb, int P, const double* __restrict__ X, int d,
+                           double prior_w, double* __restrict__ lp, int p) {
   __shared__ double red[2][256];
-  const int p = blockIdx.x;
   double s = 0.0, q = 0.0;
   for (int k = threadIdx.x; k < nrb; k += 256) s += part[(long)k * P + p];
   if (prior_w > 0.0)
@@ -1030,6 +1117,12 @@ __global__ __launch_bounds__(256) void k_init_finish(const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) lp[p] = (prior_w > 0.0) ? __fma_rn(-prior_w, red[1][0], red[0][0]) : red[0][0];
+}
+
+__global__ __launch_bounds__(256) void k_init_finish(const double* __restrict__ part, int nrb, int P,
+                                                     const double* __restrict__ X, int d, double prior_w,
+                                                     double* __restrict__ lp) {
+  init_finish_block(part, nrb, P, X, d, prior_w, lp, blockIdx.x);
 }
 
 hipError_t init_finish(const double* part, int nrb, const double* Z, const double* X, double prior_w, double* lp,
@@ -1057,6 +1150,313 @@ hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, proj_part, n, nch, nproj, P,
                      trace, nfun);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Batched form: G independent Gaussian problems of uneven d with P chains
+// each (FP32 path, FP64 state and Cholesky).  Every launch below serves all
+// problems at once: a host-built tile list maps blockIdx.x to (problem, tile),
+// and the tile runs the same body as the single-problem kernel, so results
+// are bitwise those of separate runs with the same tile shapes.
+// ============================================================================
+__global__ __launch_bounds__(256) void gk_normals(uint32_t k0, uint32_t k1, const long* __restrict__ win,
+                                                  long per_window, long total, float* __restrict__ W) {
+  const long g0 = *win * per_window;
+  const long stride = (long)gridDim.x * 256;
+  for (long q = (long)blockIdx.x * 256 + threadIdx.x; 4 * q < total; q += stride) {
+    const uint64_t ctr = (uint64_t)(g0 + 4 * q);
+    const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
+    const float ua = u01_f32(r.x), ub = u01_f32(r.y), uc = u01_f32(r.z), ud = u01_f32(r.w);
+    const float ra = sqrtf(-2.0f * logf(ua)), rc = sqrtf(-2.0f * logf(uc));
+    float s1, c1, s2, c2;
+    sincosf(6.28318530717958647692f * ub, &s1, &c1);
+    sincosf(6.28318530717958647692f * ud, &s2, &c2);
+    const float v[4] = {ra * c1, ra * s1, rc * c2, rc * s2};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (4 * q + e < total) W[4 * q + e] = v[e];
+  }
+}
+
+// U[e], e = (g n + t) P + p: Philox stream 1, counter (window, problem-step, p/2)
+__global__ __launch_bounds__(256) void gk_uniforms(uint32_t k0, uint32_t k1, const long* __restrict__ win, long total,
+                                                   int P, double* __restrict__ U) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int p = (int)(e % P);
+  const long gt = e / P;
+  const uint64_t w = (uint64_t)*win;
+  const u4_t r = philox4x32_10({(uint32_t)w, (uint32_t)gt, 1u, (uint32_t)(p >> 1)}, k0, k1);
+  U[e] = (p & 1) ? u01_f64(r.z, r.w) : u01_f64(r.x, r.y);
+}
+
+__global__ void gk_bump(long* win, double* N, double K) {
+  if (threadIdx.x == 0) {
+    *win += 1;
+    *N += K;
+  }
+}
+
+template <int BM, int KG>
+__global__ __launch_bounds__(256 * KG) void gk_tgt(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int P) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  tgt_gauss_tile<float, 32, BM, 32, KG>(b.R, b.V, b.d, P, t.a, t.b, b.lpp_part, P);
+}
+
+hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((gk_tgt<32, 2>), dim3(ntiles), dim3(512), 0, s, pr, tl, P); break;
+    case 1: hipLaunchKernelGGL((gk_tgt<64, 1>), dim3(ntiles), dim3(256), 0, s, pr, tl, P); break;
+    case 2: hipLaunchKernelGGL((gk_tgt<64, 2>), dim3(ntiles), dim3(512), 0, s, pr, tl, P); break;
+    case 3: hipLaunchKernelGGL((gk_tgt<128, 2>), dim3(ntiles), dim3(512), 0, s, pr, tl, P); break;
+    default: hipLaunchKernelGGL((gk_tgt<32, 4>), dim3(ntiles), dim3(1024), 0, s, pr, tl, P); break;
+  }
+  return hipGetLastError();
+}
+int g_tgt_bm(int cfg) {
+  static const int bm[G_TGT_CONFIGS] = {32, 64, 64, 128, 32};
+  return bm[cfg];
+}
+
+__global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, const BTile* __restrict__ tl, BStep st) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int P = st.P, d = b.d, cu = st.t & 1, nx = cu ^ 1;
+  const long dP = (long)d * P;
+  StepArgs a{};
+  a.d = d;
+  a.P = P;
+  a.prec = P32;
+  a.rho = st.rho;
+  a.c = st.c;
+  a.inv2a2 = st.inv2a2;
+  a.xr = b.xr;
+  a.mu = b.mu;
+  a.X = b.X;
+  a.Z = b.Z;
+  a.V = b.V;
+  a.nrb = b.nrb;
+  a.lpp_part = b.lpp_part;
+  a.nacc = b.nacc;
+  a.win = b.win;
+  a.err = st.err;
+  if (st.t >= 0) {
+    a.do_accept = 1;
+    a.xi_cur = b.Xi + st.t * dP;
+    a.w_cur = b.W + st.t * dP;
+    a.wlo_cur = nullptr;
+    a.zq_part_cur = b.zq_part + (long)cu * b.nch * P;
+    a.lp_cur = b.lp + (long)cu * P;
+    a.zq_cur = b.zq + (long)cu * P;
+    a.lp_nxt = b.lp + (long)nx * P;
+    a.zq_nxt = b.zq + (long)nx * P;
+    a.u = st.U + ((long)t.g * st.n + st.t) * P;
+    a.la_out = b.la + (long)st.t * P;
+    a.acc_out = b.acc + (long)st.t * P;
+    a.win_col0 = (long)st.t * P;
+  }
+  const int tn = st.t + 1;
+  if (tn < st.n) {
+    // the proposal of step tn is judged with the scalars of parity tn & 1
+    a.do_propose = 1;
+    a.xi_nxt = b.Xi + tn * dP;
+    a.w_nxt = b.W + tn * dP;
+    a.wlo_nxt = nullptr;
+    a.zq_part_nxt = b.zq_part + (long)(tn & 1) * b.nch * P;
+  }
+  step_body<P32>(a, t.a, b.nch, t.b);
+}
+
+hipError_t g_step(const BProb* pr, const BTile* tl, int ntiles, const BStep& st, hipStream_t s) {
+  hipLaunchKernelGGL(gk_step, dim3(ntiles), dim3(256), 0, s, pr, tl, st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void gk_trigemm(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int ncols,
+                                                  double c) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  trigemm_tile<float, 32>(b.Llow, b.W, b.Xi, b.d, ncols, c, t.a, t.b);
+}
+
+hipError_t g_trigemm(const BProb* pr, const BTile* tl, int ntiles, int ncols, double c, hipStream_t s) {
+  hipLaunchKernelGGL(gk_trigemm, dim3(ntiles), dim3(256), 0, s, pr, tl, ncols, c);
+  return hipGetLastError();
+}
+
+// window scatter (one K split) and row sums
+__global__ __launch_bounds__(256) void gk_syrk(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int K) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  syrk_tile<float, 32>(b.win, b.d, K, K, t.a, 0, b.G);
+}
+__global__ __launch_bounds__(256) void gk_rowsum(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int K) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  rowsum_block<float, true>(b.win, b.d, K, K, t.a, 0, b.h);
+}
+
+hipError_t g_scatter(const BProb* pr, const BTile* syrk_tl, int nsyrk, const BTile* row_tl, int nrow, int K,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(gk_syrk, dim3(nsyrk), dim3(256), 0, s, pr, syrk_tl, K);
+  hipLaunchKernelGGL(gk_rowsum, dim3(nrow), dim3(256), 0, s, pr, row_tl, K);
+  return hipGetLastError();
+}
+
+// Element-wise phases over per-problem index spaces: tile (g, block) covers
+// elements [256 block, 256 block + 256) of problem g.
+__global__ __launch_bounds__(256) void gk_fold(const BProb* __restrict__ pr, const BTile* __restrict__ dd_tl,
+                                               const double* __restrict__ N, double K) {
+  const BTile t = dd_tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const long e = (long)t.a * 256 + threadIdx.x;
+  const double n0 = *N;
+  if (e < (long)b.d * b.d) fold_S_elem(b.G, b.h, b.xr, n0, K, b.S, b.d, e);
+}
+__global__ __launch_bounds__(256) void gk_fold_mean(const BProb* __restrict__ pr, const BTile* __restrict__ d_tl,
+                                                    const double* __restrict__ N, double K) {
+  const BTile t = d_tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int i = t.a * 256 + threadIdx.x;
+  if (i < b.d) fold_mean_elem(b.h, b.xr, *N, K, b.m, i);
+}
+
+hipError_t g_fold(const BProb* pr, const BTile* dd_tl, int ndd, const BTile* d_tl, int nd, const double* N, double K,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(gk_fold, dim3(ndd), dim3(256), 0, s, pr, dd_tl, N, K);
+  hipLaunchKernelGGL(gk_fold_mean, dim3(nd), dim3(256), 0, s, pr, d_tl, N, K);
+  return hipGetLastError();
+}
+
+// covariance (no jitter) into C; clears the problem's Cholesky status
+__global__ __launch_bounds__(256) void gk_cov(const BProb* __restrict__ pr, const BTile* __restrict__ dd_tl) {
+  const BTile t = dd_tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const long e = (long)t.a * 256 + threadIdx.x;
+  if (e < (long)b.d * b.d) cov_elem(b.S, b.m, 0.0, b.C, b.d, e);
+  if (t.a == 0 && threadIdx.x == 0) *b.info = 0;
+}
+
+hipError_t g_cov(const BProb* pr, const BTile* dd_tl, int ndd, hipStream_t s) {
+  hipLaunchKernelGGL(gk_cov, dim3(ndd), dim3(256), 0, s, pr, dd_tl);
+  return hipGetLastError();
+}
+
+// blocked Cholesky, block column jb of every problem with more than jb blocks
+__global__ __launch_bounds__(64) void gk_chol_diag(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
+  chol_diag_block(b.C, b.d, j0, jn, b.Linv + (long)jb * CHOL_NB * CHOL_NB, b.info);
+}
+__global__ __launch_bounds__(256) void gk_chol_panel(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
+  chol_panel_tile(b.C, b.d, j0, jn, b.Linv + (long)jb * CHOL_NB * CHOL_NB, t.a);
+}
+__global__ __launch_bounds__(256) void gk_chol_update(const BProb* __restrict__ pr, const BTile* __restrict__ tl,
+                                                      int jb) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
+  chol_update_tile(b.C, b.d, j0, jn, jb + 1, t.a);
+}
+
+hipError_t g_chol_step(const BProb* pr, const BTile* diag, int ndiag, const BTile* panel, int npanel,
+                       const BTile* upd, int nupd, int jb, hipStream_t s) {
+  if (ndiag) hipLaunchKernelGGL(gk_chol_diag, dim3(ndiag), dim3(64), 0, s, pr, diag, jb);
+  if (npanel) hipLaunchKernelGGL(gk_chol_panel, dim3(npanel), dim3(256), 0, s, pr, panel, jb);
+  if (nupd) hipLaunchKernelGGL(gk_chol_update, dim3(nupd), dim3(256), 0, s, pr, upd, jb);
+  return hipGetLastError();
+}
+
+// A factored problem (status 0) adopts C as its factor, rounded to FP32,
+// and its merged mean as the pivot; a failed one keeps both.
+__global__ __launch_bounds__(256) void gk_adopt(const BProb* __restrict__ pr, const BTile* __restrict__ dd_tl) {
+  const BTile t = dd_tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  if (*b.info != 0) return;
+  const long e = (long)t.a * 256 + threadIdx.x;
+  if (e < (long)b.d * b.d) {
+    b.L[e] = b.C[e];
+    round_factor_elem(P32, b.L, b.Llow, b.d, e);
+  }
+  if (e < b.d) b.xr[e] = b.m[e];
+}
+
+hipError_t g_adopt(const BProb* pr, const BTile* dd_tl, int ndd, hipStream_t s) {
+  hipLaunchKernelGGL(gk_adopt, dim3(ndd), dim3(256), 0, s, pr, dd_tl);
+  return hipGetLastError();
+}
+
+// whitening z = L^-1 (x - x_ref) of every problem
+__global__ __launch_bounds__(256) void gk_sub_ref(const BProb* __restrict__ pr, const BTile* __restrict__ dp_tl, int P) {
+  const BTile t = dp_tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const long e = (long)t.a * 256 + threadIdx.x;
+  if (e < (long)b.d * P) sub_ref_elem(b.X, b.xr, b.Z, b.d, e);
+}
+__global__ __launch_bounds__(64) void gk_tri_inv(const BProb* __restrict__ pr, const BTile* __restrict__ tl) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  tri_inv_block(b.L, b.d, b.Linv, t.a);
+}
+__global__ __launch_bounds__(256) void gk_trsm_diag(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb,
+                                                    int P) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
+  trsm_diag_tile(b.Linv + (long)jb * CHOL_NB * CHOL_NB, b.Z, b.d, P, j0, jn, t.a);
+}
+__global__ __launch_bounds__(256) void gk_trsm_update(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb,
+                                                      int P) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
+  trsm_update_tile(b.L, b.Z, b.d, P, j0, jn, t.a, t.b);
+}
+__global__ __launch_bounds__(256) void gk_colnorm(const BProb* __restrict__ pr, const BTile* __restrict__ tl) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  colnorm_block(b.Z, b.d, b.zq, t.a);  // parity 0 at a window boundary
+}
+
+hipError_t g_sub_ref(const BProb* pr, const BTile* dp_tl, int ndp, int P, hipStream_t s) {
+  hipLaunchKernelGGL(gk_sub_ref, dim3(ndp), dim3(256), 0, s, pr, dp_tl, P);
+  return hipGetLastError();
+}
+hipError_t g_tri_inv(const BProb* pr, const BTile* tl, int n, hipStream_t s) {
+  hipLaunchKernelGGL(gk_tri_inv, dim3(n), dim3(64), 0, s, pr, tl);
+  return hipGetLastError();
+}
+hipError_t g_trsm_step(const BProb* pr, const BTile* diag, int ndiag, const BTile* upd, int nupd, int jb, int P,
+                       hipStream_t s) {
+  if (ndiag) hipLaunchKernelGGL(gk_trsm_diag, dim3(ndiag), dim3(256), 0, s, pr, diag, jb, P);
+  if (nupd) hipLaunchKernelGGL(gk_trsm_update, dim3(nupd), dim3(256), 0, s, pr, upd, jb, P);
+  return hipGetLastError();
+}
+hipError_t g_colnorm(const BProb* pr, const BTile* tl, int n, hipStream_t s) {
+  hipLaunchKernelGGL(gk_colnorm, dim3(n), dim3(256), 0, s, pr, tl);
+  return hipGetLastError();
+}
+
+hipError_t g_rng(uint64_t seed, const long* win, long nW, long nU, int P, float* W, double* U, hipStream_t s) {
+  long nq = (nW + 3) / 4;
+  int blocks = (int)((nq + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(gk_normals, dim3(blocks), dim3(256), 0, s, (uint32_t)seed, (uint32_t)(seed >> 32), win, nW, nW, W);
+  hipLaunchKernelGGL(gk_uniforms, dim3((unsigned)((nU + 255) / 256)), dim3(256), 0, s, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), win, nU, P, U);
+  return hipGetLastError();
+}
+
+hipError_t g_bump(long* win, double* N, double K, hipStream_t s) {
+  hipLaunchKernelGGL(gk_bump, dim3(1), dim3(64), 0, s, win, N, K);
   return hipGetLastError();
 }
 

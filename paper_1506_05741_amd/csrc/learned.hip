@@ -21,11 +21,12 @@ namespace dk {
 // ============================================================================
 DEV float softplus_f(float t) { return fmaxf(t, 0.f) + log1pf(expf(-fabsf(t))); }
 
+template <int BN>
 __global__ __launch_bounds__(512) void k_tgt_logreg(const float* __restrict__ A, const float* __restrict__ y, int n_obs,
                                                     const float* __restrict__ V, int d, int P,
                                                     const int* __restrict__ nact_ptr, int nrb, int nct,
                                                     double* __restrict__ part) {
-  constexpr int BM = 64, BN = 64, BK = 32, KG = 2;
+  constexpr int BM = 64, BK = 32, KG = 2;
   __shared__ float lds[KG * e_lds_elems<float, BM, BN, BK>()];
   __shared__ double red[2][BN];
   const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
@@ -68,12 +69,20 @@ __global__ __launch_bounds__(512) void k_tgt_logreg(const float* __restrict__ A,
 
 int logreg_row_blocks(long n_obs) { return (int)((n_obs + 63) / 64); }
 
+// Column tiles of 64 chains, or of 32 when the active count varies (delayed
+// acceptance): tiles past the survivors then exit, at a finer granularity.
 hipError_t tgt_logreg(const float* A, const float* y, long n_obs, const float* V, int d, int P, const int* nact,
                       double* part, hipStream_t s) {
-  const int nrb = logreg_row_blocks(n_obs), nct = cdiv(P, 64);
-  const int groups = (nrb + 7) / 8;
-  hipLaunchKernelGGL(k_tgt_logreg, dim3(groups * 8 * nct), dim3(512), 0, s, A, y, (int)n_obs, V, d, P, nact, nrb, nct,
-                     part);
+  const int nrb = logreg_row_blocks(n_obs), groups = (nrb + 7) / 8;
+  if (nact) {
+    const int nct = cdiv(P, 32);
+    hipLaunchKernelGGL(k_tgt_logreg<32>, dim3(groups * 8 * nct), dim3(512), 0, s, A, y, (int)n_obs, V, d, P, nact,
+                       nrb, nct, part);
+  } else {
+    const int nct = cdiv(P, 64);
+    hipLaunchKernelGGL(k_tgt_logreg<64>, dim3(groups * 8 * nct), dim3(512), 0, s, A, y, (int)n_obs, V, d, P, nact,
+                       nrb, nct, part);
+  }
   return hipGetLastError();
 }
 
@@ -416,46 +425,66 @@ hipError_t mlp_train_step(const MlpBufs& b, long n, int nb, long tau, uint64_t s
 }
 
 // ============================================================================
-// Delayed acceptance: stage 1 with the surrogate, compaction of survivors.
-// One workgroup; decisions in chain order, so slots are deterministic.
+// Delayed acceptance, stage 1 (one workgroup of 16 waves):
+//   s_new[p] = out_std * (w3 . h2[:, p] + b3) + out_mean       (network output)
+//   log a1   = (s_new - s_cur) + [plain form only] (|z'|^2 - |z|^2) / (2 alpha^2)
+// In the residual form the surrogate is r(x) - |z(x)|^2 / (2 alpha^2): its
+// Gaussian part cancels the proposal's own correction, so stage 1 compares
+// the network outputs alone.  Survivors get consecutive slots in chain
+// order (wave ballots + prefix counts), so packing is deterministic.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_da_stage1(int P, int nch, const double* __restrict__ s_new,
-                                                   const double* __restrict__ s_cur,
-                                                   const double* __restrict__ zq_part, const double* __restrict__ zq,
-                                                   const double* __restrict__ u1, double inv2a2,
-                                                   uint8_t* __restrict__ pass, int* __restrict__ slot,
-                                                   int* __restrict__ idx, int* __restrict__ nsurv,
-                                                   int* __restrict__ npass) {
-  __shared__ int scan[256];
+__global__ __launch_bounds__(1024) void k_da_screen(const float* __restrict__ w3, const float* __restrict__ b3,
+                                                    const float* __restrict__ h2, int H,
+                                                    const float* __restrict__ stats, int P, int nch,
+                                                    const double* __restrict__ s_cur,
+                                                    const double* __restrict__ zq_part,
+                                                    const double* __restrict__ zq, const double* __restrict__ u1,
+                                                    double inv2a2, int resid, double* __restrict__ s_new,
+                                                    uint8_t* __restrict__ pass, int* __restrict__ slot,
+                                                    int* __restrict__ idx, int* __restrict__ nsurv,
+                                                    int* __restrict__ npass) {
+  __shared__ int wt[16];
   __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double om = (double)stats[0], os = (double)stats[1];
+  for (int q = w; q < P; q += 16) {
+    float acc = 0.f;
+    for (int o = lane; o < H; o += 64) acc = fmaf(w3[o], h2[o + (long)q * H], acc);
+    acc = wave_sum_f32(acc);
+    if (lane == 0) s_new[q] = (double)(acc + b3[0]) * os + om;
+  }
   if (threadIdx.x == 0) base = 0;
   __syncthreads();
-  for (int p0 = 0; p0 < P; p0 += 256) {
+  for (int p0 = 0; p0 < P; p0 += 1024) {
     const int p = p0 + threadIdx.x;
     int ok = 0;
     if (p < P) {
-      double zs = 0.0;
-      for (int c = 0; c < nch; ++c) zs += zq_part[(long)c * P + p];
-      const double la1 = (s_new[p] - s_cur[p]) + (zs - zq[p]) * inv2a2;
+      double la1 = s_new[p] - s_cur[p];
+      if (!resid) {
+        double zs = 0.0;
+        for (int c = 0; c < nch; ++c) zs += zq_part[(long)c * P + p];
+        la1 += (zs - zq[p]) * inv2a2;
+      }
       ok = log(u1[p]) < la1 ? 1 : 0;
       pass[p] = (uint8_t)ok;
       npass[p] += ok;
     }
-    scan[threadIdx.x] = ok;
+    const unsigned long long m = __ballot(ok);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wt[w] = __popcll(m);
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan
-      const int v = threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
-      __syncthreads();
-      scan[threadIdx.x] += v;
-      __syncthreads();
-    }
+    int off = base;
+    for (int v = 0; v < w; ++v) off += wt[v];
     if (p < P) {
-      const int sl = base + scan[threadIdx.x] - ok;
-      slot[p] = ok ? sl : -1;
-      if (ok) idx[sl] = p;
+      slot[p] = ok ? off + below : -1;
+      if (ok) idx[off + below] = p;
     }
     __syncthreads();
-    if (threadIdx.x == 0) base += scan[255];
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int v = 0; v < 16; ++v) t += wt[v];
+      base += t;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) *nsurv = base;
@@ -471,14 +500,40 @@ __global__ __launch_bounds__(256) void k_da_gather(const float* __restrict__ V, 
   Vs[i + (long)j * d] = V[i + (long)idx[j] * d];
 }
 
-hipError_t da_stage1(int P, int nch, const double* s_new, const double* s_cur, const double* zq_part, const double* zq,
-                     const double* u1, double inv2a2, uint8_t* pass, int* slot, int* idx, int* nsurv, int* npass,
-                     const float* V, int d, float* Vs, hipStream_t s) {
-  hipLaunchKernelGGL(k_da_stage1, dim3(1), dim3(256), 0, s, P, nch, s_new, s_cur, zq_part, zq, u1, inv2a2, pass, slot,
-                     idx, nsurv, npass);
-  const long tot = (long)d * P;
+hipError_t da_screen(const MlpBufs& b, const float* V, int d, int P, int nch, const double* s_cur,
+                     const double* zq_part, const double* zq, const double* u1, double inv2a2, int resid,
+                     double* s_new, uint8_t* pass, int* slot, int* idx, int* nsurv, int* npass, float* Vs,
+                     hipStream_t s) {
+  const long tot = (long)b.D * P;
+  hipLaunchKernelGGL(k_mlp_standardize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const double*)nullptr,
+                     V, (const float*)b.in_mean, (const float*)b.in_scale, b.D, (long)P, b.xb);
+  const int H = b.H;
+  const float* W1 = b.eff;
+  const float* b1 = W1 + (long)H * b.D;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + (long)H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H;
+  hipLaunchKernelGGL((k_mlp_gemm<true, true, 1>), g2(H, P), dim3(256), 0, s, W1, b.D, H, (const float*)b.xb, b.D, P,
+                     b.D, b.a1, H, b1, (const float*)nullptr, b.h1);
+  hipLaunchKernelGGL((k_mlp_gemm<true, true, 1>), g2(H, P), dim3(256), 0, s, W2, H, H, (const float*)b.h1, H, P, H,
+                     b.a2, H, b2, (const float*)nullptr, b.h2);
+  hipLaunchKernelGGL(k_da_screen, dim3(1), dim3(1024), 0, s, W3, b3, (const float*)b.h2, H, (const float*)b.stats, P,
+                     nch, s_cur, zq_part, zq, u1, inv2a2, resid, s_new, pass, slot, idx, nsurv, npass);
   hipLaunchKernelGGL(k_da_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, (const int*)idx,
                      (const int*)nsurv, d, P, Vs);
+  return hipGetLastError();
+}
+
+// t[k] = lp[k] + c zq[k]  (residual-form training targets)
+__global__ __launch_bounds__(256) void k_axpy_f64(const double* __restrict__ lp, const double* __restrict__ zq,
+                                                  double c, long n, double* __restrict__ t) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) t[e] = __fma_rn(c, zq[e], lp[e]);
+}
+
+hipError_t axpy_f64(const double* lp, const double* zq, double c, long n, double* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lp, zq, c, n, t);
   return hipGetLastError();
 }
 

@@ -29,7 +29,11 @@ EXPORTED = (
     "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
+    "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
+    "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_field_bytes",
+    "diam_batch_get", "diam_batch_get_stats", "diam_batch_destroy",
 )
+BATCH_TILES = ("32x2", "64x1", "64x2", "128x2", "32x4")   # target tile rows x k-groups
 STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten", "surrogate", "train")
 
 
@@ -46,6 +50,14 @@ class Target(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_void_p),
                 ("R", ctypes.c_void_p), ("A", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_obs", ctypes.c_int64),
                 ("prior_var", ctypes.c_double)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("G", ctypes.c_int32), ("P", ctypes.c_int32), ("n_lag", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("jitter0", ctypes.c_double), ("jitter_tries", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
 
 
 class Stats(ctypes.Structure):
@@ -91,6 +103,18 @@ def load(path: str = LIB_PATH):
                                  ctypes.c_int),
         "diam_surrogate_eval": ([vp, vp, i32, vp], ctypes.c_int),
         "diam_set_delayed_acceptance": ([vp, i32], ctypes.c_int),
+        "diam_batch_workspace_bytes": ([ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "diam_batch_init": ([ctypes.POINTER(vp), ctypes.POINTER(BatchConfig), vp, vp, vp, vp, sz, vp, vp],
+                            ctypes.c_int),
+        "diam_batch_seed_moments": ([vp, vp, vp, dbl, vp], ctypes.c_int),
+        "diam_batch_window": ([vp, vp], ctypes.c_int),
+        "diam_batch_set_tiles": ([vp, i32], ctypes.c_int),
+        "diam_batch_autotune": ([vp, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
+        "diam_batch_set_graph": ([vp, i32], ctypes.c_int),
+        "diam_batch_field_bytes": ([vp, i32, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "diam_batch_get": ([vp, i32, i32, vp, sz], ctypes.c_int),
+        "diam_batch_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
+        "diam_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -111,9 +135,10 @@ def _ptr(t):
 
 
 def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13,
-                surrogate=False, train_max=0):
+                surrogate=0, train_max=0):
+    """surrogate: 0 none, 1 (or True) network surrogate, 2 residual form."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, 1 if surrogate else 0, int(train_max))
+    return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, int(surrogate), int(train_max))
 
 
 def gauss_target(mu, R):
@@ -275,6 +300,102 @@ class Sampler:
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.diam_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(ts, ctype=ctypes.c_void_p):
+    return (ctype * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def batch_workspace_bytes(cfg: BatchConfig, dims) -> int:
+    lib = load()
+    d = (ctypes.c_int32 * len(dims))(*[int(x) for x in dims])
+    n = ctypes.c_size_t()
+    _check(lib.diam_batch_workspace_bytes(ctypes.byref(cfg), d, ctypes.byref(n)))
+    return n.value
+
+
+def make_batch_config(G, P, n_lag, beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13):
+    return BatchConfig(G, P, n_lag, FP32, beta, alpha, seed, jitter0, jitter_tries, 0)
+
+
+class Batch:
+    """G independent Gaussian problems (mu[g] f64 (d_g,), R[g] f32 (d_g, d_g),
+    x0[g] f64 (P, d_g) i.e. d_g x P column-major), P chains each."""
+
+    def __init__(self, cfg: BatchConfig, mus, Rs, x0s, stream=None):
+        import torch
+        lib = load()
+        self.torch, self.lib, self.cfg = torch, lib, cfg
+        self.G, self.P, self.n = cfg.G, cfg.P, cfg.n_lag
+        self.dims = [int(m.numel()) for m in mus]
+        assert len(self.dims) == cfg.G == len(Rs) == len(x0s)
+        for m, R, x, d in zip(mus, Rs, x0s, self.dims):
+            assert m.dtype == torch.float64 and m.is_cuda and m.is_contiguous()
+            assert R.dtype == torch.float32 and R.is_cuda and R.is_contiguous() and R.shape == (d, d)
+            assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == d * cfg.P
+        self._keep = [list(mus), list(Rs), list(x0s)]
+        dims = (ctypes.c_int32 * cfg.G)(*self.dims)
+        nbytes = batch_workspace_bytes(cfg, self.dims)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=x0s[0].device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(x0s[0].device)
+        ctx = ctypes.c_void_p()
+        _check(lib.diam_batch_init(ctypes.byref(ctx), ctypes.byref(cfg), dims, _ptr_array(mus), _ptr_array(Rs),
+                                   _ptr(self.ws), nbytes, _ptr_array(x0s), ctypes.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    def seed_moments(self, S0s, m0s, N0):
+        self._keep.append((list(S0s), list(m0s)))
+        j = (ctypes.c_int32 * self.G)()
+        st = self.lib.diam_batch_seed_moments(self.ctx, _ptr_array(S0s), _ptr_array(m0s), float(N0), j)
+        if st not in (OK, E_NOT_PD):
+            _check(st)
+        return st, list(j)
+
+    def window(self):
+        j = (ctypes.c_int32 * self.G)()
+        st = self.lib.diam_batch_window(self.ctx, j)
+        if st not in (OK, E_NOT_PD):
+            _check(st)
+        return st, list(j)
+
+    def set_tiles(self, choice):
+        _check(self.lib.diam_batch_set_tiles(self.ctx, int(choice)))
+
+    def set_graph(self, on=True):
+        _check(self.lib.diam_batch_set_graph(self.ctx, 1 if on else 0))
+
+    def autotune(self, reps=20):
+        c = ctypes.c_int32()
+        us = (ctypes.c_double * len(BATCH_TILES))()
+        _check(self.lib.diam_batch_autotune(self.ctx, int(reps), ctypes.byref(c), us))
+        return c.value, dict(zip(BATCH_TILES, list(us)))
+
+    def get(self, g, field):
+        torch = self.torch
+        n = ctypes.c_size_t()
+        _check(self.lib.diam_batch_field_bytes(self.ctx, int(g), field, ctypes.byref(n)))
+        out = torch.empty(n.value, dtype=torch.uint8, device=self.ws.device)
+        _check(self.lib.diam_batch_get(self.ctx, int(g), field, _ptr(out), n.value))
+        return out
+
+    def get_f64(self, g, field, shape):
+        return self.get(g, field).view(self.torch.float64).reshape(shape)
+
+    def stats(self):
+        s = Stats()
+        _check(self.lib.diam_batch_get_stats(self.ctx, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.diam_batch_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

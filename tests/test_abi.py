@@ -128,3 +128,36 @@ def test_philox_reference_matches_published_kat():
         v = [int(x, 16) for x in r]
         out = philox4x32_10(*v[:6])
         assert [int(o) for o in out] == v[6:]
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n_lag=7), "n_lag must be even"),
+    (dict(P=64, n_lag=128), "P * n_lag"),
+    (dict(G=0), "G must"),
+    (dict(beta=0.0), "beta"),
+])
+def test_bad_batch_config_is_rejected(kw, msg):
+    base = dict(G=3, P=32, n_lag=8)
+    base.update(kw)
+    G = base.pop("G")
+    cfg = diam.make_batch_config(G, **base)
+    with pytest.raises(diam.DiamError) as e:
+        diam.batch_workspace_bytes(cfg, [16] * max(G, 1))
+    assert e.value.status == diam.E_ARG and msg in str(e.value)
+
+
+def test_batch_rejects_other_precisions_and_bad_dims():
+    cfg = diam.make_batch_config(2, 32, 8)
+    cfg.precision = diam.FP64
+    with pytest.raises(diam.DiamError, match="DIAM_FP32 only"):
+        diam.batch_workspace_bytes(cfg, [16, 16])
+    with pytest.raises(diam.DiamError, match="outside"):
+        diam.batch_workspace_bytes(diam.make_batch_config(2, 32, 8), [16, 0])
+
+
+def test_batch_workspace_grows_with_the_problems():
+    cfg = diam.make_batch_config(2, 32, 8)
+    a = diam.batch_workspace_bytes(cfg, [64, 64])
+    b = diam.batch_workspace_bytes(cfg, [64, 128])
+    # per problem: five d x d FP64 matrices (S, L, C, scatter) and FP32 factor dominate
+    assert b - a > (128 * 128 - 64 * 64) * (4 * 8 + 4)
