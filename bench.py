@@ -224,6 +224,86 @@ def learned_experiment(args, torch, diam):
     return out
 
 
+def batch_experiment(args, torch, diam):
+    """Batched form: 48 independent Gaussian targets, d log-uniform in
+    [128, 3072] (lambda_i = i^-2, seed 1000 + g), 32 chains each, n_lag = 128,
+    FP32 with FP64 Cholesky, warm start.  One benchmark window = n_lag steps
+    of all 1536 chains + merge + refactorisation of all 48 problems (grouped
+    launches, graph-captured window), against the same windows run problem by
+    problem through the single-problem API."""
+    from paper_1506_05741_amd import synth
+    dev = torch.device("cuda:0")
+    P, nl = 32, 128
+    dims = [int(x) for x in synth.batch_dims(48)]
+    t0 = time.perf_counter()
+    ts = [synth.gaussian_target(d, 1000 + g) for g, d in enumerate(dims)]
+    x0 = [synth.gaussian_exact_draws(t, P, 2000 + g) for g, t in enumerate(ts)]
+    log(f"48 batch targets built in {time.perf_counter() - t0:.1f} s")
+    mus = [torch.as_tensor(t.mu, device=dev) for t in ts]
+    Rs = [torch.as_tensor(t.R, dtype=torch.float32, device=dev).contiguous() for t in ts]
+    xs = [torch.as_tensor(np.ascontiguousarray(x.T), device=dev) for x in x0]
+    S0 = [torch.as_tensor(t.Sigma + np.outer(t.mu, t.mu), device=dev) for t in ts]
+    m0 = [torch.as_tensor(t.mu, device=dev) for t in ts]
+    N0 = 10.0 * P * nl
+    cfg = diam.make_batch_config(48, P, nl, beta=0.3, seed=77)
+    b = diam.Batch(cfg, mus, Rs, xs)
+    assert b.seed_moments(S0, m0, N0)[0] == diam.OK
+    choice, us = b.autotune(reps=20)
+    for _ in range(1):
+        assert b.window()[0] == diam.OK
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.batch_windows):
+        st, _ = b.window()
+        assert st == diam.OK
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t1
+    nacc = sum(int(b.get(g, diam.F_NACC).view(torch.int32).sum()) for g in range(48))
+    acc = nacc / (48 * P * nl * (args.batch_windows + 1))
+    b.close()
+    chain_steps = 48 * P * nl * args.batch_windows
+    flops = 2.0 * sum(d * d for d in dims) * P
+    out = {"workload": "48 Gaussian targets, d log-uniform in [128, 3072] (sum d = %d), 32 chains each, "
+                       "n_lag=128, beta=0.3, fp32 with fp64 Cholesky, warm start" % sum(dims),
+           "windows": args.batch_windows, "ms_per_window": 1e3 * T / args.batch_windows,
+           "chain_steps_per_s": chain_steps / T, "acceptance": acc,
+           "autotune_us_per_target_launch": us, "tile_choice": diam.BATCH_TILES[choice],
+           "target_roofline": {"kernel": "gk_tgt (grouped fp32 MFMA target contraction)", "bound": "mfma",
+                               "achieved": flops / (us[diam.BATCH_TILES[choice]] * 1e-6) / 1e12,
+                               "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+                               "frac": flops / (us[diam.BATCH_TILES[choice]] * 1e-6) / PEAK["fp32"]}}
+    # the same windows problem by problem through the single-problem API
+    singles = []
+    for g, t in enumerate(ts):
+        c = diam.make_config(t.d, P, nl, "fp32", beta=0.3, seed=77 + g)
+        s = diam.Sampler(c, mus[g], Rs[g], xs[g])
+        assert s.seed_moments(S0[g], m0[g], N0)[0] == diam.OK
+        singles.append(s)
+
+    def seq_window():
+        for s in singles:
+            s.step_batch(nl)
+            s.merge_moments()
+            assert s.update_proposal()[0] == diam.OK
+
+    seq_window()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nseq = max(1, args.batch_windows // 2)
+    for _ in range(nseq):
+        seq_window()
+    torch.cuda.synchronize()
+    Ts = time.perf_counter() - t1
+    for s in singles:
+        s.close()
+    out["sequential"] = {"windows": nseq, "ms_per_window": 1e3 * Ts / nseq,
+                         "chain_steps_per_s": 48 * P * nl * nseq / Ts}
+    out["speedup_vs_sequential"] = out["chain_steps_per_s"] / out["sequential"]["chain_steps_per_s"]
+    log(f"batch: {out['chain_steps_per_s']:.4g} chain-steps/s ({out['ms_per_window']:.2f} ms/window, tiles "
+        f"{out['tile_choice']}), sequential {out['sequential']['chain_steps_per_s']:.4g}")
+    return out
+
+
 def cpu_baseline(tgt, args):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: a few steps of all P chains, one merge of those steps and one
@@ -285,6 +365,9 @@ def main():
     ap.add_argument("--learned-windows", dest="learned_windows", type=int, default=4)
     ap.add_argument("--learned-precision", dest="learned_precision", default="fp32", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--train-steps", dest="train_steps", type=int, default=3000)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form experiment")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-form experiment")
+    ap.add_argument("--batch-windows", dest="batch_windows", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -305,6 +388,9 @@ def main():
         log(f"copy calibration: 3 copies of {n * 4} bytes")
         del src, dst
 
+    if args.batch_only:
+        print(json.dumps({"batch": batch_experiment(args, torch, diam)}), flush=True)
+        return
     if args.learned_only:
         print(json.dumps({"learned": learned_experiment(args, torch, diam)}), flush=True)
         return
@@ -371,6 +457,8 @@ def main():
                                   "ess": res["ess_per_s"] / ref["ess_per_s"]}
     if not args.no_learned:
         out["learned"] = learned_experiment(args, torch, diam)
+    if not args.no_batch:
+        out["batch"] = batch_experiment(args, torch, diam)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(tgt, args)

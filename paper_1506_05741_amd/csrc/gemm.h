@@ -443,4 +443,322 @@ DEV void b_gemm_seg(BFrag<BM, BN>& f, const u16* __restrict__ A, long dA, long l
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide BF16 engine: WGM x WGN wavefronts (64 * WGM * WGN threads) over a
+// BM x BN tile, each wave holding a BM/WGM x BN/WGN block of 16 x 16
+// accumulators; K is staged through LDS in 64-deep slices (two 16x16x32
+// MFMA k-steps per slice) with double buffering, the next slice's global
+// loads in flight while the current one is multiplied.  Large wave blocks
+// cut LDS reads per MFMA (a fragment read feeds FN or FM MFMAs).
+// Segmented K as b_gemm_seg (hi/lo operand pairs).
+// ---------------------------------------------------------------------------
+constexpr int WBK = 64;
+constexpr int WLD = WBK + 8;  // LDS row stride (bf16): 144 bytes
+
+template <int BM, int BN, int WGM, int WGN>
+struct WFrag {
+  static constexpr int NTH = 64 * WGM * WGN;
+  static constexpr int FM = BM / (16 * WGM), FN = BN / (16 * WGN);
+  f4_t c[FM][FN];
+  DEVM void zero() {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[a][b][r] = 0.f;
+  }
+};
+
+template <int ROWS, int NTH>
+struct WStage {
+  static constexpr int PER = ROWS * WBK / 8 / NTH;  // 16-byte chunks per thread
+  static_assert(PER >= 1, "tile too small for the wide engine");
+  uint4 v[PER];
+};
+
+template <int ROWS, int NTH>
+DEV void w_load(WStage<ROWS, NTH>& s, const u16* __restrict__ p, long ld, int nrows, int r0, int k0, int kend,
+                bool vec_ok) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < WStage<ROWS, NTH>::PER; ++e) {
+    const int idx = t + e * NTH;
+    const int r = idx >> 3, k = (idx & 7) * 8;
+    const int gr = r0 + r, gk = k0 + k;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (gr < nrows) {
+      const u16* q = p + (long)gr * ld + gk;
+      if (vec_ok && gk + 8 <= kend) {
+        val = *(const uint4*)q;
+      } else {
+        u16 h[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) h[x] = (gk + x < kend) ? q[x] : (u16)0;
+        val.x = h[0] | ((uint32_t)h[1] << 16);
+        val.y = h[2] | ((uint32_t)h[3] << 16);
+        val.z = h[4] | ((uint32_t)h[5] << 16);
+        val.w = h[6] | ((uint32_t)h[7] << 16);
+      }
+    }
+    s.v[e] = val;
+  }
+}
+
+template <int ROWS, int NTH>
+DEV void w_store(const WStage<ROWS, NTH>& s, u16* lds) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < WStage<ROWS, NTH>::PER; ++e) {
+    const int idx = t + e * NTH;
+    const int r = idx >> 3, k = (idx & 7) * 8;
+    *(uint4*)(lds + r * WLD + k) = s.v[e];
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN>
+DEV void w_compute(WFrag<BM, BN, WGM, WGN>& f, const u16* As, const u16* Bs) {
+  typedef WFrag<BM, BN, WGM, WGN> F;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w % WGM, wn = w / WGM;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+#pragma unroll
+  for (int ks = 0; ks < WBK; ks += 32) {
+    bf8_t a[F::FM], b[F::FN];
+#pragma unroll
+    for (int m = 0; m < F::FM; ++m) a[m] = *(const bf8_t*)(As + (wm * (BM / WGM) + m * 16 + lr) * WLD + ks + lk);
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n) b[n] = *(const bf8_t*)(Bs + (wn * (BN / WGN) + n * 16 + lr) * WLD + ks + lk);
+#pragma unroll
+    for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+      for (int n = 0; n < F::FN; ++n) f.c[m][n] = mfma_bf16(a[m], b[n], f.c[m][n]);
+  }
+}
+
+template <int BM, int BN>
+constexpr int w_lds_elems() { return 2 * (BM + BN) * WLD; }
+
+// Coordinates of accumulator (m, n, r) of this lane inside the tile.
+template <int BM, int BN, int WGM, int WGN>
+DEV void w_coords(int m, int n, int r, int& ti, int& tj) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w % WGM, wn = w / WGM;
+  ti = wm * (BM / WGM) + m * 16 + 4 * (lane >> 4) + r;
+  tj = wn * (BN / WGN) + n * 16 + (lane & 15);
+}
+
+// K range [kbeg, kend) per segment (kbeg a multiple of 8 for vector loads).
+template <int BM, int BN, int WGM, int WGN>
+DEV void w_gemm_seg(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, long lda, int M,
+                    const u16* __restrict__ B, long dB, long ldb, int N, bool vec, int i0, int j0, int kbeg, int kend,
+                    int nseg, u16* lds) {
+  constexpr int NTH = 64 * WGM * WGN;
+  u16* const A0 = lds;
+  u16* const A1 = lds + BM * WLD;
+  u16* const B0 = lds + 2 * BM * WLD;
+  u16* const B1 = lds + 2 * BM * WLD + BN * WLD;
+  WStage<BM, NTH> sa;
+  WStage<BN, NTH> sb;
+  const int nks = (kend - kbeg + WBK - 1) / WBK;
+  const int nk = nks * nseg;
+  if (nks <= 0) return;
+  auto load = [&](int kt) {
+    const int sgm = kt / nks, k0 = kbeg + (kt - sgm * nks) * WBK;
+    w_load<BM, NTH>(sa, A + (sgm & 1) * dA, lda, M, i0, k0, kend, vec);
+    w_load<BN, NTH>(sb, B + (sgm >> 1) * dB, ldb, N, j0, k0, kend, vec);
+  };
+  load(0);
+  w_store<BM, NTH>(sa, A0);
+  w_store<BN, NTH>(sb, B0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    {
+      const bool more = kt + 1 < nk;
+      if (more) load(kt + 1);
+      w_compute<BM, BN, WGM, WGN>(f, A0, B0);
+      if (more) {
+        w_store<BM, NTH>(sa, A1);
+        w_store<BN, NTH>(sb, B1);
+      }
+      __syncthreads();
+      if (!more) break;
+    }
+    {
+      const bool more = kt + 2 < nk;
+      if (more) load(kt + 2);
+      w_compute<BM, BN, WGM, WGN>(f, A1, B1);
+      if (more) {
+        w_store<BM, NTH>(sa, A0);
+        w_store<BN, NTH>(sb, B0);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hi/lo BF16 engine with direct-to-LDS loads.  C = (A_hi + A_lo)(B_hi + B_lo)
+// over K: each 32-deep K slice of all four operand parts is copied from
+// global memory straight into an LDS ring of ST stages by
+// global_load_lds_dwordx4 (no staging registers; ST - 1 slices in flight),
+// and every fragment read from LDS feeds two of the four products.  Each
+// wave-wide copy fills 1 KB of LDS = 16 rows x 4 chunks of 16 bytes; chunk c
+// of row r sits at position c ^ ((r >> 2) & 3), which spreads the 16 rows a
+// quarter-wavefront reads over distinct banks.  Unguarded: the caller
+// guarantees that all rows and the whole K range lie inside the operands
+// (K a multiple of 32) and that rows start on 16-byte boundaries.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+constexpr int HBK = 32;
+
+DEV int hswz(int r) { return (r >> 2) & 3; }
+
+DEV void h_copy_block(const u16* __restrict__ p, long ld, int r0, int k0, u16* lds_block) {
+  const int lane = threadIdx.x & 63;
+  const int r = r0 + (lane >> 2);
+  const int c = (lane & 3) ^ hswz(r);
+  __builtin_amdgcn_global_load_lds((const void*)(p + (long)r * ld + k0 + c * 8), (lds_ptr_t)lds_block, 16, 0, 0);
+}
+
+template <int BM, int BN, int ST>
+constexpr int h_lds_elems() { return ST * 2 * (BM + BN) * HBK; }
+
+template <int BM, int BN, int WGM, int WGN, int ST>
+DEV void h_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, long lda, const u16* __restrict__ B,
+                long dB, long ldb, int i0, int j0, int kend, u16* lds) {
+  typedef WFrag<BM, BN, WGM, WGN> F;
+  constexpr int NW = WGM * WGN;
+  constexpr int SA = BM * HBK, SB = BN * HBK, SS = 2 * (SA + SB);
+  constexpr int BLK_A = BM / 16, BLK_B = BN / 16, NBLK = 2 * (BLK_A + BLK_B);
+  static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
+  constexpr int LPW = NBLK / NW;
+  const int nk = kend / HBK;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  auto issue = [&](int kt) {
+    const int k0 = kt * HBK;
+    u16* st = lds + (kt % ST) * SS;
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+      const int blk = w * LPW + q;
+      if (blk < 2 * BLK_A) {
+        const int h = blk / BLK_A, b = blk % BLK_A;
+        h_copy_block(A + h * dA, lda, i0 + b * 16, k0, st + h * SA + b * 512);
+      } else {
+        const int bb = blk - 2 * BLK_A, h = bb / BLK_B, b = bb % BLK_B;
+        h_copy_block(B + h * dB, ldb, j0 + b * 16, k0, st + 2 * SA + h * SB + b * 512);
+      }
+    }
+  };
+  const int wm = w % WGM, wn = w / WGM;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's copies of slice kt are done when at most the later
+    // slices' copies are outstanding; the barrier then covers all waves
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_barrier" ::: "memory");
+    // the ring slot refilled here was last read before this barrier
+    if (kt + ST - 1 < nk) issue(kt + ST - 1);
+    const u16* st = lds + (kt % ST) * SS;
+    bf8_t ah[F::FM], al[F::FM], bh[F::FN], bl[F::FN];
+#pragma unroll
+    for (int m = 0; m < F::FM; ++m) {
+      const int r = wm * (BM / WGM) + m * 16 + lr;
+      const int o = r * HBK + ((lk ^ hswz(r)) * 8);
+      ah[m] = *(const bf8_t*)(st + o);
+      al[m] = *(const bf8_t*)(st + SA + o);
+    }
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n) {
+      const int r = wn * (BN / WGN) + n * 16 + lr;
+      const int o = r * HBK + ((lk ^ hswz(r)) * 8);
+      bh[n] = *(const bf8_t*)(st + 2 * SA + o);
+      bl[n] = *(const bf8_t*)(st + 2 * SA + SB + o);
+    }
+#pragma unroll
+    for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+      for (int n = 0; n < F::FN; ++n) {
+        f.c[m][n] = mfma_bf16(ah[m], bh[n], f.c[m][n]);
+        f.c[m][n] = mfma_bf16(al[m], bh[n], f.c[m][n]);
+        f.c[m][n] = mfma_bf16(ah[m], bl[n], f.c[m][n]);
+        f.c[m][n] = mfma_bf16(al[m], bl[n], f.c[m][n]);
+      }
+  }
+}
+
+// Plain BF16 engine with direct-to-LDS loads (one part per operand): 64-deep
+// K slices, chunk c of row r at position c ^ ((r >> 1) & 7) (8 chunks per
+// row), ST-stage ring.  K range [kbeg, kend), both multiples of 64;
+// unguarded like h_gemm.
+constexpr int PBK = 64;
+
+DEV int pswz(int r) { return (r >> 1) & 7; }
+
+DEV void p_copy_block(const u16* __restrict__ p, long ld, int r0, int k0, u16* lds_block) {
+  const int lane = threadIdx.x & 63;
+  const int r = r0 + (lane >> 3);
+  const int c = (lane & 7) ^ pswz(r);
+  __builtin_amdgcn_global_load_lds((const void*)(p + (long)r * ld + k0 + c * 8), (lds_ptr_t)lds_block, 16, 0, 0);
+}
+
+template <int BM, int BN, int ST>
+constexpr int p_lds_elems() { return ST * (BM + BN) * PBK; }
+
+template <int BM, int BN, int WGM, int WGN, int ST>
+DEV void p_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long lda, const u16* __restrict__ B, long ldb,
+                int i0, int j0, int kbeg, int kend, u16* lds) {
+  typedef WFrag<BM, BN, WGM, WGN> F;
+  constexpr int NW = WGM * WGN;
+  constexpr int SA = BM * PBK, SS = (BM + BN) * PBK;
+  constexpr int BLK_A = BM / 8, BLK_B = BN / 8, NBLK = BLK_A + BLK_B;
+  static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
+  constexpr int LPW = NBLK / NW;
+  const int nk = (kend - kbeg) / PBK;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  auto issue = [&](int kt) {
+    const int k0 = kbeg + kt * PBK;
+    u16* st = lds + (kt % ST) * SS;
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+      const int blk = w * LPW + q;
+      if (blk < BLK_A) p_copy_block(A, lda, i0 + blk * 8, k0, st + blk * 512);
+      else p_copy_block(B, ldb, j0 + (blk - BLK_A) * 8, k0, st + SA + (blk - BLK_A) * 512);
+    }
+  };
+  const int wm = w % WGM, wn = w / WGM;
+  const int lr = lane & 15, lk = lane >> 4;
+  // the ring may still be read by other waves from a previous call
+  asm volatile("s_barrier" ::: "memory");
+  for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + ST - 1 < nk) issue(kt + ST - 1);
+    const u16* As = lds + (kt % ST) * SS;
+    const u16* Bs = As + SA;
+#pragma unroll
+    for (int ks = 0; ks < PBK / 32; ++ks) {
+      bf8_t a[F::FM], b[F::FN];
+#pragma unroll
+      for (int m = 0; m < F::FM; ++m) {
+        const int r = wm * (BM / WGM) + m * 16 + lr, c = ks * 4 + lk;
+        a[m] = *(const bf8_t*)(As + r * PBK + ((c ^ pswz(r)) * 8));
+      }
+#pragma unroll
+      for (int n = 0; n < F::FN; ++n) {
+        const int r = wn * (BN / WGN) + n * 16 + lr, c = ks * 4 + lk;
+        b[n] = *(const bf8_t*)(Bs + r * PBK + ((c ^ pswz(r)) * 8));
+      }
+#pragma unroll
+      for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+        for (int n = 0; n < F::FN; ++n) f.c[m][n] = mfma_bf16(a[m], b[n], f.c[m][n]);
+    }
+  }
+}
+
 }  // namespace gemm

@@ -109,34 +109,67 @@ __global__ __launch_bounds__(256) void k_trigemm_e(const T* __restrict__ L, cons
 // Tile order: workgroup ids are dealt round-robin to the 8 XCDs, so ids
 // xcd + 8 k on one XCD take the ni row blocks of one column block of W
 // (longest K range first): that slice of W is fetched into the XCD's L2 once.
-constexpr int TRI_BM = 256, TRI_BN = 128;
-
-__global__ __launch_bounds__(256) void k_trigemm_bf16(const u16* __restrict__ Lhi, const u16* __restrict__ Whi,
-                                                      long dW, float* __restrict__ Xi, int d, int ncols, float c,
-                                                      int vec_ok, int nj, int ni) {
-  constexpr int BM = TRI_BM, BN = TRI_BN;
-  __shared__ u16 lds[b_lds_elems<BM, BN>()];
+// Wide variant: TBM (j) x TBN (i) tiles, WGM x WGN wavefronts, 64-deep K slices.
+template <int TBM, int TBN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_trigemm_bf16w(const u16* __restrict__ Lhi,
+                                                                 const u16* __restrict__ Whi, long dW,
+                                                                 float* __restrict__ Xi, int d, int ncols, float c,
+                                                                 int vec_ok, int nj, int ni) {
+  typedef WFrag<TBM, TBN, WGM, WGN> F;
+  __shared__ u16 lds[w_lds_elems<TBM, TBN>()];
   const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
   const int jb = (k / ni) * 8 + xcd;
   if (jb >= nj) return;
   const int ib = ni - 1 - (k % ni);
-  const int j0 = jb * BM, i0 = ib * BN;
-  const int kend = min(d, i0 + BN);
-  BFrag<BM, BN> f;
+  const int j0 = jb * TBM, i0 = ib * TBN;
+  const int kend = min(d, i0 + TBN);
+  F f;
   f.zero();
-  b_gemm_seg<BM, BN>(f, Whi, dW, d, ncols, Lhi, (long)d * d, d, d, vec_ok, j0, i0, kend, 4, lds);
+  w_gemm_seg<TBM, TBN, WGM, WGN>(f, Whi, dW, d, ncols, Lhi, (long)d * d, d, d, vec_ok, j0, i0, 0, kend, 4, lds);
 #pragma unroll
-  for (int m = 0; m < BFrag<BM, BN>::FM; ++m)
+  for (int m = 0; m < F::FM; ++m)
 #pragma unroll
-    for (int n = 0; n < BFrag<BM, BN>::FN; ++n)
+    for (int n = 0; n < F::FN; ++n)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int tj, ti;
-        frag_coords<BM, BN>(m, n, r, tj, ti);
+        w_coords<TBM, TBN, WGM, WGN>(m, n, r, tj, ti);
         const int i = i0 + ti, j = j0 + tj;
         if (i < d && j < ncols) Xi[i + (long)j * d] = c * f.c[m][n][r];
       }
 }
+// Direct-to-LDS hi/lo variant for operands that fill whole tiles (d a
+// multiple of TBN, ncols of TBM): the K range of a row tile ends at its last
+// row; the four products accumulate per 32-deep slice.
+template <int TBM, int TBN, int WGM, int WGN, int ST>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_trigemm_hl(const u16* __restrict__ Lhi, const u16* __restrict__ Whi,
+                                                              long dW, float* __restrict__ Xi, int d, int ncols, float c,
+                                                              int nj, int ni) {
+  typedef WFrag<TBM, TBN, WGM, WGN> F;
+  __shared__ __attribute__((aligned(1024))) u16 lds[h_lds_elems<TBM, TBN, ST>()];
+  const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int jb = (k / ni) * 8 + xcd;
+  if (jb >= nj) return;
+  const int ib = ni - 1 - (k % ni);
+  const int j0 = jb * TBM, i0 = ib * TBN;
+  const int kend = min(d, i0 + TBN);
+  F f;
+  f.zero();
+  h_gemm<TBM, TBN, WGM, WGN, ST>(f, Whi, dW, d, Lhi, (long)d * d, d, j0, i0, kend, lds);
+#pragma unroll
+  for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int tj, ti;
+        w_coords<TBM, TBN, WGM, WGN>(m, n, r, tj, ti);
+        Xi[(i0 + ti) + (long)(j0 + tj) * d] = c * f.c[m][n][r];
+      }
+}
+
+// tile shape of the wide proposal kernel
+constexpr int TW_BM = 256, TW_BN = 128, TW_WGM = 4, TW_WGN = 2;
 
 hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, void* Xi, int d, long ncols, double c,
                    hipStream_t s) {
@@ -152,10 +185,23 @@ hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, voi
     const u16* Lhi = (const u16*)L;
     const long dW = (const u16*)Wlo - (const u16*)W;
     const int vec_ok = (d % 8 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)W % 16 == 0) && ((uintptr_t)Wlo % 16 == 0);
-    const int nj = cdiv(ncols, TRI_BM), ni = cdiv(d, TRI_BN);
-    const int groups = (nj + 7) / 8;
-    hipLaunchKernelGGL(k_trigemm_bf16, dim3(groups * 8 * ni), dim3(256), 0, s, Lhi, (const u16*)W, dW, (float*)Xi, d,
-                       (int)ncols, (float)c, vec_ok, nj, ni);
+    const bool whole = vec_ok && (ncols % 256 == 0);
+    if (whole && d % 256 == 0) {
+      const int nj = ncols / 256, ni = d / 256, groups = (nj + 7) / 8;
+      hipLaunchKernelGGL((k_trigemm_hl<256, 256, 2, 4, 2>), dim3(groups * 8 * ni), dim3(512), 0, s, Lhi, (const u16*)W,
+                         dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
+      return hipGetLastError();
+    }
+    if (whole && d % 128 == 0) {
+      const int nj = ncols / 256, ni = d / 128, groups = (nj + 7) / 8;
+      hipLaunchKernelGGL((k_trigemm_hl<256, 128, 4, 2, 3>), dim3(groups * 8 * ni), dim3(512), 0, s, Lhi, (const u16*)W,
+                         dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
+      return hipGetLastError();
+    }
+    const int nj = cdiv(ncols, TW_BM), ni = cdiv(d, TW_BN), groups = (nj + 7) / 8;
+    hipLaunchKernelGGL((k_trigemm_bf16w<TW_BM, TW_BN, TW_WGM, TW_WGN>), dim3(groups * 8 * ni),
+                       dim3(64 * TW_WGM * TW_WGN), 0, s, Lhi, (const u16*)W, dW, (float*)Xi, d, (int)ncols, (float)c,
+                       vec_ok, nj, ni);
   }
   return hipGetLastError();
 }
@@ -280,6 +326,61 @@ __global__ __launch_bounds__(256) void k_syrk_bf16(const u16* __restrict__ Xt, i
       }
 }
 
+// Direct-to-LDS variant for whole tiles (d a multiple of 256, K chunks of
+// 64): 256 (i) x 128 (j) tiles covering the lower triangle (bj < 2 (bi + 1)),
+// fp32 accumulation folded into fp64 every FOLD_BF16 columns.
+DEV void syrk_tile_256x128(int t, int nbj, int& bi, int& bj) {
+  int b = 0, c0 = 0;
+  for (;;) {
+    const int n = min(2 * b + 2, nbj);
+    if (t < c0 + n) break;
+    c0 += n;
+    ++b;
+  }
+  bi = b;
+  bj = t - c0;
+}
+
+__global__ __launch_bounds__(512) void k_syrk_pl(const u16* __restrict__ Xt, int d, int K, int kchunk,
+                                                 double* __restrict__ Gpart) {
+  constexpr int BM = 256, BN = 128, WGM = 4, WGN = 2, ST = 3;
+  typedef WFrag<BM, BN, WGM, WGN> F;
+  __shared__ __attribute__((aligned(1024))) u16 lds[p_lds_elems<BM, BN, ST>()];
+  int bi, bj;
+  syrk_tile_256x128(blockIdx.x, d / 128, bi, bj);
+  const int i0 = bi * BM, j0 = bj * BN;
+  const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  double acc[F::FM][F::FN][4];
+#pragma unroll
+  for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][n][r] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += FOLD_BF16) {
+    F f;
+    f.zero();
+    p_gemm<BM, BN, WGM, WGN, ST>(f, Xt, K, Xt, K, i0, j0, k0, min(ke, k0 + FOLD_BF16), lds);
+#pragma unroll
+    for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+      for (int n = 0; n < F::FN; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][n][r] += (double)f.c[m][n][r];
+  }
+  double* G = Gpart + (long)blockIdx.y * d * d;
+#pragma unroll
+  for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        w_coords<BM, BN, WGM, WGN>(m, n, r, ti, tj);
+        G[(j0 + tj) + (long)(i0 + ti) * d] = acc[m][n][r];  // G(i,j) at (row j, col i): upper
+      }
+}
+
 // Row sums over K of the window.  COLMAJOR: element (i, k) at X[i + k d];
 // otherwise at X[i K + k] (bf16 transposed window).
 template <typename T, bool COLMAJOR>
@@ -356,9 +457,13 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict_
 
 // Output tiles of the scatter: 64 x 64 lower pairs (f64/f32) or 128 x 64
 // lower-covering tiles (bf16).
-static int syrk_tiles(int prec, int d) {
+// bf16 windows whose tiles are whole take the direct-to-LDS kernel
+static bool syrk_pl(int prec, int d, long K) { return prec == PMIX && d % 256 == 0 && K % 64 == 0; }
+
+static int syrk_tiles(int prec, int d, long K) {
   if (prec != PMIX) return cdiv(d, 64) * (cdiv(d, 64) + 1) / 2;
-  const int nbi = cdiv(d, 128), nbj = cdiv(d, 64);
+  const int bi_rows = syrk_pl(prec, d, K) ? 256 : 128, bj_cols = bi_rows / 2;
+  const int nbi = cdiv(d, bi_rows), nbj = cdiv(d, bj_cols);
   int n = 0;
   for (int b = 0; b < nbi; ++b) n += min(2 * b + 2, nbj);
   return n;
@@ -367,7 +472,7 @@ static int syrk_tiles(int prec, int d) {
 // K is split so that at least ~512 workgroups run; chunks are whole
 // multiples of 64 columns (keeps the bf16 vector loads 16-byte aligned).
 static long syrk_kchunk(int prec, int d, long K) {
-  const int nt = syrk_tiles(prec, d);
+  const int nt = syrk_tiles(prec, d, K);
   int ns = cdiv(512, nt);
   const int maxs = (int)((K + 2047) / 2048);
   if (ns > maxs) ns = maxs;
@@ -391,9 +496,11 @@ hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, doub
   const int kchunk = (int)syrk_kchunk(prec, d, K);
   double* Gpart = (double*)scratch;
   double* hpart = Gpart + (size_t)ns * d * d;
-  const int nt = syrk_tiles(prec, d);
+  const int nt = syrk_tiles(prec, d, K);
   dim3 grid(nt, ns);
-  if (prec == P64)
+  if (syrk_pl(prec, d, K) && (uintptr_t)Xs % 16 == 0)
+    hipLaunchKernelGGL(k_syrk_pl, grid, dim3(512), 0, s, (const u16*)Xs, d, (int)K, kchunk, Gpart);
+  else if (prec == P64)
     hipLaunchKernelGGL((k_syrk_e<double, 16>), grid, dim3(256), 0, s, (const double*)Xs, d, (int)K, kchunk, Gpart);
   else if (prec == P32)
     hipLaunchKernelGGL((k_syrk_e<float, 32>), grid, dim3(256), 0, s, (const float*)Xs, d, (int)K, kchunk, Gpart);
