@@ -18,11 +18,11 @@ inline int tgt_row_blocks(int d) { return (d + TGT_BM - 1) / TGT_BM; }
 inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 
 // Target contractions write per-row-block partial sums of log-density
-// contributions: log pi(x_p) = sum_rb part[rb][p] (+ the prior, for the
+// contributions: log pi(x_p) = sum_rb part[p][rb] (+ the prior, for the
 // logistic target, added by the step kernel).
-// Gaussian: part[rb][p] = -1/2 sum over rows of block rb of (R (x_p - mu))_i^2.
+// Gaussian: part[p][rb] = -1/2 sum over rows of block rb of (R (x_p - mu))_i^2.
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
-// Logistic: part[rb][p] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
+// Logistic: part[p][rb] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
 // (A n_obs x d row-major FP32, V d x P FP32); columns >= *nact skipped.
 int logreg_row_blocks(long n_obs);
 hipError_t tgt_logreg(const float* A, const float* y, long n_obs, const float* V, int d, int P, const int* nact,
@@ -103,9 +103,9 @@ struct StepArgs {
   int do_accept;
   const void* xi_cur;                     // d x P (f64 or f32)
   const void* w_cur; const void* wlo_cur; // d x P
-  const double* lpp_part;                 // nrb x P
+  const double* lpp_part;                 // P x nrb (chain-major)
   int nrb;
-  const double* zq_part_cur;              // nch x P
+  const double* zq_part_cur;              // P x nch (chain-major)
   const double* lp_cur; const double* zq_cur;
   double* lp_nxt; double* zq_nxt;
   const double* u;                        // P
@@ -119,12 +119,12 @@ struct StepArgs {
   int do_propose;
   const void* xi_nxt;
   const void* w_nxt; const void* wlo_nxt;
-  double* zq_part_nxt;                    // nch x P
+  double* zq_part_nxt;                    // P x nch
   // target variants
   int v32;                                // write V as FP32 whatever the precision
   double prior_w;                         // > 0: add -prior_w |x|^2 to log pi (pq partials)
-  const double* pq_part_cur;              // nch x P
-  double* pq_part_nxt;                    // nch x P
+  const double* pq_part_cur;              // P x nch
+  double* pq_part_nxt;                    // P x nch
   // delayed acceptance (second stage on stage-1 survivors)
   int da;
   const uint8_t* pass1;                   // P
@@ -138,7 +138,7 @@ hipError_t step(const StepArgs& a, hipStream_t s);
 
 // V = X - mu (mu may be null; FP64 or FP32 V), Z = X, for the initial evaluation.
 hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);
-// lp[p] = sum_rb part[rb][p] - prior_w |x_p|^2; zq[p] = ||Z_p||^2.
+// lp[p] = sum_rb part[p][rb] - prior_w |x_p|^2; zq[p] = ||Z_p||^2.
 hipError_t init_finish(const double* part, int nrb, const double* Z, const double* X, double prior_w, double* lp,
                        double* zq, int d, int P, hipStream_t s);
 // trace[t][1 + k][p] = sum_ch proj_part[t][ch][k][p]
@@ -152,7 +152,7 @@ struct BProb {
   const float* R;                   // d x d row-major
   const double* mu;                 // d
   double *X, *Z, *xr, *lp, *zq;     // d x P, d x P, d, 2 x P, 2 x P
-  double *zq_part, *lpp_part, *la;  // 2 x nch x P, nrb x P, n x P
+  double *zq_part, *lpp_part, *la;  // 2 x P x nch, P x nrb, n x P
   uint8_t* acc;                     // n x P
   float *V, *W, *Xi, *win;          // d x P, d x P n (x3)
   double *S, *m, *L, *C, *Linv, *G, *h;

@@ -18,7 +18,8 @@ DEV double propose1(double xr, double x, double rho, double xi) { return __fma_r
 // of Y^2 in FP64 per 64-row block (the caller adds the blocks in order).
 // ============================================================================
 // One output tile: rows [bx BM, +BM) of Y, chains [by BN, +BN); the tile's
-// FP64 partial sums go to part[bx * ldp + j] (one row per BM rows of R).
+// FP64 partial sums go to part[j * ldp + bx] (chain-major: a chain's ldp
+// row-block partials are contiguous for the reader).
 template <typename T, int BK, int BM, int BN, int KG>
 DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d, int P, int bx, int by,
                         double* __restrict__ part, int ldp) {
@@ -49,14 +50,14 @@ DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d,
   __syncthreads();
   if (threadIdx.x < BN) {
     const int j = j0 + threadIdx.x;
-    if (j < P) part[(long)bx * ldp + j] = -0.5 * (red[0][threadIdx.x] + red[1][threadIdx.x]);
+    if (j < P) part[(long)j * ldp + bx] = -0.5 * (red[0][threadIdx.x] + red[1][threadIdx.x]);
   }
 }
 
 template <typename T, int BK>
 __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
                                                    double* __restrict__ part) {
-  tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, P);
+  tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, gridDim.x);
 }
 
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
@@ -622,20 +623,36 @@ hipError_t cov_assemble(const double* S, const double* m, double eps, double* C,
 // Inverse of the lower-triangular 64 x 64 block held in Ls (row-major, LDS):
 // lane c forms column c of L^-1 by forward substitution; x[] stays in
 // registers (the loops are fully unrolled), Ls reads are broadcasts.
-DEV void tri_inverse_col(const double (*Ls)[CHOL_NB + 1], double* x, int c) {
+// rdiag[q] = 1 / Ls[q][q]; four partial sums break the dependency chain of
+// each substitution step.
+DEV void tri_inverse_col(const double (*Ls)[CHOL_NB + 1], const double* rdiag, double* x, int c) {
 #pragma unroll
   for (int rr = 0; rr < CHOL_NB; ++rr) {
-    double s = (rr == c) ? 1.0 : 0.0;
+    double s[4] = {(rr == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < rr; ++q) s = __fma_rn(-Ls[rr][q], x[q], s);
-    x[rr] = s / Ls[rr][rr];
+    for (int q = 0; q < rr; ++q) s[q & 3] = __fma_rn(-Ls[rr][q], x[q], s[q & 3]);
+    x[rr] = ((s[0] + s[1]) + (s[2] + s[3])) * rdiag[rr];
   }
 }
 
+// lane's value v broadcast from lane `src` (a compile-time lane after unrolling)
+DEV double readlane_f64(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lane r holds row r of the block.  Step c: the pivot comes from lane c by
+// readlane, column c of L goes through a double-buffered LDS vector (one
+// barrier per step), and every lane applies the rank-1 update to its whole
+// row without per-element masks: entries right of the diagonal collect
+// values that are never read (the broadcast and the stores mask them).
 DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
                          int* __restrict__ info) {
-  __shared__ double colv[CHOL_NB];
+  __shared__ double colv[2][CHOL_NB];
   __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
+  __shared__ double rdiag[CHOL_NB];
   const int r = threadIdx.x;
   double a[CHOL_NB];
 #pragma unroll
@@ -648,36 +665,34 @@ DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* 
     }
     a[c] = v;
   }
-  int fail = 0;
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
-    if (r == c) colv[c] = a[c];
-    __syncthreads();
-    const double piv = colv[c];
-    if (!(piv > 0.0) && fail == 0) fail = c + 1;
+    const double piv = readlane_f64(a[c], c);
     const double sq = sqrt(piv);
-    __syncthreads();
-    double l = a[c];
-    if (r == c) l = sq;
-    else if (r > c) l = a[c] / sq;
+    const double l = (r == c) ? sq : a[c] * (1.0 / sq);
     a[c] = l;
-    colv[r] = (r >= c) ? l : 0.0;
+    colv[c & 1][r] = (r >= c) ? l : 0.0;
     __syncthreads();
 #pragma unroll
-    for (int q = c + 1; q < CHOL_NB; ++q)
-      if (r >= q) a[q] = __fma_rn(-l, colv[q], a[q]);
-    __syncthreads();
+    for (int q = c + 1; q < CHOL_NB; ++q) a[q] = __fma_rn(-l, colv[c & 1][q], a[q]);
   }
   if (r < jn) {
 #pragma unroll
     for (int c = 0; c < CHOL_NB; ++c)
       if (c < jn) A[(j0 + r) + (long)(j0 + c) * d] = (c <= r) ? a[c] : 0.0;
   }
-  if (r == 0 && fail && fail <= jn && *info == 0) *info = j0 + fail;
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) Ls[r][c] = (c <= r) ? a[c] : 0.0;
   __syncthreads();
-  tri_inverse_col(Ls, a, r);
+  // a pivot that is not > 0 (or NaN) leaves a diagonal root that is not > 0,
+  // and every later pivot inherits the failure: the first bad column is the
+  // lowest such lane
+  const double diag = Ls[r][r];
+  const unsigned long long bad = __ballot(r < jn && !(diag > 0.0));
+  if (r == 0 && bad && *info == 0) *info = j0 + __ffsll((long long)bad);
+  rdiag[r] = 1.0 / diag;
+  __syncthreads();
+  tri_inverse_col(Ls, rdiag, a, r);
 #pragma unroll
   for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
 }
@@ -690,6 +705,7 @@ __global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d,
 // Inverses of all (already factored) diagonal blocks of L, one wave per block.
 DEV void tri_inv_block(const double* __restrict__ L, int d, double* __restrict__ Linv, int bx) {
   __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
+  __shared__ double rdiag[CHOL_NB];
   const int r = threadIdx.x, j0 = bx * CHOL_NB, jn = min(CHOL_NB, d - j0);
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
@@ -698,8 +714,10 @@ DEV void tri_inv_block(const double* __restrict__ L, int d, double* __restrict__
     Ls[r][c] = v;
   }
   __syncthreads();
+  rdiag[r] = 1.0 / Ls[r][r];
+  __syncthreads();
   double x[CHOL_NB];
-  tri_inverse_col(Ls, x, r);
+  tri_inverse_col(Ls, rdiag, x, r);
   double* out = Linv + (long)bx * CHOL_NB * CHOL_NB;
 #pragma unroll
   for (int q = 0; q < CHOL_NB; ++q) out[q + r * CHOL_NB] = x[q];
@@ -1089,17 +1107,17 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
     const int col = a.da ? a.slot[p] : p;
     double s = 0.0;
     if (live)
-      for (int q = lane; q < a.nrb; q += 64) s += a.lpp_part[(long)q * P + col];
+      for (int q = lane; q < a.nrb; q += 64) s += a.lpp_part[(long)col * a.nrb + q];
     s = wave_sum_f64(s);
     if (a.prior_w > 0.0) {
       double pq = 0.0;
-      for (int q = lane; q < nch; q += 64) pq += a.pq_part_cur[(long)q * P + p];
+      for (int q = lane; q < nch; q += 64) pq += a.pq_part_cur[(long)p * nch + q];
       pq = wave_sum_f64(pq);
       s = __fma_rn(-a.prior_w, pq, s);
     }
     const double lpp = s;
     double zs = 0.0;
-    for (int q = lane; q < nch; q += 64) zs += a.zq_part_cur[(long)q * P + p];
+    for (int q = lane; q < nch; q += 64) zs += a.zq_part_cur[(long)p * nch + q];
     zs = wave_sum_f64(zs);
     const double lp = a.lp_cur[p], zq = a.zq_cur[p];
     double la;
@@ -1154,10 +1172,10 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   }
   if (a.do_propose) {
     zacc = wave_sum_f64(zacc);
-    if (lane == 0) a.zq_part_nxt[(long)ch * P + p] = zacc;
+    if (lane == 0) a.zq_part_nxt[(long)p * nch + ch] = zacc;
     if (a.prior_w > 0.0) {
       xacc = wave_sum_f64(xacc);
-      if (lane == 0) a.pq_part_nxt[(long)ch * P + p] = xacc;
+      if (lane == 0) a.pq_part_nxt[(long)p * nch + ch] = xacc;
     }
   }
   if (a.do_accept && a.nproj > 0) {
@@ -1207,7 +1225,7 @@ DEV void init_finish_block(const double* __restrict__ part, int nrb, int P, cons
                            double prior_w, double* __restrict__ lp, int p) {
   __shared__ double red[2][256];
   double s = 0.0, q = 0.0;
-  for (int k = threadIdx.x; k < nrb; k += 256) s += part[(long)k * P + p];
+  for (int k = threadIdx.x; k < nrb; k += 256) s += part[(long)p * nrb + k];
   if (prior_w > 0.0)
     for (int i = threadIdx.x; i < d; i += 256) {
       const double x = X[i + (long)p * d];
@@ -1309,7 +1327,7 @@ template <int BM, int KG>
 __global__ __launch_bounds__(256 * KG) void gk_tgt(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int P) {
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
-  tgt_gauss_tile<float, 32, BM, 32, KG>(b.R, b.V, b.d, P, t.a, t.b, b.lpp_part, P);
+  tgt_gauss_tile<float, 32, BM, 32, KG>(b.R, b.V, b.d, P, t.a, t.b, b.lpp_part, b.nrb);
 }
 
 hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s) {
