@@ -86,20 +86,27 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         window()
     torch.cuda.synchronize()
     s.set_trace(proj, trace)
-    if profile:
-        s.profile(True)
-        s.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         window()
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    prof = s.profile_read(reset=True) if profile else None
+    nacc = s.get(diam.F_NACC).view(torch.int32).sum().item()
+    prof = None
+    if profile:
+        # stage breakdown from HIP events on extra windows (events add small
+        # gaps between launches, so they stay out of the timed region)
+        s.set_trace(None, None)
+        s.profile(True)
+        s.profile_read(reset=True)
+        for _ in range(args.profile_windows):
+            window()
+        prof = s.profile_read(reset=True)
+        s.profile(False)
     tr = trace.cpu().numpy()
     half = n_timed // 2
     ess = {name: ess_per_chain(tr[half:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
-    nacc = s.get(diam.F_NACC).view(torch.int32).sum().item()
     s.close()
     chain_steps = P * n_timed
     return {
@@ -183,8 +190,7 @@ def learned_experiment(args, torch, diam):
         trace = torch.empty((n_timed, 3, P), dtype=torch.float64, device=dev)
         s.set_trace(proj, trace)
         nacc0 = s.get(diam.F_NACC).view(torch.int32).sum().item()
-        s.profile(True)
-        s.profile_read(reset=True)
+        npass0 = s.get(diam.F_NPASS).view(torch.int32).sum().item() if use_da else 0
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.learned_windows):
@@ -193,16 +199,23 @@ def learned_experiment(args, torch, diam):
             assert s.update_proposal()[0] == diam.OK
         torch.cuda.synchronize()
         T = time.perf_counter() - t1
-        prof = s.profile_read(reset=True)
         tr = trace.cpu().numpy()
-        ess = {name: ess_per_chain(tr[:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
         nacc = s.get(diam.F_NACC).view(torch.int32).sum().item() - nacc0
+        npass = (s.get(diam.F_NPASS).view(torch.int32).sum().item() - npass0) if use_da else 0
+        s.set_trace(None, None)
+        s.profile(True)
+        s.profile_read(reset=True)
+        s.step_batch(nl)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+        prof = s.profile_read(reset=True)
+        s.profile(False)
+        ess = {name: ess_per_chain(tr[:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
         r = {"beta": beta, "delayed_acceptance": use_da,
              "seconds": T, "chain_steps_per_s": P * n_timed / T, "ess": ess, "ess_per_s": min(ess.values()) / T,
              "acceptance": nacc / (P * n_timed),
-             "stage_ms_per_window": {k: v[0] / args.learned_windows for k, v in prof.items() if v[1]}}
+             "stage_ms_per_window": {k: v[0] for k, v in prof.items() if v[1]}}
         if use_da:
-            npass = s.get(diam.F_NPASS).view(torch.int32).sum().item()
             r["stage1_pass_rate"] = npass / (P * n_timed)
             r["stage2_accept_rate"] = nacc / max(npass, 1)
             r["ess_per_s_incl_training"] = min(ess.values()) / (T + train_s)
@@ -355,6 +368,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--profile-windows", dest="profile_windows", type=int, default=2,
+                    help="extra windows timed per stage with HIP events (after the timed region)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-part (logistic) experiment")
     ap.add_argument("--copy-calibration", dest="copy_calibration", type=int, default=0,
                     help="first run 3 device copies of this many bytes (counter calibration)")
@@ -424,7 +439,7 @@ def main():
         "bound": "mfma", "achieved": flops / dt / 1e12, "peak": PEAK[tdt] / 1e12, "unit": "TFLOP/s",
         "frac": flops / dt / PEAK[tdt], "traffic": None, "avg_us": dt * 1e6, "launches": n_t,
     }
-    stages = {k: {"ms_per_window": v[0] / args.steps, "regions": v[1]} for k, v in prof.items()}
+    stages = {k: {"ms_per_window": v[0] / args.profile_windows, "regions": v[1]} for k, v in prof.items() if v[1]}
 
     out = {
         "metric": METRIC,
@@ -452,7 +467,8 @@ def main():
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],
                        "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"],
-                       "stage_ms_per_window": {k: v[0] / args.steps for k, v in ref["profile"].items()}}
+                       "stage_ms_per_window": {k: v[0] / args.profile_windows for k, v in ref["profile"].items()
+                                               if v[1]}}
         out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],
                                   "ess": res["ess_per_s"] / ref["ess_per_s"]}
     if not args.no_learned:

@@ -87,7 +87,8 @@ typedef struct {
 
 /* Target log density (Section 2.1: only the unnormalised density is needed).
  * DIAM_TGT_GAUSS: log pi(x) = -1/2 ||R (x - mu)||^2, R d x d row-major with
- * R^T R = Sigma^-1 (any square root of the precision).  R is FP64 for
+ * R^T R = Sigma^-1 (any square root of the precision); mu and R 16-byte
+ * aligned (else DIAM_E_ARG).  R is FP64 for
  * DIAM_FP64 and FP32 otherwise; mu is FP64.  Evaluating it costs one dense
  * d x d by d x P contraction per step, the cost model of the paper's test
  * targets (Section 3.1).
@@ -168,6 +169,7 @@ int diam_init(diam_ctx** out, const diam_config* cfg, const diam_target* tgt, vo
  * U: P x n_steps f64 uniforms in (0, 1) (step-major; 2P per step under
  *    delayed acceptance), or NULL for Philox.
  *    Accept iff log u < log alpha; a NaN log alpha rejects (Section 2.2).
+ * W and U must be 16-byte aligned (else DIAM_E_ARG).
  * n_accepted: P int32 counters incremented per accepted proposal, or NULL.
  * The batch of search directions beta alpha A W for the n_steps steps is
  * formed in one contraction first, as Algorithm 1 does every n_lag steps. */
@@ -197,7 +199,7 @@ int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double 
  * step t (counted from this call) trace[(t * (1 + n_proj) + f) * P + p] gets
  * f = 0: log pi of chain p's state after the step, f >= 1: proj[:, f-1]^T x.
  * proj: d x n_proj f64 (n_proj <= 4).  capacity: steps the trace can hold;
- * recording stops when full.  trace == NULL disables. */
+ * recording stops when full.  trace == NULL disables. proj and trace 16-byte aligned. */
 int diam_set_trace(diam_ctx* ctx, const double* proj, int32_t n_proj, double* trace, int64_t capacity);
 
 /* ---- learned-part form (requires cfg.surrogate = 1 or 2) -----------------

@@ -50,6 +50,8 @@ struct Layout {
   size_t mlp_master, mlp_eff, mlp_grad, mlp_m, mlp_in_mean, mlp_in_scale, mlp_stats, mlp_Xs, mlp_ts, mlp_xb, mlp_tb,
       mlp_a1, mlp_h1, mlp_a2, mlp_h2, mlp_ga1, mlp_ga2, mlp_out, mlp_gout, mlp_loss, mlp_bidx, s_cur, s_new, pass1,
       slot, idx, nsurv, npass, Vs, t64, Zs;
+  // split-bf16 target (mixed form, Gaussian)
+  size_t R3, V3, Yp;
   size_t total;
 };
 
@@ -63,6 +65,10 @@ int elem_bytes_ctr(int prec) { return prec == DIAM_FP64 ? 8 : 4; }
 
 int target_row_blocks(const diam_config& c, const diam_target& t) {
   return t.kind == DIAM_TGT_LOGREG ? dk::logreg_row_blocks(t.n_obs) : dk::tgt_row_blocks(c.d);
+}
+
+bool use_s3(const diam_config& c, const diam_target& t) {
+  return c.precision == DIAM_MIXED && t.kind == DIAM_TGT_GAUSS && dk::tgt_s3_ok(c.d, c.P);
 }
 
 Layout make_layout(const diam_config& c, const diam_target& tg) {
@@ -105,6 +111,10 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.status = take(sizeof(Status));
   L.proj_part = take(nl * (size_t)nch * 4 * P * 8);
   L.linv = take(dk::chol_scratch_bytes(c.d));
+  const bool s3 = use_s3(c, tg);
+  L.R3 = take(s3 ? 3 * dd * 2 : 0);
+  L.V3 = take(s3 ? 3 * dP * 2 : 0);
+  L.Yp = take(s3 ? dk::tgt_s3_scratch_bytes(c.d, c.P) : 0);
   if (c.surrogate) {
     const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
     const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
@@ -158,6 +168,9 @@ struct diam_ctx {
   double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *pq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part, *linv;
   // target
   int logreg;
+  int s3;          // split-bf16 target contraction
+  uint16_t *R3, *V3;
+  float* Yp;
   double prior_w;
   // learned-part form
   dk::MlpBufs mlp;
@@ -217,6 +230,7 @@ static int check_target(const diam_config* c, const diam_target* t) {
   if (!t) return fail(DIAM_E_ARG, "null target");
   if (t->kind == DIAM_TGT_GAUSS) {
     if (!t->mu || !t->R) return fail(DIAM_E_ARG, "Gaussian target needs mu and R");
+    if ((uintptr_t)t->mu % 16 || (uintptr_t)t->R % 16) return fail(DIAM_E_ARG, "mu and R must be 16-byte aligned");
   } else if (t->kind == DIAM_TGT_LOGREG) {
     if (!t->A || !t->y || t->n_obs < 1 || t->n_obs > (1L << 30)) return fail(DIAM_E_ARG, "logistic target needs A, y, n_obs >= 1");
     if (!(t->prior_var > 0.0)) return fail(DIAM_E_ARG, "prior_var must be > 0");
@@ -365,6 +379,10 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->zq_part = dptr(c, lay.zq_part);
   c->pq_part = dptr(c, lay.pq_part);
   c->logreg = tgt->kind == DIAM_TGT_LOGREG;
+  c->s3 = use_s3(*cfg, *tgt);
+  c->R3 = (uint16_t*)(c->ws + lay.R3);
+  c->V3 = (uint16_t*)(c->ws + lay.V3);
+  c->Yp = (float*)(c->ws + lay.Yp);
   c->prior_w = c->logreg ? 1.0 / (2.0 * tgt->prior_var) : 0.0;
   c->trained = 0;
   c->da_on = 0;
@@ -482,7 +500,13 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
     HIPCHK_INIT(dk::tgt_logreg(tgt->A, tgt->y, tgt->n_obs, (const float*)c->V, d, P, nullptr, c->lpp_part, s));
   } else {
     HIPCHK_INIT(dk::init_eval(c->prec == dk::P64, c->X, tgt->mu, c->V, c->Z, d, P, s));
-    HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s));
+    if (c->s3) {
+      HIPCHK_INIT(dk::split3_f32((const float*)tgt->R, (long)d * d, c->R3, s));
+      HIPCHK_INIT(dk::split3_f32((const float*)c->V, (long)d * P, c->V3, s));
+      HIPCHK_INIT(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s));
+    } else {
+      HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s));
+    }
   }
   HIPCHK_INIT(dk::init_finish(c->lpp_part, c->nrb, c->Z, c->X, c->prior_w, c->lp, c->zq, d, P, s));
   if (cfg->surrogate) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->npass, (long)P);
@@ -497,6 +521,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   if (n == 0) return DIAM_OK;
   if (c->siw + n > c->cfg.n_lag)
     return fail(DIAM_E_STATE, "steps_in_window %d + n_steps %d exceeds n_lag %d", c->siw, n, c->cfg.n_lag);
+  if ((uintptr_t)W % 16 || (uintptr_t)U % 16) return fail(DIAM_E_ARG, "W and U must be 16-byte aligned");
   const int d = c->cfg.d, P = c->cfg.P;
   const long dP = (long)d * P;
   hipStream_t s = c->stream;
@@ -550,6 +575,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.win = c->win;
   a.err = &c->status->err;
   a.v32 = c->logreg;
+  a.v3 = c->s3 ? c->V3 : nullptr;
   a.prior_w = c->prior_w;
   a.proj = c->proj;
   a.nproj = tracing ? c->nproj : 0;
@@ -580,6 +606,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     if (c->logreg)
       HIPCHK(dk::tgt_logreg(c->tgt.A, c->tgt.y, c->tgt.n_obs, c->da_on ? c->Vs : (const float*)c->V, d, P,
                             c->da_on ? c->nsurv : nullptr, c->lpp_part, s));
+    else if (c->s3)
+      HIPCHK(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s));
     else
       HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s));
     prof_end(c, ps);
@@ -814,6 +842,7 @@ extern "C" int diam_set_trace(diam_ctx* c, const double* proj, int32_t n_proj, d
   if (n_proj < 0 || n_proj > 4) return fail(DIAM_E_ARG, "n_proj must be in [0, 4]");
   if (n_proj > 0 && !proj) return fail(DIAM_E_ARG, "null proj");
   if (trace && capacity < 0) return fail(DIAM_E_ARG, "negative capacity");
+  if ((uintptr_t)proj % 16 || (uintptr_t)trace % 16) return fail(DIAM_E_ARG, "proj and trace must be 16-byte aligned");
   c->proj = proj;
   c->nproj = trace ? n_proj : 0;
   c->trace = trace;

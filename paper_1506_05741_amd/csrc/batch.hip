@@ -62,7 +62,7 @@ struct BLay {
 // Tile lists of every phase (host side, uploaded once).
 struct Tiles {
   std::vector<BTile> all;
-  Seg tgt[dk::G_TGT_CONFIGS], step, trigemm, syrk, rowsum, dd, d1, dp, colnorm, triinv;
+  Seg tgt[dk::G_TGT_CONFIGS], decide, step, trigemm, syrk, rowsum, dd, d1, dp, colnorm, triinv;
   std::vector<Seg> cdiag, cpanel, cupd, tdiag, tupd;
   int max_nb = 0;
   Seg add(const std::vector<BTile>& v) {
@@ -86,6 +86,10 @@ Tiles build_tiles(const std::vector<int>& dims, int P, int n) {
         for (int by = 0; by < cdivh(P, 32); ++by) v.push_back({g, bx, by});
     T.tgt[c] = T.add(v);
   }
+  v.clear();
+  for (int g = 0; g < G; ++g)
+    for (int pq = 0; pq < cdivh(P, 4); ++pq) v.push_back({g, 0, pq});
+  T.decide = T.add(v);
   v.clear();
   for (int g = 0; g < G; ++g)
     for (int ch = 0; ch < dk::step_chunks(dims[g]); ++ch)
@@ -294,6 +298,8 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
   if (!mu || !R || !x0) return bfail(DIAM_E_ARG, "null target or start arrays");
   for (int g = 0; g < cfg->G; ++g)
     if (!mu[g] || !R[g] || !x0[g]) return bfail(DIAM_E_ARG, "problem %d: null mu, R or x0", g);
+  for (int g = 0; g < cfg->G; ++g)
+    if ((uintptr_t)mu[g] % 16 || (uintptr_t)R[g] % 16) return bfail(DIAM_E_ARG, "problem %d: mu, R not 16-byte aligned", g);
   if (!workspace || ((uintptr_t)workspace & 255)) return bfail(DIAM_E_ARG, "workspace null or not 256-byte aligned");
   std::vector<int> dv(dims, dims + cfg->G);
   Tiles T = build_tiles(dv, cfg->P, cfg->n_lag);
@@ -476,12 +482,12 @@ static int enqueue_window(diam_batch* b, hipStream_t s) {
   st.U = b->U_all;
   st.err = b->err;
   st.t = -1;
-  BCHK(dk::g_step(b->dp, tl(T.step), T.step.n, st, s));
+  BCHK(dk::g_step(b->dp, tl(T.decide), T.decide.n, tl(T.step), T.step.n, st, s));
   const Seg& tg = T.tgt[b->tgt_cfg];
   for (int t = 0; t < n; ++t) {
     BCHK(dk::g_tgt(b->tgt_cfg, b->dp, tl(tg), tg.n, P, s));
     st.t = t;
-    BCHK(dk::g_step(b->dp, tl(T.step), T.step.n, st, s));
+    BCHK(dk::g_step(b->dp, tl(T.decide), T.decide.n, tl(T.step), T.step.n, st, s));
   }
   BCHK(dk::g_scatter(b->dp, tl(T.syrk), T.syrk.n, tl(T.rowsum), T.rowsum.n, (int)K, s));
   BCHK(dk::g_fold(b->dp, tl(T.dd), T.dd.n, tl(T.d1), T.d1.n, b->Nd, (double)K, s));

@@ -22,6 +22,14 @@ inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 // logistic target, added by the step kernel).
 // Gaussian: part[p][rb] = -1/2 sum over rows of block rb of (R (x_p - mu))_i^2.
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
+// Mixed form, Gaussian: the same partials from three-part bf16 splits of R
+// and V (FP32-equivalent products); needs tgt_s3_ok(d, P); Yp scratch of
+// tgt_s3_scratch_bytes.  split3_f32 writes the parts of n floats at dst,
+// dst + n, dst + 2n.
+bool tgt_s3_ok(int d, int P);
+size_t tgt_s3_scratch_bytes(int d, int P);
+hipError_t split3_f32(const float* src, long n, uint16_t* dst, hipStream_t s);
+hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s);
 // Logistic: part[p][rb] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
 // (A n_obs x d row-major FP32, V d x P FP32); columns >= *nact skipped.
 int logreg_row_blocks(long n_obs);
@@ -133,6 +141,7 @@ struct StepArgs {
   const double* s_in; double* s_out;      // P: surrogate at the current states
   const double* u2;                       // P
   int da_resid;                           // residual surrogate r(x) - |z|^2/(2 alpha^2)
+  uint16_t* v3;                           // non-null: write V as three bf16 parts (d x P each) instead
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
 
@@ -169,7 +178,8 @@ struct BStep {
 constexpr int G_TGT_CONFIGS = 5;    // target tile shapes the autotuner chooses from
 int g_tgt_bm(int cfg);
 hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s);
-hipError_t g_step(const BProb* pr, const BTile* tl, int ntiles, const BStep& st, hipStream_t s);
+hipError_t g_step(const BProb* pr, const BTile* dec_tl, int ndec, const BTile* tl, int ntiles, const BStep& st,
+                  hipStream_t s);
 hipError_t g_trigemm(const BProb* pr, const BTile* tl, int ntiles, int ncols, double c, hipStream_t s);
 hipError_t g_scatter(const BProb* pr, const BTile* syrk_tl, int nsyrk, const BTile* row_tl, int nrow, int K,
                      hipStream_t s);

@@ -60,6 +60,86 @@ __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, cons
   tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, gridDim.x);
 }
 
+// ---- split-BF16 target (mixed form): Y = R V with both operands in three
+// bf16 parts (FP32-equivalent products, see s3_gemm), 64 x 64 tiles, K split
+// in S3_KSPLIT ranges whose FP32 partial Y are summed in FP64 by the
+// reduction, which squares and sums 64-row blocks (chain-major partials).
+constexpr int S3_KSPLIT = 4;
+
+DEV void split3(float x, u16& h, u16& m, u16& l) {
+  h = f32_to_bf16_bits(x);
+  const float r1 = x - bf16_bits_to_f32(h);
+  m = f32_to_bf16_bits(r1);
+  const float r2 = r1 - bf16_bits_to_f32(m);
+  l = f32_to_bf16_bits(r2);
+}
+
+__global__ __launch_bounds__(256) void k_split3(const float* __restrict__ src, long n, u16* __restrict__ dst) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  u16 h, m, l;
+  split3(src[e], h, m, l);
+  dst[e] = h;
+  dst[n + e] = m;
+  dst[2 * n + e] = l;
+}
+
+hipError_t split3_f32(const float* src, long n, uint16_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_split3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, dst);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_tgt_s3(const u16* __restrict__ R3, const u16* __restrict__ V3, int d, int P,
+                                                float* __restrict__ Yp) {
+  constexpr int BM = 64, BN = 64, WGM = 2, WGN = 2, ST = 2;
+  typedef WFrag<BM, BN, WGM, WGN> F;
+  __shared__ __attribute__((aligned(1024))) u16 lds[s3_lds_elems<BM, BN, ST>()];
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
+  const int kl = d / S3_KSPLIT;
+  F f;
+  f.zero();
+  s3_gemm<BM, BN, WGM, WGN, ST>(f, R3, (long)d * d, d, V3, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl, lds);
+  float* Y = Yp + (long)ks * P * d;
+#pragma unroll
+  for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+    for (int n = 0; n < F::FN; ++n) {
+      int ti, tj;
+      w_coords<BM, BN, WGM, WGN>(m, n, 0, ti, tj);
+      // four consecutive rows of one chain: one 16-byte store
+      *(f4_t*)(Y + (long)(j0 + tj) * d + i0 + ti) = f.c[m][n];
+    }
+}
+
+// part[j][rb] = -1/2 sum over rows of block rb of (sum_s Yp[s])^2, one wave per (j, rb)
+__global__ __launch_bounds__(256) void k_tgt_s3_reduce(const float* __restrict__ Yp, int d, int P, int nrb,
+                                                       double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= (long)P * nrb) return;
+  const int j = (int)(wid / nrb), rb = (int)(wid % nrb);
+  const int i = rb * 64 + lane;
+  double y = 0.0;
+  if (i < d)
+    for (int s = 0; s < S3_KSPLIT; ++s) y += (double)Yp[((long)s * P + j) * d + i];
+  const double q = wave_sum_f64(y * y);
+  if (lane == 0) part[(long)j * nrb + rb] = -0.5 * q;
+}
+
+bool tgt_s3_ok(int d, int P) { return d % (S3_KSPLIT * 32) == 0 && d % 64 == 0 && P % 64 == 0; }
+
+size_t tgt_s3_scratch_bytes(int d, int P) { return (size_t)S3_KSPLIT * d * P * sizeof(float); }
+
+hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_tgt_s3, dim3(d / 64, P / 64, S3_KSPLIT), dim3(256), 0, s, (const u16*)R3, (const u16*)V3, d, P,
+                     Yp);
+  const int nrb = tgt_row_blocks(d);
+  const long waves = (long)P * nrb;
+  hipLaunchKernelGGL(k_tgt_s3_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, d, P, nrb,
+                     part);
+  return hipGetLastError();
+}
+
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
   dim3 grid(cdiv(d, TGT_BM), cdiv(P, 64));
   if (prec == P64)
@@ -1060,8 +1140,12 @@ DEV void store_win(void* win, long e, double v) {
 
 constexpr int MAXPROJ = 4;
 
-// chunk ch of nch (STEP_RCH rows each) of chains 4 pq .. 4 pq + 3, one wave each
-template <int PR>
+// chunk ch of nch (STEP_RCH rows each) of chains 4 pq .. 4 pq + 3, one wave each.
+// MODE 0: decision and state update in one pass (every chunk's wave
+// recomputes its chain's decision); MODE 1: decision only (one wave per
+// chain, ch = 0), written to acc_out and the per-chain scalars; MODE 2: state
+// update and next proposal only, reading the decision from acc_out.
+template <int PR, int MODE = 0>
 DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   typedef typename StepT<PR>::XI XI;
   typedef typename StepT<PR>::VT VT;
@@ -1079,7 +1163,7 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   double x[RPL], z[RPL], xr[RPL], xc[RPL], wc[RPL], xn[RPL], wn[RPL], mu[RPL];
   bool in[RPL];
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) {
+  for (int q = 0; q < RPL && MODE != 1; ++q) {
     const int i = r0 + q * 64 + lane;
     in[q] = i < d;
     const long e = i + (long)p * d;
@@ -1100,7 +1184,8 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
     }
   }
   bool acc = false;
-  if (a.do_accept) {
+  if (MODE == 2 && a.do_accept) acc = a.acc_out[p] != 0;
+  if (MODE != 2 && a.do_accept) {
     // exact log density of the proposal: target partials (of this chain, or
     // of its survivor slot under delayed acceptance) plus the prior
     const bool live = !a.da || a.pass1[p];
@@ -1143,6 +1228,7 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
       if (live && isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
     }
   }
+  if (MODE == 1) return;
   double zacc = 0.0, xacc = 0.0;
   double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1163,8 +1249,18 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
     }
     if (a.do_propose) {
       const double xp = propose1(xr[q], xv, a.rho, xn[q]);
-      if (a.v32) ((float*)a.V)[e] = (float)(xp - mu[q]);
-      else V[e] = (VT)(xp - mu[q]);
+      if (a.v3) {
+        u16 h, m, l;
+        split3((float)(xp - mu[q]), h, m, l);
+        const long n = (long)d * P;
+        a.v3[e] = h;
+        a.v3[n + e] = m;
+        a.v3[2 * n + e] = l;
+      } else if (a.v32) {
+        ((float*)a.V)[e] = (float)(xp - mu[q]);
+      } else {
+        V[e] = (VT)(xp - mu[q]);
+      }
       const double zp = __fma_rn(a.c, wn[q], a.rho * zv);
       zacc = __fma_rn(zp, zp, zacc);
       xacc = __fma_rn(xp, xp, xacc);
@@ -1186,16 +1282,155 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   }
 }
 
+// Paired-row loads and stores for the update half (d even, so that every
+// chain's column starts on an even element): lane l owns rows 2l, 2l + 1 of
+// its 128-row chunk and moves them with 16-, 8- or 4-byte accesses.
+template <int PR> struct Pair2;
+template <> struct Pair2<P64> { typedef double2 XI; typedef double2 W; };
+template <> struct Pair2<P32> { typedef float2 XI; typedef float2 W; };
+template <> struct Pair2<PMIX> { typedef float2 XI; typedef uint32_t W; };
+
 template <int PR>
-__global__ __launch_bounds__(256) void k_step(StepArgs a) {
-  step_body<PR>(a, blockIdx.x, gridDim.x, blockIdx.y);
+DEV void load_w2(const void* w, const void* wlo, long e, double& w0, double& w1) {
+  if (PR == P64) {
+    const double2 v = *(const double2*)((const double*)w + e);
+    w0 = v.x; w1 = v.y;
+  } else if (PR == P32) {
+    const float2 v = *(const float2*)((const float*)w + e);
+    w0 = v.x; w1 = v.y;
+  } else {
+    const uint32_t h = *(const uint32_t*)((const u16*)w + e), l = *(const uint32_t*)((const u16*)wlo + e);
+    w0 = (double)bf16_bits_to_f32((u16)(h & 0xffff)) + (double)bf16_bits_to_f32((u16)(l & 0xffff));
+    w1 = (double)bf16_bits_to_f32((u16)(h >> 16)) + (double)bf16_bits_to_f32((u16)(l >> 16));
+  }
 }
 
+template <int PR>
+DEV void load_xi2(const void* xi, long e, double& v0, double& v1) {
+  if (PR == P64) {
+    const double2 v = *(const double2*)((const double*)xi + e);
+    v0 = v.x; v1 = v.y;
+  } else {
+    const float2 v = *(const float2*)((const float*)xi + e);
+    v0 = v.x; v1 = v.y;
+  }
+}
+
+template <int PR>
+DEV void store_win2(void* win, long e, double v0, double v1) {
+  if (PR == P64) {
+    *(double2*)((double*)win + e) = make_double2(v0, v1);
+  } else if (PR == P32) {
+    *(float2*)((float*)win + e) = make_float2((float)v0, (float)v1);
+  } else {
+    *(uint32_t*)((u16*)win + e) = (uint32_t)f32_to_bf16_bits((float)v0) | ((uint32_t)f32_to_bf16_bits((float)v1) << 16);
+  }
+}
+
+template <int PR>
+DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = pq * 4 + w;
+  if (p >= a.P) return;
+  const int d = a.d, P = a.P;
+  const int i = ch * STEP_RCH + 2 * lane;
+  const bool in = i < d;  // d even: the pair lies wholly inside or outside
+  const long e = i + (long)p * d;
+  const bool acc = a.do_accept && a.acc_out[p] != 0;
+  double x0 = 0, x1 = 0, z0 = 0, z1 = 0, r0 = 0, r1 = 0;
+  double c0 = 0, c1 = 0, wc0 = 0, wc1 = 0, n0 = 0, n1 = 0, wn0 = 0, wn1 = 0, m0 = 0, m1 = 0;
+  if (in) {
+    const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e), rv = *(const double2*)(a.xr + i);
+    x0 = xv.x; x1 = xv.y; z0 = zv.x; z1 = zv.y; r0 = rv.x; r1 = rv.y;
+    if (acc) {
+      load_xi2<PR>(a.xi_cur, e, c0, c1);
+      load_w2<PR>(a.w_cur, a.wlo_cur, e, wc0, wc1);
+    }
+    if (a.do_propose) {
+      load_xi2<PR>(a.xi_nxt, e, n0, n1);
+      load_w2<PR>(a.w_nxt, a.wlo_nxt, e, wn0, wn1);
+      if (a.mu) {
+        const double2 mv = *(const double2*)(a.mu + i);
+        m0 = mv.x; m1 = mv.y;
+      }
+    }
+  }
+  double zacc = 0.0, xacc = 0.0;
+  double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
+  if (in) {
+    if (a.do_accept) {
+      if (acc) {
+        x0 = propose1(r0, x0, a.rho, c0);
+        x1 = propose1(r1, x1, a.rho, c1);
+        z0 = __fma_rn(a.c, wc0, a.rho * z0);
+        z1 = __fma_rn(a.c, wc1, a.rho * z1);
+        *(double2*)(a.X + e) = make_double2(x0, x1);
+        *(double2*)(a.Z + e) = make_double2(z0, z1);
+      }
+      store_win2<PR>(a.win, i + (a.win_col0 + p) * (long)d, x0 - r0, x1 - r1);
+      for (int k = 0; k < a.nproj; ++k) {
+        const double2 pv = *(const double2*)(a.proj + i + (long)k * d);
+        pacc[k] = __fma_rn(pv.y, x1, __fma_rn(pv.x, x0, pacc[k]));
+      }
+    }
+    if (a.do_propose) {
+      const double xp0 = propose1(r0, x0, a.rho, n0), xp1 = propose1(r1, x1, a.rho, n1);
+      if (a.v3) {
+        u16 h0, m0_, l0, h1, m1_, l1;
+        split3((float)(xp0 - m0), h0, m0_, l0);
+        split3((float)(xp1 - m1), h1, m1_, l1);
+        const long n = (long)d * P;
+        *(uint32_t*)(a.v3 + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        *(uint32_t*)(a.v3 + n + e) = (uint32_t)m0_ | ((uint32_t)m1_ << 16);
+        *(uint32_t*)(a.v3 + 2 * n + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      } else if (a.v32 || PR != P64) {
+        *(float2*)((float*)a.V + e) = make_float2((float)(xp0 - m0), (float)(xp1 - m1));
+      } else {
+        *(double2*)((double*)a.V + e) = make_double2(xp0 - m0, xp1 - m1);
+      }
+      const double zp0 = __fma_rn(a.c, wn0, a.rho * z0), zp1 = __fma_rn(a.c, wn1, a.rho * z1);
+      zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
+      xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
+    }
+  }
+  if (a.do_propose) {
+    zacc = wave_sum_f64(zacc);
+    if (lane == 0) a.zq_part_nxt[(long)p * nch + ch] = zacc;
+    if (a.prior_w > 0.0) {
+      xacc = wave_sum_f64(xacc);
+      if (lane == 0) a.pq_part_nxt[(long)p * nch + ch] = xacc;
+    }
+  }
+  if (a.do_accept && a.nproj > 0) {
+    for (int k = 0; k < a.nproj; ++k) {
+      const double v = wave_sum_f64(pacc[k]);
+      if (lane == 0) a.proj_part[((long)ch * a.nproj + k) * P + p] = v;
+    }
+  }
+}
+
+template <int PR, int MODE>
+__global__ __launch_bounds__(256) void k_step(StepArgs a, int nch) {
+  if (MODE == 2 && (a.d & 1) == 0) step_update2<PR>(a, blockIdx.x, nch, blockIdx.y);
+  else step_body<PR, MODE>(a, blockIdx.x, nch, blockIdx.y);
+}
+
+// A step with an accept half runs as a decision launch (one wave per chain)
+// followed by the streaming update; the first proposal of a call has no
+// decision.
 hipError_t step(const StepArgs& a, hipStream_t s) {
-  dim3 grid(step_chunks(a.d), cdiv(a.P, 4));
-  if (a.prec == P64) hipLaunchKernelGGL(k_step<P64>, grid, dim3(256), 0, s, a);
-  else if (a.prec == P32) hipLaunchKernelGGL(k_step<P32>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_step<PMIX>, grid, dim3(256), 0, s, a);
+  const int nch = step_chunks(a.d);
+  const dim3 gdec(1, cdiv(a.P, 4)), gupd(nch, cdiv(a.P, 4));
+  if (a.prec == P64) {
+    if (a.do_accept) hipLaunchKernelGGL((k_step<P64, 1>), gdec, dim3(256), 0, s, a, nch);
+    hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, a, nch);
+  } else if (a.prec == P32) {
+    if (a.do_accept) hipLaunchKernelGGL((k_step<P32, 1>), gdec, dim3(256), 0, s, a, nch);
+    hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, a, nch);
+  } else {
+    if (a.do_accept) hipLaunchKernelGGL((k_step<PMIX, 1>), gdec, dim3(256), 0, s, a, nch);
+    hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, a, nch);
+  }
   return hipGetLastError();
 }
 
@@ -1346,6 +1581,7 @@ int g_tgt_bm(int cfg) {
   return bm[cfg];
 }
 
+template <int MODE>
 __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, const BTile* __restrict__ tl, BStep st) {
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
@@ -1392,11 +1628,16 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
     a.wlo_nxt = nullptr;
     a.zq_part_nxt = b.zq_part + (long)(tn & 1) * b.nch * P;
   }
-  step_body<P32>(a, t.a, b.nch, t.b);
+  if (MODE == 2 && (d & 1) == 0) step_update2<P32>(a, t.a, b.nch, t.b);
+  else step_body<P32, MODE>(a, t.a, b.nch, t.b);
 }
 
-hipError_t g_step(const BProb* pr, const BTile* tl, int ntiles, const BStep& st, hipStream_t s) {
-  hipLaunchKernelGGL(gk_step, dim3(ntiles), dim3(256), 0, s, pr, tl, st);
+// decision launch over (problem, 0, chain quad) tiles, then the update over
+// (problem, chunk, chain quad) tiles; the first proposal has no decision
+hipError_t g_step(const BProb* pr, const BTile* dec_tl, int ndec, const BTile* tl, int ntiles, const BStep& st,
+                  hipStream_t s) {
+  if (st.t >= 0) hipLaunchKernelGGL((gk_step<1>), dim3(ndec), dim3(256), 0, s, pr, dec_tl, st);
+  hipLaunchKernelGGL((gk_step<2>), dim3(ntiles), dim3(256), 0, s, pr, tl, st);
   return hipGetLastError();
 }
 

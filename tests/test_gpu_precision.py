@@ -55,9 +55,10 @@ LP_TOL = {"fp32": 1e-4, "mixed": 1e-4}
 S_TOL = {"fp32": 1e-5, "mixed": 5e-3}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed"])
-def test_per_stage_error_against_fp64(prec):
-    d, P, n_lag = 256, 32, 16
+@pytest.mark.parametrize("prec,P", [("fp32", 32), ("mixed", 32), ("mixed", 64)])
+def test_per_stage_error_against_fp64(prec, P):
+    # P = 64 takes the mixed form's split-bf16 target contraction (d, P whole tiles)
+    d, n_lag = 256, 16
     t, x0, s = make(d, P, n_lag, prec)
     o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), d, P, n_lag, 0.3, X=x0)
     S0, m0 = synth.gaussian_warm_moments(t)
@@ -107,7 +108,7 @@ def _moments_ok(t, X, k_sigma=4.0):
     """X: n x d x P states (window ends).  Means and second central moments of
     v^T x for coordinates, extreme eigenvectors and random unit vectors."""
     n, d, P = X.shape
-    V = np.concatenate([np.eye(d), t.Q[:, [0, -1]], synth.unit_vectors(d, 16, 5)], axis=1)
+    V = np.concatenate([np.eye(d)[:, : min(d, 32)], t.Q[:, [0, -1]], synth.unit_vectors(d, 16, 5)], axis=1)
     worst = 0.0
     for j in range(V.shape[1]):
         v = V[:, j]
@@ -119,9 +120,10 @@ def _moments_ok(t, X, k_sigma=4.0):
     return worst
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
-def test_posterior_moments_within_4se(prec):
-    d, P, n_lag, windows = 32, 256, 50, 40
+@pytest.mark.parametrize("prec,d,P", [("fp64", 32, 256), ("fp32", 32, 256), ("mixed", 32, 256), ("mixed", 128, 64)])
+def test_posterior_moments_within_4se(prec, d, P):
+    # (mixed, 128, 64) runs the split-bf16 target contraction
+    n_lag, windows = 50, 40
     t, x0, s = make(d, P, n_lag, prec, tseed=0, seed=7)
     ends = []
     for _ in range(windows):
