@@ -55,9 +55,9 @@ LP_TOL = {"fp32": 1e-4, "mixed": 1e-4}
 S_TOL = {"fp32": 1e-5, "mixed": 5e-3}
 
 
-@pytest.mark.parametrize("prec,P", [("fp32", 32), ("mixed", 32), ("mixed", 64)])
+@pytest.mark.parametrize("prec,P", [("fp32", 32), ("mixed", 32), ("mixed", 64), ("mixed", 128)])
 def test_per_stage_error_against_fp64(prec, P):
-    # P = 64 takes the mixed form's split-bf16 target contraction (d, P whole tiles)
+    # P = 64 and 128 take the mixed form's split-bf16 target contraction (64 and 128 tiles)
     d, n_lag = 256, 16
     t, x0, s = make(d, P, n_lag, prec)
     o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), d, P, n_lag, 0.3, X=x0)
