@@ -33,7 +33,7 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of the target kernels from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE runs scaled by a device copy's counters (see profiles/); a
 # kernel missing here has changed since its counters were taken.
-TRAFFIC = {}
+TRAFFIC = {"k_tgt_s3": 184.8e6}   # profiles/hbm_traffic_k_tgt_s3_d4096_P256.md (d=4096, P=256)
 
 
 def log(msg):
@@ -444,7 +444,8 @@ def main():
                               "column sums of Y^2)",
                     "bound": "mfma", "achieved": 6 * useful / dt / 1e12, "peak": PEAK["bf16"] / 1e12,
                     "unit": "TFLOP/s", "frac": 6 * useful / dt / PEAK["bf16"],
-                    "traffic": TRAFFIC.get("k_tgt_s3"), "avg_us": dt * 1e6, "launches": n_t,
+                    "traffic": TRAFFIC.get("k_tgt_s3") if (args.d, args.P) == (4096, 256) else None,
+                    "avg_us": dt * 1e6, "launches": n_t,
                     "useful_tflops": useful / dt / 1e12}
     else:
         tdt = "fp64" if args.precision == "fp64" else "fp32"
