@@ -88,7 +88,7 @@ Tiles build_tiles(const std::vector<int>& dims, int P, int n) {
   }
   v.clear();
   for (int g = 0; g < G; ++g)
-    for (int pq = 0; pq < cdivh(P, 4); ++pq) v.push_back({g, 0, pq});
+    for (int p = 0; p < P; ++p) v.push_back({g, 0, p});
   T.decide = T.add(v);
   v.clear();
   for (int g = 0; g < G; ++g)

@@ -652,6 +652,8 @@ DEV void h_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, 
   };
   const int wm = w % WGM, wn = w / WGM;
   const int lr = lane & 15, lk = lane >> 4;
+  // the ring may still be read by other waves from a previous call
+  asm volatile("s_barrier" ::: "memory");
   for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's copies of slice kt are done when at most the later

@@ -226,33 +226,42 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_trigemm_bf16w(const u16* __r
       }
 }
 // Direct-to-LDS hi/lo variant for operands that fill whole tiles (d a
-// multiple of TBN, ncols of TBM): the K range of a row tile ends at its last
-// row; the four products accumulate per 32-deep slice.
+// multiple of 2 TBN, ncols of TBM; 256 x 128 tiles on 8 waves, 3-stage ring): the K range of a row tile ends at its
+// last row, so row tiles ib and ni - 1 - ib together cost the same for every
+// pair; each workgroup takes one such pair of one column block of W (the
+// pairs of a column block run on one XCD, which keeps that block of W in its
+// L2).  The four products accumulate per 32-deep slice.
 template <int TBM, int TBN, int WGM, int WGN, int ST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_trigemm_hl(const u16* __restrict__ Lhi, const u16* __restrict__ Whi,
                                                               long dW, float* __restrict__ Xi, int d, int ncols, float c,
                                                               int nj, int ni) {
   typedef WFrag<TBM, TBN, WGM, WGN> F;
   __shared__ __attribute__((aligned(1024))) u16 lds[h_lds_elems<TBM, TBN, ST>()];
+  const int npair = ni / 2;
   const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
-  const int jb = (k / ni) * 8 + xcd;
+  const int jb = (k / npair) * 8 + xcd;
   if (jb >= nj) return;
-  const int ib = ni - 1 - (k % ni);
-  const int j0 = jb * TBM, i0 = ib * TBN;
-  const int kend = min(d, i0 + TBN);
-  F f;
-  f.zero();
-  h_gemm<TBM, TBN, WGM, WGN, ST>(f, Whi, dW, d, Lhi, (long)d * d, d, j0, i0, kend, lds);
+  const int q = k % npair;
+  const int j0 = jb * TBM;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int ib = h ? q : ni - 1 - q;
+    const int i0 = ib * TBN;
+    const int kend = min(d, i0 + TBN);
+    F f;
+    f.zero();
+    h_gemm<TBM, TBN, WGM, WGN, ST>(f, Whi, dW, d, Lhi, (long)d * d, d, j0, i0, kend, lds);
 #pragma unroll
-  for (int m = 0; m < F::FM; ++m)
+    for (int m = 0; m < F::FM; ++m)
 #pragma unroll
-    for (int n = 0; n < F::FN; ++n)
+      for (int n = 0; n < F::FN; ++n)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int tj, ti;
-        w_coords<TBM, TBN, WGM, WGN>(m, n, r, tj, ti);
-        Xi[(i0 + ti) + (long)(j0 + tj) * d] = c * f.c[m][n][r];
-      }
+        for (int r = 0; r < 4; ++r) {
+          int tj, ti;
+          w_coords<TBM, TBN, WGM, WGN>(m, n, r, tj, ti);
+          Xi[(i0 + ti) + (long)(j0 + tj) * d] = c * f.c[m][n][r];
+        }
+  }
 }
 
 // tile shape of the wide proposal kernel
@@ -273,16 +282,16 @@ hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, voi
     const long dW = (const u16*)Wlo - (const u16*)W;
     const int vec_ok = (d % 8 == 0) && ((uintptr_t)L % 16 == 0) && ((uintptr_t)W % 16 == 0) && ((uintptr_t)Wlo % 16 == 0);
     const bool whole = vec_ok && (ncols % 256 == 0);
-    if (whole && d % 256 == 0) {
+    if (whole && d % 512 == 0) {
       const int nj = ncols / 256, ni = d / 256, groups = (nj + 7) / 8;
-      hipLaunchKernelGGL((k_trigemm_hl<256, 256, 2, 4, 2>), dim3(groups * 8 * ni), dim3(512), 0, s, Lhi, (const u16*)W,
-                         dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
+      hipLaunchKernelGGL((k_trigemm_hl<256, 256, 2, 4, 2>), dim3(groups * 8 * (ni / 2)), dim3(512), 0, s, Lhi,
+                         (const u16*)W, dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
       return hipGetLastError();
     }
-    if (whole && d % 128 == 0) {
+    if (whole && d % 256 == 0) {
       const int nj = ncols / 256, ni = d / 128, groups = (nj + 7) / 8;
-      hipLaunchKernelGGL((k_trigemm_hl<256, 128, 4, 2, 3>), dim3(groups * 8 * ni), dim3(512), 0, s, Lhi, (const u16*)W,
-                         dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
+      hipLaunchKernelGGL((k_trigemm_hl<256, 128, 4, 2, 3>), dim3(groups * 8 * (ni / 2)), dim3(512), 0, s, Lhi,
+                         (const u16*)W, dW, (float*)Xi, d, (int)ncols, (float)c, nj, ni);
       return hipGetLastError();
     }
     const int nj = cdiv(ncols, TW_BM), ni = cdiv(d, TW_BN), groups = (nj + 7) / 8;
@@ -1288,6 +1297,66 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
   }
 }
 
+// Sum over the 256 threads of a workgroup in a fixed order (every thread
+// gets the result).  red: 4 doubles of LDS.
+DEV double block_sum_f64(double v, double* red) {
+  v = wave_sum_f64(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Decision of chain p by one workgroup of 256 threads: the target partials
+// (thousands of row blocks for the logistic target) are summed by all
+// threads, then MH (or the second stage of delayed acceptance) decides.
+DEV void decide_block(const StepArgs& a, int nch, int p) {
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  const bool live = !a.da || a.pass1[p];
+  const int col = a.da ? a.slot[p] : p;
+  double s = 0.0;
+  if (live)
+    for (int q = t; q < a.nrb; q += 256) s += a.lpp_part[(long)col * a.nrb + q];
+  s = block_sum_f64(s, red);
+  if (a.prior_w > 0.0) {
+    double pq = 0.0;
+    for (int q = t; q < nch; q += 256) pq += a.pq_part_cur[(long)p * nch + q];
+    pq = block_sum_f64(pq, red);
+    s = __fma_rn(-a.prior_w, pq, s);
+  }
+  const double lpp = s;
+  double zs = 0.0;
+  for (int q = t; q < nch; q += 256) zs += a.zq_part_cur[(long)p * nch + q];
+  zs = block_sum_f64(zs, red);
+  if (t != 0) return;
+  const double lp = a.lp_cur[p], zq = a.zq_cur[p];
+  double la;
+  bool acc;
+  if (!a.da) {
+    la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
+    acc = log(a.u[p]) < la;  // NaN compares false: rejected
+  } else {
+    // second stage: log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x)),
+    // with s = r - |z|^2/(2 alpha^2) in the residual form (r = network)
+    double l2 = (lpp - lp) - (a.s_new[p] - a.s_in[p]);
+    if (a.da_resid) l2 += (zs - zq) * a.inv2a2;
+    la = live ? l2 : -INFINITY;
+    acc = live && (log(a.u2[p]) < la);
+  }
+  a.lp_nxt[p] = acc ? lpp : lp;
+  a.zq_nxt[p] = acc ? zs : zq;
+  a.nacc[p] += acc ? 1 : 0;
+  a.la_out[p] = la;
+  a.acc_out[p] = acc ? 1 : 0;
+  if (a.da) a.s_out[p] = acc ? a.s_new[p] : a.s_in[p];
+  if (a.trace_lp) a.trace_lp[p] = acc ? lpp : lp;
+  if (live && isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
+}
+
+__global__ __launch_bounds__(256) void k_decide(StepArgs a, int nch) { decide_block(a, nch, blockIdx.x); }
+
 // Paired-row loads and stores for the update half (d even, so that every
 // chain's column starts on an even element): lane l owns rows 2l, 2l + 1 of
 // its 128-row chunk and moves them with 16-, 8- or 4-byte accesses.
@@ -1426,17 +1495,11 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a, int nch) {
 // decision.
 hipError_t step(const StepArgs& a, hipStream_t s) {
   const int nch = step_chunks(a.d);
-  const dim3 gdec(1, cdiv(a.P, 4)), gupd(nch, cdiv(a.P, 4));
-  if (a.prec == P64) {
-    if (a.do_accept) hipLaunchKernelGGL((k_step<P64, 1>), gdec, dim3(256), 0, s, a, nch);
-    hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, a, nch);
-  } else if (a.prec == P32) {
-    if (a.do_accept) hipLaunchKernelGGL((k_step<P32, 1>), gdec, dim3(256), 0, s, a, nch);
-    hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, a, nch);
-  } else {
-    if (a.do_accept) hipLaunchKernelGGL((k_step<PMIX, 1>), gdec, dim3(256), 0, s, a, nch);
-    hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, a, nch);
-  }
+  const dim3 gupd(nch, cdiv(a.P, 4));
+  if (a.do_accept) hipLaunchKernelGGL(k_decide, dim3(a.P), dim3(256), 0, s, a, nch);
+  if (a.prec == P64) hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, a, nch);
+  else if (a.prec == P32) hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, a, nch);
+  else hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, a, nch);
   return hipGetLastError();
 }
 
@@ -1634,12 +1697,14 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
     a.wlo_nxt = nullptr;
     a.zq_part_nxt = b.zq_part + (long)(tn & 1) * b.nch * P;
   }
-  if (MODE == 2 && (d & 1) == 0) step_update2<P32>(a, t.a, b.nch, t.b);
-  else step_body<P32, MODE>(a, t.a, b.nch, t.b);
+  if (MODE == 1) decide_block(a, b.nch, t.b);
+  else if ((d & 1) == 0) step_update2<P32>(a, t.a, b.nch, t.b);
+  else step_body<P32, 2>(a, t.a, b.nch, t.b);
 }
 
-// decision launch over (problem, 0, chain quad) tiles, then the update over
-// (problem, chunk, chain quad) tiles; the first proposal has no decision
+// decision launch over (problem, 0, chain) tiles (a workgroup per chain),
+// then the update over (problem, chunk, chain quad) tiles; the first
+// proposal has no decision
 hipError_t g_step(const BProb* pr, const BTile* dec_tl, int ndec, const BTile* tl, int ntiles, const BStep& st,
                   hipStream_t s) {
   if (st.t >= 0) hipLaunchKernelGGL((gk_step<1>), dim3(ndec), dim3(256), 0, s, pr, dec_tl, st);
