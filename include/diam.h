@@ -290,8 +290,9 @@ int diam_batch_autotune(diam_batch* b, int32_t reps, int32_t* choice, double* us
 /* Graph capture of the window on (default) or off (eager launches). */
 int diam_batch_set_graph(diam_batch* b, int32_t on);
 /* Per-problem fields at a window boundary: DIAM_F_X, Z, LOGP, ZQ, XREF, L, S,
- * M, LA, ACC (last window, n_lag x P), NACC, W (last window's normals, d x
- * P n_lag f32), U (last window's uniforms, n_lag x P f64). */
+ * M, LA, ACC (last window, n_lag x P), NACC, W (last window's normals, ld x
+ * P n_lag f32 with ld = d rounded up to a multiple of 4; rows >= d unused),
+ * U (last window's uniforms, n_lag x P f64). */
 int diam_batch_field_bytes(diam_batch* b, int32_t g, int32_t field, size_t* bytes);
 int diam_batch_get(diam_batch* b, int32_t g, int32_t field, void* dst, size_t bytes);
 /* steps, windows and n_samples of the batch (the other members are not used). */

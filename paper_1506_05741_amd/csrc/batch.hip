@@ -40,6 +40,8 @@ constexpr int NB = dk::CHOL_NB;
 
 inline int cdivh(long a, long b) { return (int)((a + b - 1) / b); }
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+// leading dimension of the padded target and proposal operands (16-byte rows)
+inline int pad4(int d) { return (d + 3) & ~3; }
 
 struct Seg {
   long off = 0;
@@ -48,7 +50,7 @@ struct Seg {
 
 // Workspace offsets of one problem.
 struct PLay {
-  size_t X, Z, xr, lp, zq, zq_part, lpp_part, la, acc, V, Xi, win, S, m, L, C, Linv, G, h, Llow, nacc;
+  size_t X, Z, xr, lp, zq, zq_part, lpp_part, la, acc, V, Xi, win, S, m, L, C, Linv, G, h, Llow, nacc, Rp, Vp, Lp;
 };
 
 struct BLay {
@@ -167,7 +169,7 @@ BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles) {
   L.nW = 0;
   for (int g = 0; g < G; ++g) {
     L.Woff.push_back((size_t)L.nW);
-    L.nW += (long)dims[g] * P * n;
+    L.nW += (long)pad4(dims[g]) * P * n;
     L.nW = (L.nW + 63) / 64 * 64;  // 256-byte aligned problem slices
   }
   L.nU = (long)G * n * P;
@@ -194,7 +196,7 @@ BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles) {
     q.la = take((size_t)n * P * 8);
     q.acc = take((size_t)n * P);
     q.V = take(dP * 4);
-    q.Xi = take(win * 4);
+    q.Xi = take((size_t)pad4(dims[g]) * P * n * 4);
     q.win = take(win * 4);
     q.S = take(dd * 8);
     q.m = take(d * 8);
@@ -205,6 +207,10 @@ BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles) {
     q.h = take(d * 8);
     q.Llow = take(dd * 4);
     q.nacc = take((size_t)P * 4);
+    const size_t ld = pad4(dims[g]);
+    q.Rp = take(ld * ld * 4);
+    q.Vp = take(ld * P * 4);
+    q.Lp = take(ld * ld * 4);
     L.p.push_back(q);
   }
   L.total = o;
@@ -232,6 +238,18 @@ __global__ void k_bfill_identity(double* L, int d) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e < (long)d * d) L[e] = ((e % d) == (e / d)) ? 1.0 : 0.0;
 }
+// zero-padded copies for the target tiles: Rp (ld x ld) from R (d x d,
+// row-major) and Vp (ld x P) from V (d x P)
+__global__ void k_pad_rows(const float* src, int d, long ncols, int ld, float* dst, int rowmajor) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)ld * ncols) return;
+  const int r = (int)(e % ld);
+  const long c = e / ld;
+  float v = 0.f;
+  if (r < d && c < (rowmajor ? d : ncols)) v = src[r + c * d];
+  dst[e] = v;
+}
+
 __global__ void k_bzero(char* p, long n) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e < n) p[e] = 0;
@@ -379,6 +397,10 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
     p.Llow = (float*)(w + q.Llow);
     p.nacc = (int*)(w + q.nacc);
     p.info = b->info + g;
+    p.ld = pad4(dv[g]);
+    p.Rp = (const float*)(w + q.Rp);
+    p.Vp = (float*)(w + q.Vp);
+    p.Lp = (float*)(w + q.Lp);
   }
   set_nrb(b);
   hipStream_t s = b->user;
@@ -404,7 +426,18 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
     hipLaunchKernelGGL(k_bzero, dim3(cdivh(d * 8, 256)), dim3(256), 0, s, (char*)p.m, (long)d * 8);
     hipLaunchKernelGGL(k_bzero, dim3(cdivh(P * 4, 256)), dim3(256), 0, s, (char*)p.nacc, (long)P * 4);
     BCHK_INIT(dk::round_factor(dk::P32, p.L, p.Llow, d, s));
+    hipLaunchKernelGGL(k_pad_rows, dim3(cdivh((long)p.ld * p.ld, 256)), dim3(256), 0, s, (const float*)p.Llow, d,
+                       (long)p.ld, p.ld, p.Lp, 1);
     BCHK_INIT(dk::init_eval(0, p.X, p.mu, p.V, p.Z, d, P, s));
+    {
+      const long nr = (long)p.ld * p.ld, nv = (long)p.ld * P;
+      // row-major R: element (i, k) at i d + k -> treat as column k' = i of length d
+      hipLaunchKernelGGL(k_pad_rows, dim3(cdivh(nr, 256)), dim3(256), 0, s, p.R, d, (long)p.ld, p.ld, (float*)p.Rp,
+                         1);
+      hipLaunchKernelGGL(k_pad_rows, dim3(cdivh(nv, 256)), dim3(256), 0, s, (const float*)p.V, d, (long)P, p.ld,
+                         p.Vp, 0);
+      BCHK_INIT(hipGetLastError());
+    }
     BCHK_INIT(dk::tgt_gauss(dk::P32, p.R, p.V, d, P, p.lpp_part, s));
     BCHK_INIT(dk::init_finish(p.lpp_part, dk::tgt_row_blocks(d), p.Z, p.X, 0.0, p.lp, p.zq, d, P, s));
   }
@@ -453,6 +486,9 @@ static int retry_failed(diam_batch* b, int32_t* jitter, int* any_fail) {
       if (j < b->cfg.jitter_tries) {
         BCHK(hipMemcpyAsync(p.L, p.C, (size_t)d * d * 8, hipMemcpyDeviceToDevice, s));
         BCHK(dk::round_factor(dk::P32, p.L, p.Llow, d, s));
+        hipLaunchKernelGGL(k_pad_rows, dim3(cdivh((long)p.ld * p.ld, 256)), dim3(256), 0, s, (const float*)p.Llow, d,
+                           (long)p.ld, p.ld, p.Lp, 1);
+        BCHK(hipGetLastError());
         BCHK(hipMemcpyAsync(p.xr, p.m, (size_t)d * 8, hipMemcpyDeviceToDevice, s));
         BCHK(dk::trsm_whiten(p.L, p.X, p.xr, p.Z, p.zq, p.Linv, d, b->P, s));
       } else {
@@ -694,7 +730,7 @@ static int bfield(diam_batch* b, int32_t g, int32_t f, const void** src, size_t*
     case DIAM_F_LA: *src = p.la; *bytes = n * P * 8; break;
     case DIAM_F_ACC: *src = p.acc; *bytes = n * P; break;
     case DIAM_F_NACC: *src = p.nacc; *bytes = P * 4; break;
-    case DIAM_F_W: *src = p.W; *bytes = d * P * n * 4; break;
+    case DIAM_F_W: *src = p.W; *bytes = (size_t)p.ld * P * n * 4; break;  // rows padded to ld
     case DIAM_F_U: *src = b->U_all + (long)g * n * P; *bytes = n * P * 8; break;
     default: return bfail(DIAM_E_ARG, "field %d is not kept by the batched form", f);
   }

@@ -199,8 +199,8 @@ DEV void e_loop(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, c
 // buffer, so each SIMD runs KG wavefronts; at the end the groups' partial
 // accumulators are added into group 0 in fixed order (deterministic).  Only
 // group 0's accumulators hold the result.  lds: KG * e_lds_elems elements.
-// Tiles that lie inside both operands with whole, aligned BK-slices take the
-// unguarded fast loop.
+// Tiles that lie inside both operands with aligned rows take the unguarded
+// fast loop over whole rounds of KG slices and a guarded loop for the rest.
 template <typename T, int BM, int BN, int BK, bool AKC, bool BKC, int KG = 1>
 DEV void e_gemm(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, const T* __restrict__ B, long ldb,
                 int N, int i0, int j0, int kbeg, int kend, T* lds) {
@@ -212,10 +212,22 @@ DEV void e_gemm(EFrag<T, BM, BN>& f, const T* __restrict__ A, long lda, int M, c
   const int nit = (nk + KG - 1) / KG;
   const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % VEC == 0) && ((uintptr_t)B % 16 == 0) &&
                        (ldb % VEC == 0) && (kbeg % VEC == 0);
-  const bool fast = aligned && (i0 + BM <= M) && (j0 + BN <= N) && ((kend - kbeg) % (BK * KG) == 0);
+  const bool fast = aligned && (i0 + BM <= M) && (j0 + BN <= N);
   if (nit > 0) {
-    if (fast) e_loop<T, BM, BN, BK, AKC, BKC, true>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kend, base, g, t, KG, nit);
-    else e_loop<T, BM, BN, BK, AKC, BKC, false>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kend, base, g, t, KG, nit);
+    if (fast) {
+      // whole rounds of KG slices unguarded, the remaining slices guarded;
+      // slice s still goes to k-group s % KG, as in a single guarded loop
+      const int nfull = (kend - kbeg) / (BK * KG);
+      const int kmid = kbeg + nfull * BK * KG;
+      if (nfull > 0)
+        e_loop<T, BM, BN, BK, AKC, BKC, true>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kmid, base, g, t, KG, nfull);
+      if (kmid < kend) {
+        const int nit2 = ((kend - kmid + BK - 1) / BK + KG - 1) / KG;
+        e_loop<T, BM, BN, BK, AKC, BKC, false>(f, A, lda, M, B, ldb, N, i0, j0, kmid, kend, base, g, t, KG, nit2);
+      }
+    } else {
+      e_loop<T, BM, BN, BK, AKC, BKC, false>(f, A, lda, M, B, ldb, N, i0, j0, kbeg, kend, base, g, t, KG, nit);
+    }
   }
   if (KG > 1) {
     constexpr int FM = EFrag<T, BM, BN>::FM, FN = EFrag<T, BM, BN>::FN;

@@ -142,6 +142,8 @@ struct StepArgs {
   const double* u2;                       // P
   int da_resid;                           // residual surrogate r(x) - |z|^2/(2 alpha^2)
   uint16_t* v3;                           // non-null: write V as three bf16 parts (d x P each) instead
+  int ldv;                                // leading dimension of V (0: d)
+  int ldw;                                // leading dimension of Xi and W (0: d)
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
 
@@ -158,12 +160,16 @@ hipError_t proj_reduce(const double* proj_part, int n, int nch, int nproj, int P
 // Per-problem device buffers (FP64 state and moments, FP32 operands).
 struct BProb {
   int d, nch, nrb, nb;              // dimension, step chunks, target row blocks, Cholesky blocks
+  int ld;                           // d rounded up to a multiple of 4 (padded target operands)
   const float* R;                   // d x d row-major
+  const float* Rp;                  // R zero-padded to ld x ld (16-byte rows for the target tiles)
+  float* Vp;                        // ld x P, x' - mu with zero padding rows
+  float* Lp;                        // FP32 factor zero-padded to ld x ld (column-major)
   const double* mu;                 // d
   double *X, *Z, *xr, *lp, *zq;     // d x P, d x P, d, 2 x P, 2 x P
   double *zq_part, *lpp_part, *la;  // 2 x P x nch, P x nrb, n x P
   uint8_t* acc;                     // n x P
-  float *V, *W, *Xi, *win;          // d x P, d x P n (x3)
+  float *V, *W, *Xi, *win;          // d x P; W and Xi ld x P n; win d x P n
   double *S, *m, *L, *C, *Linv, *G, *h;
   float* Llow;                      // d x d
   int *nacc, *info;

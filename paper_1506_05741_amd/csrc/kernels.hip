@@ -1187,13 +1187,14 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
       x[q] = a.X[e];
       z[q] = a.Z[e];
       xr[q] = a.xr[i];
+      const long ew = i + (long)p * (a.ldw ? a.ldw : d);
       if (a.do_accept) {
-        xc[q] = (double)xi_cur[e];
-        wc[q] = load_w<PR>(a.w_cur, a.wlo_cur, e);
+        xc[q] = (double)xi_cur[ew];
+        wc[q] = load_w<PR>(a.w_cur, a.wlo_cur, ew);
       }
       if (a.do_propose) {
-        xn[q] = (double)xi_nxt[e];
-        wn[q] = load_w<PR>(a.w_nxt, a.wlo_nxt, e);
+        xn[q] = (double)xi_nxt[ew];
+        wn[q] = load_w<PR>(a.w_nxt, a.wlo_nxt, ew);
         mu[q] = a.mu ? a.mu[i] : 0.0;
       }
     }
@@ -1271,10 +1272,10 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
         a.v3[e] = h;
         a.v3[n + e] = m;
         a.v3[2 * n + e] = l;
-      } else if (a.v32) {
-        ((float*)a.V)[e] = (float)(xp - mu[q]);
       } else {
-        V[e] = (VT)(xp - mu[q]);
+        const long ev = i + (long)p * (a.ldv ? a.ldv : d);
+        if (a.v32) ((float*)a.V)[ev] = (float)(xp - mu[q]);
+        else V[ev] = (VT)(xp - mu[q]);
       }
       const double zp = __fma_rn(a.c, wn[q], a.rho * zv);
       zacc = __fma_rn(zp, zp, zacc);
@@ -1417,13 +1418,14 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
   if (in) {
     const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e), rv = *(const double2*)(a.xr + i);
     x0 = xv.x; x1 = xv.y; z0 = zv.x; z1 = zv.y; r0 = rv.x; r1 = rv.y;
+    const long ew = i + (long)p * (a.ldw ? a.ldw : d);
     if (acc) {
-      load_xi2<PR>(a.xi_cur, e, c0, c1);
-      load_w2<PR>(a.w_cur, a.wlo_cur, e, wc0, wc1);
+      load_xi2<PR>(a.xi_cur, ew, c0, c1);
+      load_w2<PR>(a.w_cur, a.wlo_cur, ew, wc0, wc1);
     }
     if (a.do_propose) {
-      load_xi2<PR>(a.xi_nxt, e, n0, n1);
-      load_w2<PR>(a.w_nxt, a.wlo_nxt, e, wn0, wn1);
+      load_xi2<PR>(a.xi_nxt, ew, n0, n1);
+      load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, wn0, wn1);
       if (a.mu) {
         const double2 mv = *(const double2*)(a.mu + i);
         m0 = mv.x; m1 = mv.y;
@@ -1458,10 +1460,10 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
         *(uint32_t*)(a.v3 + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
         *(uint32_t*)(a.v3 + n + e) = (uint32_t)m0_ | ((uint32_t)m1_ << 16);
         *(uint32_t*)(a.v3 + 2 * n + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
-      } else if (a.v32 || PR != P64) {
-        *(float2*)((float*)a.V + e) = make_float2((float)(xp0 - m0), (float)(xp1 - m1));
       } else {
-        *(double2*)((double*)a.V + e) = make_double2(xp0 - m0, xp1 - m1);
+        const long ev = i + (long)p * (a.ldv ? a.ldv : d);
+        if (a.v32 || PR != P64) *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - m0), (float)(xp1 - m1));
+        else *(double2*)((double*)a.V + ev) = make_double2(xp0 - m0, xp1 - m1);
       }
       const double zp0 = __fma_rn(a.c, wn0, a.rho * z0), zp1 = __fma_rn(a.c, wn1, a.rho * z1);
       zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
@@ -1631,7 +1633,7 @@ template <int BM, int KG>
 __global__ __launch_bounds__(256 * KG) void gk_tgt(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int P) {
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
-  tgt_gauss_tile<float, 32, BM, 32, KG>(b.R, b.V, b.d, P, t.a, t.b, b.lpp_part, b.nrb);
+  tgt_gauss_tile<float, 32, BM, 32, KG>(b.Rp, b.Vp, b.ld, P, t.a, t.b, b.lpp_part, b.nrb);
 }
 
 hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s) {
@@ -1655,7 +1657,7 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
   const int P = st.P, d = b.d, cu = st.t & 1, nx = cu ^ 1;
-  const long dP = (long)d * P;
+  const long dP = (long)b.ld * P;  // one step's slice of W and Xi (padded rows)
   StepArgs a{};
   a.d = d;
   a.P = P;
@@ -1667,7 +1669,9 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
   a.mu = b.mu;
   a.X = b.X;
   a.Z = b.Z;
-  a.V = b.V;
+  a.V = b.Vp;
+  a.ldv = b.ld;
+  a.ldw = b.ld;
   a.nrb = b.nrb;
   a.lpp_part = b.lpp_part;
   a.nacc = b.nacc;
@@ -1716,7 +1720,7 @@ __global__ __launch_bounds__(256) void gk_trigemm(const BProb* __restrict__ pr, 
                                                   double c) {
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
-  trigemm_tile<float, 32>(b.Llow, b.W, b.Xi, b.d, ncols, c, t.a, t.b);
+  trigemm_tile<float, 32>(b.Lp, b.W, b.Xi, b.ld, ncols, c, t.a, t.b);
 }
 
 hipError_t g_trigemm(const BProb* pr, const BTile* tl, int ntiles, int ncols, double c, hipStream_t s) {
@@ -1821,6 +1825,7 @@ __global__ __launch_bounds__(256) void gk_adopt(const BProb* __restrict__ pr, co
   if (e < (long)b.d * b.d) {
     b.L[e] = b.C[e];
     round_factor_elem(P32, b.L, b.Llow, b.d, e);
+    b.Lp[(e % b.d) + (e / b.d) * b.ld] = b.Llow[e];
   }
   if (e < b.d) b.xr[e] = b.m[e];
 }

@@ -76,7 +76,8 @@ def test_batch_matches_separate_samplers():
         st, jit = b.window()
         assert st == diam.OK
         for g, (t, s) in enumerate(zip(ts, singles)):
-            W = b.get(g, diam.F_W).view(torch.float32).double().reshape(n_lag, P, t.d).contiguous()
+            ld = (t.d + 3) // 4 * 4                         # the batch keeps normals in rows padded to 4
+            W = b.get(g, diam.F_W).view(torch.float32).reshape(n_lag, P, ld)[:, :, : t.d].double().contiguous()
             U = b.get(g, diam.F_U).view(torch.float64).reshape(n_lag, P).contiguous()
             s.step_batch(n_lag, W, U)
             assert torch.equal(b.get(g, diam.F_ACC), s.get(diam.F_ACC)), (w, g)
