@@ -616,15 +616,18 @@ DEV void w_gemm_seg(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long 
 // global_load_lds_dwordx4 (no staging registers; ST - 1 slices in flight),
 // and every fragment read from LDS feeds two of the four products.  Each
 // wave-wide copy fills 1 KB of LDS = 16 rows x 4 chunks of 16 bytes; chunk c
-// of row r sits at position c ^ ((r >> 2) & 3), which spreads the 16 rows a
-// quarter-wavefront reads over distinct banks.  Unguarded: the caller
+// of row r sits at position c ^ hswz(r).  The swizzle puts the rows that one
+// LDS cycle serves on distinct banks whether a 16-byte read is served 8 or 16
+// lanes at a time (rows r and r + 2 share the 128-byte bank row of 64-byte
+// rows, rows r and r + 4 the 256-byte one); it depends on r mod 16 only, so
+// global and tile-local row numbers give the same placement.  Unguarded: the caller
 // guarantees that all rows and the whole K range lie inside the operands
 // (K a multiple of 32) and that rows start on 16-byte boundaries.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 constexpr int HBK = 32;
 
-DEV int hswz(int r) { return (r >> 2) & 3; }
+DEV int hswz(int r) { return ((r >> 2) ^ (r >> 1)) & 3; }
 
 DEV void h_copy_block(const u16* __restrict__ p, long ld, int r0, int k0, u16* lds_block) {
   const int lane = threadIdx.x & 63;
@@ -704,12 +707,12 @@ DEV void h_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, 
 }
 
 // Plain BF16 engine with direct-to-LDS loads (one part per operand): 64-deep
-// K slices, chunk c of row r at position c ^ ((r >> 1) & 7) (8 chunks per
-// row), ST-stage ring.  K range [kbeg, kend), both multiples of 64;
+// K slices, chunk c of row r at position c ^ pswz(r) (8 chunks per 128-byte
+// row, conflict-free for 8 or 16 lanes per LDS cycle like hswz), ST-stage ring.  K range [kbeg, kend), both multiples of 64;
 // unguarded like h_gemm.
 constexpr int PBK = 64;
 
-DEV int pswz(int r) { return (r >> 1) & 7; }
+DEV int pswz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 DEV void p_copy_block(const u16* __restrict__ p, long ld, int r0, int k0, u16* lds_block) {
   const int lane = threadIdx.x & 63;
