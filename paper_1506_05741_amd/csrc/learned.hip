@@ -36,7 +36,11 @@ __global__ __launch_bounds__(512) void k_tgt_logreg(const float* __restrict__ A,
   if (rb >= nrb || j0 >= nact) return;  // uniform per workgroup, before any barrier
   EFrag<float, BM, BN> f;
   f.zero();
-  e_gemm<float, BM, BN, BK, true, true, KG>(f, A, d, n_obs, V, d, nact, i0, j0, 0, d, lds);
+  // V always holds P columns (under delayed acceptance the survivors packed
+  // first, the rest stale but readable), so the loads are bounded by P and a
+  // partly filled last tile keeps the unguarded vector path; only columns
+  // below nact are written
+  e_gemm<float, BM, BN, BK, true, true, KG>(f, A, d, n_obs, V, d, P, i0, j0, 0, d, lds);
   const bool g0 = threadIdx.x < NT;
   const int lane = threadIdx.x & 63, w = (threadIdx.x & (NT - 1)) >> 6, wm = w & 1, wn = w >> 1;
   if (g0) {
