@@ -712,7 +712,9 @@ hipError_t cov_assemble(const double* S, const double* m, double eps, double* C,
 //   k_chol_diag   one wavefront factors the 64 x 64 diagonal block with its
 //                 rows in registers and forms the block's inverse;
 //   k_chol_panel  MFMA: A_ij <- A_ij L_jj^-T as a product with that inverse;
-//   k_chol_update MFMA: trailing lower tiles A_ik -= A_ij A_kj^T.
+//   k_chol_update_diag MFMA: trailing lower tiles A_ik -= A_ij A_kj^T, and
+//                 the next diagonal block factored by the workgroup that
+//                 updated it.
 // ============================================================================
 
 // Inverse of the lower-triangular 64 x 64 block held in Ls (row-major, LDS):
@@ -743,12 +745,21 @@ DEV double readlane_f64(double v, int src) {
 // barrier per step), and every lane applies the rank-1 update to its whole
 // row without per-element masks: entries right of the diagonal collect
 // values that are never read (the broadcast and the stores mask them).
-DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
-                         int* __restrict__ info) {
-  __shared__ double colv[2][CHOL_NB];
-  __shared__ double Ls[CHOL_NB][CHOL_NB + 1];
-  __shared__ double rdiag[CHOL_NB];
+// The first wavefront of the workgroup does the work; further wavefronts
+// (when the block is factored inside a larger workgroup) only take part in
+// the barriers and touch no memory.
+// LDS: two column buffers of 2 CHOL_NB (the second half takes the stores of
+// the idle wavefronts, so the store in the unrolled loop needs no branch),
+// the factored block, the reciprocal diagonal.
+constexpr int CHOL_DIAG_LDS = 4 * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB;  // doubles
+
+DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
+                        int* __restrict__ info, double* sh) {
+  double (*colv)[2 * CHOL_NB] = (double (*)[2 * CHOL_NB])sh;
+  double (*Ls)[CHOL_NB + 1] = (double (*)[CHOL_NB + 1])(sh + 4 * CHOL_NB);
+  double* rdiag = sh + 4 * CHOL_NB + CHOL_NB * (CHOL_NB + 1);
   const int r = threadIdx.x;
+  const bool act = r < CHOL_NB;
   double a[CHOL_NB];
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
@@ -766,7 +777,7 @@ DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* 
     const double sq = sqrt(piv);
     const double l = (r == c) ? sq : a[c] * (1.0 / sq);
     a[c] = l;
-    colv[c & 1][r] = (r >= c) ? l : 0.0;
+    colv[c & 1][act ? r : CHOL_NB + (r & (CHOL_NB - 1))] = (r >= c) ? l : 0.0;
     __syncthreads();
 #pragma unroll
     for (int q = c + 1; q < CHOL_NB; ++q) a[q] = __fma_rn(-l, colv[c & 1][q], a[q]);
@@ -776,20 +787,30 @@ DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* 
     for (int c = 0; c < CHOL_NB; ++c)
       if (c < jn) A[(j0 + r) + (long)(j0 + c) * d] = (c <= r) ? a[c] : 0.0;
   }
+  if (act) {
 #pragma unroll
-  for (int c = 0; c < CHOL_NB; ++c) Ls[r][c] = (c <= r) ? a[c] : 0.0;
+    for (int c = 0; c < CHOL_NB; ++c) Ls[r][c] = (c <= r) ? a[c] : 0.0;
+  }
   __syncthreads();
   // a pivot that is not > 0 (or NaN) leaves a diagonal root that is not > 0,
   // and every later pivot inherits the failure: the first bad column is the
   // lowest such lane
-  const double diag = Ls[r][r];
+  const double diag = act ? Ls[r][r] : 1.0;
   const unsigned long long bad = __ballot(r < jn && !(diag > 0.0));
   if (r == 0 && bad && *info == 0) *info = j0 + __ffsll((long long)bad);
-  rdiag[r] = 1.0 / diag;
+  if (act) rdiag[r] = 1.0 / diag;
   __syncthreads();
-  tri_inverse_col(Ls, rdiag, a, r);
+  if (act) {
+    tri_inverse_col(Ls, rdiag, a, r);
 #pragma unroll
-  for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
+    for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
+  }
+}
+
+DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
+                         int* __restrict__ info) {
+  __shared__ double sh[CHOL_DIAG_LDS];
+  chol_diag_core(A, d, j0, jn, Linv, info, sh);
 }
 
 __global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
@@ -850,9 +871,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ A, int 
 
 // Trailing update A(i, k) -= sum_c A(i, c) A(k, c) over the panel columns,
 // for the lower tiles of block rows/cols >= t0.
-DEV void chol_update_tile(double* __restrict__ A, int d, int j0, int jn, int t0, int t) {
+constexpr int CHOL_UPD_LDS = e_lds_elems<double, 64, 64, 16>();  // doubles
+
+DEV void chol_update_core(double* __restrict__ A, int d, int j0, int jn, int t0, int t, double* lds) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ double lds[e_lds_elems<double, BM, BN, BK>()];
   int bi, bk;
   tile_pair(t, bi, bk);
   const int i0 = (t0 + bi) * BM, k0 = (t0 + bk) * BN;
@@ -873,23 +895,42 @@ DEV void chol_update_tile(double* __restrict__ A, int d, int j0, int jn, int t0,
       }
 }
 
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int d, int j0, int jn, int t0) {
-  chol_update_tile(A, d, j0, jn, t0, blockIdx.x);
+DEV void chol_update_tile(double* __restrict__ A, int d, int j0, int jn, int t0, int t) {
+  __shared__ double lds[CHOL_UPD_LDS];
+  chol_update_core(A, d, j0, jn, t0, t, lds);
 }
 
 size_t chol_scratch_bytes(int d) { return (size_t)cdiv(d, CHOL_NB) * CHOL_NB * CHOL_NB * sizeof(double); }
 
+// Trailing update of block column j0 fused with the factorisation of the
+// next diagonal block: workgroup 0 updates tile (t0, t0), the first of the
+// row-by-row enumeration, which is that diagonal block, and then factors it
+// while the other workgroups finish the update.  The barrier at the start of
+// the factorisation orders the tile's stores before its loads (one
+// workgroup); nothing else reads the block before the next launch.
+// Both phases use the same LDS buffer.
+__global__ __launch_bounds__(256) void k_chol_update_diag(double* __restrict__ A, int d, int j0, int jn, int t0,
+                                                          double* __restrict__ Linv_next, int* __restrict__ info) {
+  constexpr int NLDS = CHOL_UPD_LDS > CHOL_DIAG_LDS ? CHOL_UPD_LDS : CHOL_DIAG_LDS;
+  __shared__ double lds[NLDS];
+  chol_update_core(A, d, j0, jn, t0, blockIdx.x, lds);
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    const int j1 = t0 * CHOL_NB;
+    chol_diag_core(A, d, j1, min(CHOL_NB, d - j1), Linv_next, info, lds);
+  }
+}
+
 hipError_t potrf(double* A, int d, int* info, double* Linv, hipStream_t s) {
   const int nb = cdiv(d, CHOL_NB);
-  for (int jb = 0; jb < nb; ++jb) {
-    const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
-    double* Li = Linv + (long)jb * CHOL_NB * CHOL_NB;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, d, j0, jn, Li, info);
+  hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, d, 0, min(CHOL_NB, d), Linv, info);
+  for (int jb = 0; jb + 1 < nb; ++jb) {
+    const int j0 = jb * CHOL_NB, jn = CHOL_NB;
+    const double* Li = Linv + (long)jb * CHOL_NB * CHOL_NB;
     const int m = nb - jb - 1;
-    if (m > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(m), dim3(256), 0, s, A, d, j0, jn, (const double*)Li);
-      hipLaunchKernelGGL(k_chol_update, dim3(m * (m + 1) / 2), dim3(256), 0, s, A, d, j0, jn, jb + 1);
-    }
+    hipLaunchKernelGGL(k_chol_panel, dim3(m), dim3(256), 0, s, A, d, j0, jn, Li);
+    hipLaunchKernelGGL(k_chol_update_diag, dim3(m * (m + 1) / 2), dim3(256), 0, s, A, d, j0, jn, jb + 1,
+                       Linv + (long)(jb + 1) * CHOL_NB * CHOL_NB, info);
   }
   return hipGetLastError();
 }
