@@ -1,0 +1,170 @@
+"""The mixed form at the full benchmark size: d = 4096, P = 256, n_lag = 256,
+the Gaussian target of seed 2 with the warm start (the workload bench.py
+times, in the same launch configuration: internal Philox normals and
+uniforms, the 256 x 256 paired proposal tiles, the 128 x 128 split-bf16
+target tiles, the plain-bf16 scatter, the fused blocked Cholesky).
+
+At this size the oracle cannot run whole windows, so outputs are checked one
+by one against FP64 recomputations on the host:
+  * log pi of sampled chains at the start (the definition -1/2 |R (x - mu)|^2);
+  * columns of Xi = beta alpha A~ W~ for sampled chains and steps, with the
+    rounded factor A~ and the hi + lo normals W~ the GPU drew;
+  * log alpha of the first step for sampled chains, rebuilt from the GPU's
+    proposal, z and uniforms (target at the proposal in FP64), and the accept
+    decisions away from near-ties;
+  * the window's contribution to the merged moments (mean, and a 64 x 64
+    block of the raw second moment) against FP64 sums of the GPU's visited
+    states, read after every step;
+  * the factor against numpy's Cholesky of the GPU's own moments.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1506_05741_amd import diam, synth
+
+D, P, NL, BETA = 4096, 256, 256, 0.3
+RHO = float(np.sqrt(1.0 - BETA * BETA))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def bf16_pair(s, n):
+    """hi + lo normals of the last call as (n, P, D) float64 on the GPU."""
+    hi = s.get(diam.F_W).view(torch.bfloat16).reshape(n, P, D).double()
+    lo = s.get(diam.F_WLO).view(torch.bfloat16).reshape(n, P, D).double()
+    return hi + lo
+
+
+def logpi(t, x):
+    y = t.R @ (x - t.mu)
+    return -0.5 * float(y @ y)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    t = synth.gaussian_target(D, 2)
+    x0 = synth.gaussian_exact_draws(t, P, 3)
+    S0, m0 = synth.gaussian_warm_moments(t)
+    N0 = float(P) * 50176
+    cfg = diam.make_config(D, P, NL, "mixed", beta=BETA, seed=1234)
+    s = diam.Sampler(cfg, dev(t.mu), dev(t.R, torch.float32), dev(x0.T))
+    st, j = s.seed_moments(dev(S0), dev(m0), N0)
+    assert st == diam.OK and j == -1
+    log(f"d={D} P={P} n_lag={NL} mixed sampler ready")
+    return t, x0, s, N0
+
+
+def test_full_size_window_against_fp64_recomputation(setup):
+    t, x0, s, N0 = setup
+    J = [0, 1, 97, 200, 255]
+    rng = np.random.default_rng(5)
+    I = np.sort(rng.choice(D, 64, replace=False))
+    It = torch.as_tensor(I, device="cuda")
+
+    # log pi at the start
+    lp = host(s.get_f64(diam.F_LOGP, (P,)))
+    for j in J:
+        ref = logpi(t, x0[:, j])
+        assert abs(lp[j] - ref) <= 1e-5 * (1 + abs(ref)), (j, lp[j], ref)
+    log(f"log pi at the start matches FP64 on chains {J}")
+
+    L = host(s.get_f64(diam.F_L, (D, D))).T          # rounded factor (hi + lo), lower
+    xr = host(s.get_f64(diam.F_XREF, (D,)))
+    Z = host(s.get_f64(diam.F_Z, (P, D)))
+    zq = host(s.get_f64(diam.F_ZQ, (P,)))
+    S_before = s.get_f64(diam.F_S, (D, D))[It][:, It].clone()
+    m_before = s.get_f64(diam.F_M, (D,)).clone()
+
+    xsum = torch.zeros(D, dtype=torch.float64, device="cuda")
+    sblk = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    nties = 0
+    for k in range(NL):
+        s.step_batch(1)
+        if k == 0:
+            W = host(bf16_pair(s, 1)[0])                # (P, D)
+            Xi = host(s.get(diam.F_XI).view(torch.float32).reshape(P, D)).astype(np.float64)
+            U = host(s.get_f64(diam.F_U, (P,)))
+            la = host(s.get_f64(diam.F_LA, (P,)))
+            acc = host(s.get(diam.F_ACC)).astype(bool)
+            for j in J:
+                xi_ref = BETA * (L @ W[j])
+                e = np.linalg.norm(Xi[j] - xi_ref) / np.linalg.norm(xi_ref)
+                assert e < 1e-4, (j, e)
+                xp = xr + RHO * (x0[:, j] - xr) + Xi[j]
+                zp = RHO * Z[j] + BETA * W[j]
+                la_ref = (logpi(t, xp) - lp[j]) + 0.5 * (float(zp @ zp) - zq[j])
+                assert abs(la[j] - la_ref) <= 1e-5 * (1 + abs(lp[j])), (j, la[j], la_ref)
+                if abs(la_ref - np.log(U[j])) > 1e-5 * (1 + abs(lp[j])):
+                    assert acc[j] == (np.log(U[j]) < la_ref), j
+                else:
+                    nties += 1
+            log(f"step 1: Xi columns, log alpha and decisions match FP64 on chains {J} ({nties} near-ties)")
+        X = s.get_f64(diam.F_X, (P, D))
+        xsum += X.sum(0)
+        XI = X[:, It]
+        sblk += XI.T @ XI
+    n = P * NL
+    s.merge_moments()
+    S_after = s.get_f64(diam.F_S, (D, D))[It][:, It]
+    m_after = s.get_f64(diam.F_M, (D,))
+    # the window's own contribution, recovered in FP64 (N0 / n = 196: no cancellation to speak of)
+    Sw = host(((N0 + n) * S_after - N0 * S_before) / n)
+    mw = host(((N0 + n) * m_after - N0 * m_before) / n)
+    Sw_ref = host(sblk / n)
+    mw_ref = host(xsum / n)
+    eS = np.linalg.norm(Sw - Sw_ref) / np.linalg.norm(Sw_ref)
+    em = np.linalg.norm(mw - mw_ref) / np.linalg.norm(mw_ref)
+    log(f"window contribution to the merge: S block rel {eS:.2e}, mean rel {em:.2e}")
+    assert eS < 1e-4 and em < 1e-6
+
+    st, jit = s.update_proposal()
+    assert st == diam.OK and jit == -1
+    Sg = host(s.get_f64(diam.F_S, (D, D))).T
+    mg = host(s.get_f64(diam.F_M, (D,)))
+    Lg = host(s.get_f64(diam.F_L, (D, D))).T
+    L_ref = np.linalg.cholesky(Sg - np.outer(mg, mg))
+    eL = np.linalg.norm(Lg - L_ref) / np.linalg.norm(L_ref)
+    log(f"factor vs numpy Cholesky of the GPU's moments: rel {eL:.2e}")
+    assert eL < 1e-4
+    nacc = int(s.get(diam.F_NACC).view(torch.int32).sum())
+    assert nacc > 0.5 * n
+
+
+def test_full_size_window_in_one_call(setup):
+    """One whole window per call, as the benchmark runs it: the proposal
+    contraction covers all 65536 columns at once."""
+    t, x0, s, N0 = setup
+    L = host(s.get_f64(diam.F_L, (D, D))).T
+    nacc0 = int(s.get(diam.F_NACC).view(torch.int32).sum())
+    s.step_batch(NL)
+    Xi = s.get(diam.F_XI).view(torch.float32).reshape(NL, P, D)
+    W = bf16_pair(s, NL)
+    for (k, j) in [(0, 0), (17, 100), (128, 31), (255, 255)]:
+        xi = host(Xi[k, j]).astype(np.float64)
+        xi_ref = BETA * (L @ host(W[k, j]))
+        e = np.linalg.norm(xi - xi_ref) / np.linalg.norm(xi_ref)
+        assert e < 1e-4, (k, j, e)
+    la = host(s.get_f64(diam.F_LA, (NL, P)))
+    assert np.isfinite(la).all()
+    s.merge_moments()
+    st, jit = s.update_proposal()
+    assert st == diam.OK and jit == -1
+    acc = (int(s.get(diam.F_NACC).view(torch.int32).sum()) - nacc0) / (P * NL)
+    log(f"one-call window: Xi columns match FP64, acceptance {acc:.3f}")
+    assert acc > 0.5
