@@ -1,4 +1,4 @@
-"""The mixed form at the full benchmark size: d = 4096, P = 256, n_lag = 256,
+"""Full-size checks.  The mixed form at the benchmark size: d = 4096, P = 256, n_lag = 256,
 the Gaussian target of seed 2 with the warm start (the workload bench.py
 times, in the same launch configuration: internal Philox normals and
 uniforms, the 256 x 256 paired proposal tiles, the 128 x 128 split-bf16
@@ -16,6 +16,9 @@ by one against FP64 recomputations on the host:
     block of the raw second moment) against FP64 sums of the GPU's visited
     states, read after every step;
   * the factor against numpy's Cholesky of the GPU's own moments.
+The logistic-regression posterior of the learned form at its full size
+(n = 200000, d = 512, P = 128) gets the same per-chain checks of log pi and
+of one step.
 """
 import sys
 
@@ -168,3 +171,57 @@ def test_full_size_window_in_one_call(setup):
     acc = (int(s.get(diam.F_NACC).view(torch.int32).sum()) - nacc0) / (P * NL)
     log(f"one-call window: Xi columns match FP64, acceptance {acc:.3f}")
     assert acc > 0.5
+
+
+def test_full_size_logistic_target_and_step():
+    """The learned form's posterior at its full size (n = 200000, d = 512,
+    P = 128, FP32 form): log pi of sampled chains against the FP64 definition
+    (Bernoulli log likelihood with the stable softplus, Gaussian prior), then
+    log alpha and the decisions of one step rebuilt in FP64 from the GPU's
+    proposal, z and uniforms."""
+    d, P2, nl, beta = 512, 128, 200, 1.0
+    rho = float(np.sqrt(1.0 - beta * beta))
+    data = synth.logreg_data()
+    A64 = data.A.astype(np.float64)
+    y64 = data.y.astype(np.float64)
+
+    def lp_ref(x):
+        tt = A64 @ x
+        return float(y64 @ tt - (np.maximum(tt, 0.0) + np.log1p(np.exp(-np.abs(tt)))).sum()) \
+            - float(x @ x) / (2.0 * data.prior_var)
+
+    rng = np.random.default_rng(8)
+    x0 = data.w_true[:, None] + 0.1 * rng.standard_normal((d, P2))
+    cfg = diam.make_config(d, P2, nl, "fp32", beta=beta, seed=31)
+    s = diam.Sampler(cfg, None, None, dev(x0.T), A=dev(data.A, torch.float32), y=dev(data.y, torch.float32),
+                     prior_var=data.prior_var)
+    # moments that put the pivot at the truth with a 0.1 I factor
+    S0 = 0.01 * np.eye(d) + np.outer(data.w_true, data.w_true)
+    st, _ = s.seed_moments(dev(S0), dev(data.w_true), 10 * P2 * nl)
+    assert st == diam.OK
+    J = [0, 5, 64, 127]
+    lp = host(s.get_f64(diam.F_LOGP, (P2,)))
+    for j in J:
+        ref = lp_ref(x0[:, j])
+        assert abs(lp[j] - ref) <= 1e-6 * (1 + abs(ref)), (j, lp[j], ref)
+    xr = host(s.get_f64(diam.F_XREF, (d,)))
+    Z = host(s.get_f64(diam.F_Z, (P2, d)))
+    zq = host(s.get_f64(diam.F_ZQ, (P2,)))
+    s.step_batch(1)
+    Xi = host(s.get(diam.F_XI).view(torch.float32).reshape(P2, d)).astype(np.float64)
+    W = host(s.get(diam.F_W).view(torch.float32).reshape(P2, d)).astype(np.float64)
+    U = host(s.get_f64(diam.F_U, (P2,)))
+    la = host(s.get_f64(diam.F_LA, (P2,)))
+    acc = host(s.get(diam.F_ACC)).astype(bool)
+    ties = 0
+    for j in J:
+        xp = xr + rho * (x0[:, j] - xr) + Xi[j]
+        zp = rho * Z[j] + beta * W[j]
+        la_ref = (lp_ref(xp) - lp[j]) + 0.5 * (float(zp @ zp) - zq[j])
+        tol = 1e-6 * (1 + abs(lp[j]))
+        assert abs(la[j] - la_ref) <= tol, (j, la[j], la_ref)
+        if abs(la_ref - np.log(U[j])) > tol:
+            assert acc[j] == (np.log(U[j]) < la_ref), j
+        else:
+            ties += 1
+    log(f"logistic n=200000 d=512 P=128: log pi, log alpha and decisions match FP64 on chains {J} ({ties} near-ties)")
