@@ -567,6 +567,9 @@ static int syrk_tiles(int prec, int d, long K) {
 
 // K is split so that at least ~512 workgroups run; chunks are whole
 // multiples of 64 columns (keeps the bf16 vector loads 16-byte aligned).
+// FP32 chunks are whole multiples of the FP32 span FOLD_K: a window of at
+// most FOLD_K samples is then one chunk, accumulated exactly as the grouped
+// scatter of the batched form accumulates it (same FP32 sums, same FP64 fold).
 static long syrk_kchunk(int prec, int d, long K) {
   const int nt = syrk_tiles(prec, d, K);
   int ns = cdiv(512, nt);
@@ -574,6 +577,7 @@ static long syrk_kchunk(int prec, int d, long K) {
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
   long kc = (K + ns - 1) / ns;
+  if (prec == P32) return ((kc + FOLD_K - 1) / FOLD_K) * FOLD_K;
   return ((kc + 63) / 64) * 64;
 }
 static int syrk_splits(int prec, int d, long K) {
