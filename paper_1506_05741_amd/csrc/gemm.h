@@ -649,7 +649,7 @@ DEV void h_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, 
   static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
   constexpr int LPW = NBLK / NW;
   const int nk = kend / HBK;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   auto issue = [&](int kt) {
     const int k0 = kt * HBK;
     u16* st = lds + (kt % ST) * SS;
@@ -734,7 +734,8 @@ DEV void p_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long lda,
   static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
   constexpr int LPW = NBLK / NW;
   const int nk = (kend - kbeg) / PBK;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave index in a scalar register: the copy assignment below branches per wave, not per lane
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   auto issue = [&](int kt) {
     const int k0 = kbeg + kt * PBK;
     u16* st = lds + (kt % ST) * SS;
@@ -798,7 +799,7 @@ DEV void s3_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
   static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
   constexpr int LPW = NBLK / NW;
   const int nk = (kend - kbeg) / HBK;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   auto issue = [&](int kt) {
     const int k0 = kbeg + kt * HBK;
     u16* st = lds + (kt % ST) * SS;
