@@ -17,6 +17,7 @@ Modules
              form of Algorithm 1), the moment merge of Section 2.4.1 with
              M = 1, Cholesky with a diagonal-jitter rule, and two-stage
              delayed acceptance with a surrogate.
+``psrf``     potential scale reduction factor of the chains (Section 2.4.2).
 ``ess``      integrated autocorrelation time / effective sample size
              (Section 2.2, eq. mse) via Geyer's initial monotone sequence.
 ``mlp``      the 512-256-256-1 GELU surrogate, its backward pass and Adam.
