@@ -104,9 +104,12 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         s.set_trace(None, None)
         s.profile(True)
         s.profile_read(reset=True)
+        s.psrf_enable(True)                      # the PSRF fold is timed in these windows only
         for _ in range(args.profile_windows):
             window()
         prof = s.profile_read(reset=True)
+        psrf_worst = s.psrf()[1] if args.profile_windows else None
+        s.psrf_enable(False)
         s.profile(False)
     tr = trace.cpu().numpy()
     half = n_timed // 2
@@ -123,6 +126,7 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         "ess": ess,
         "acceptance": nacc / (P * (n_timed + args.warmup * nl)),
         "profile": prof,
+        "psrf_worst": psrf_worst if profile else None,
     }
 
 
@@ -462,6 +466,17 @@ def main():
                                 "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s", "frac": pf / dtp / PEAK["bf16"],
                                 "avg_us": dtp * 1e6}
     stages = {k: {"ms_per_window": v[0] / args.profile_windows, "regions": v[1]} for k, v in prof.items() if v[1]}
+    # the PSRF fold of a merged window (profiled windows only): store read + accumulators read and written
+    psrf = None
+    ms_ps, n_ps = prof.get("psrf", (0.0, 0))
+    if n_ps:
+        eb = {"fp64": 8, "fp32": 4, "mixed": 2}[args.precision]
+        pbytes = args.d * args.P * args.n_lag * eb + 4 * args.d * args.P * 8
+        dps = ms_ps / n_ps * 1e-3
+        psrf = {"kernel": "k_psrf_acc (fold of a merged window into the per-chain PSRF accumulators)",
+                "bound": "hbm", "achieved": pbytes / dps / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": pbytes / dps / HBM_PEAK, "bytes_per_window": pbytes, "us_per_window": dps * 1e6,
+                "worst_sqrt_r_minus_1": res["psrf_worst"]}
 
     out = {
         "metric": METRIC,
@@ -484,6 +499,7 @@ def main():
         "acceptance": res["acceptance"],
         "stage_ms_per_window": stages,
         "roofline": roofline,
+        "psrf": psrf,
     }
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],

@@ -236,6 +236,27 @@ int diam_surrogate_eval(diam_ctx* ctx, const double* X, int32_t n, double* out);
  * rows of P uniforms (stage 1, stage 2). */
 int diam_set_delayed_acceptance(diam_ctx* ctx, int32_t on);
 
+/* ---- convergence diagnostic -------------------------------------------------
+ * Potential scale reduction factor of the P chains (Section 2.4.2, eqs. winco,
+ * btwco and psrf) with M = 1: chain p's local moments are the averages over
+ * its n visited states since the diagnostic was enabled, the global mean is
+ * the average of the chain means, and for every coordinate i
+ *   B_i = n/(P-1) sum_p (m^p - m^glob)_i^2,  W_i = n/((n-1) P) sum_p C^p_ii,
+ *   R_i = (n-1)/n + (P+1)/(P n) B_i / W_i,   diagnostic sqrt(R_i).
+ * diam_psrf_enable(ctx, 1) zeroes the per-chain accumulators (d x P FP64
+ * means and sums of squared deviations, in the workspace); every later
+ * diam_merge_moments folds the window's stored states into them (the values
+ * the moment merge uses: the shift from the window's pivot in FP64, FP32 or
+ * bf16, plus the pivot, merged window by window in FP64 by the pairwise
+ * update).  on = 0 stops folding and keeps the accumulators. */
+int diam_psrf_enable(diam_ctx* ctx, int32_t on);
+/* sqrt(R_i), i < d, into out (device, d f64; NULL: an internal buffer) and,
+ * when worst (host) is non-NULL, max_i (sqrt(R_i) - 1) (NaN when some W_i is
+ * 0, e.g. a coordinate that never moved), which synchronises the stream.
+ * DIAM_E_STATE unless the diagnostic is enabled, P >= 2 and at least two
+ * states per chain have been folded. */
+int diam_psrf(diam_ctx* ctx, double* out, double* worst);
+
 /* ---- batched form ---------------------------------------------------------
  * G independent Gaussian problems of dimensions dims[g] (each target as in
  * diam_target, R FP32), P chains each, one shared n_lag.  Every call serves
@@ -319,7 +340,8 @@ enum {
   DIAM_ST_WHITEN = 6,   /* factor rounding, pivot copy, z = A^-1 (x - x_ref) */
   DIAM_ST_SURROGATE = 7, /* surrogate forward pass + stage-1 screen and survivor packing (per step) */
   DIAM_ST_TRAIN = 8,    /* surrogate standardisation, initialisation and Adam steps */
-  DIAM_NSTAGES = 9
+  DIAM_ST_PSRF = 9,     /* folding a merged window into the PSRF accumulators */
+  DIAM_NSTAGES = 10
 };
 /* Enable (on != 0) or disable event timing.  Enabling creates the events. */
 int diam_profile_enable(diam_ctx* ctx, int32_t on);

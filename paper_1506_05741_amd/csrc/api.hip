@@ -52,6 +52,8 @@ struct Layout {
       slot, idx, nsurv, npass, Vs, t64, Zs;
   // split-bf16 target (mixed form, Gaussian)
   size_t R3, V3, Yp;
+  // PSRF accumulators
+  size_t pmean, pm2, pout;
   size_t total;
 };
 
@@ -115,6 +117,9 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.R3 = take(s3 ? 3 * dd * 2 : 0);
   L.V3 = take(s3 ? 3 * dP * 2 : 0);
   L.Yp = take(s3 ? dk::tgt_s3_scratch_bytes(c.d, c.P) : 0);
+  L.pmean = take(dP * 8);
+  L.pm2 = take(dP * 8);
+  L.pout = take(d * 8);
   if (c.surrogate) {
     const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
     const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
@@ -172,6 +177,10 @@ struct diam_ctx {
   uint16_t *R3, *V3;
   float* Yp;
   double prior_w;
+  // PSRF
+  double *pmean, *pm2, *pout;
+  int psrf_on;
+  double psrf_n;  // states per chain folded since enabling
   // learned-part form
   dk::MlpBufs mlp;
   double *s_cur, *s_new;
@@ -440,6 +449,11 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->Wlo = c->ws + lay.Wlo;
   c->Xi = c->ws + lay.Xi;
   c->win = c->ws + lay.win;
+  c->pmean = dptr(c, lay.pmean);
+  c->pm2 = dptr(c, lay.pm2);
+  c->pout = dptr(c, lay.pout);
+  c->psrf_on = 0;
+  c->psrf_n = 0.0;
   c->wint = c->ws + lay.wint;
   c->xr = dptr(c, lay.xr);
   c->S = dptr(c, lay.S);
@@ -760,9 +774,45 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
   HIPCHK(dk::syrk_window(c->prec, Xs, d, K, G, c->h, c->syrk, s));
   HIPCHK(dk::fold_moments(G, c->h, c->xr, c->N, K, c->S, c->m, d, s));
   prof_end(c, ps);
+  if (c->psrf_on) {
+    // the store still holds the window's states and xr its pivot
+    const int pp = prof_begin(c, DIAM_ST_PSRF);
+    HIPCHK(dk::psrf_accumulate(c->prec, c->win, d, P, c->siw, c->xr, c->psrf_n, c->pmean, c->pm2, s));
+    prof_end(c, pp);
+    c->psrf_n += (double)c->siw;
+  }
   c->N += (double)K;
   c->siw = 0;
   c->windows += 1;
+  return DIAM_OK;
+}
+
+extern "C" int diam_psrf_enable(diam_ctx* c, int32_t on) {
+  if (!c) return fail(DIAM_E_ARG, "null context");
+  if (on) c->psrf_n = 0.0;  // zeroed lazily: the first fold after this overwrites
+  c->psrf_on = on ? 1 : 0;
+  return DIAM_OK;
+}
+
+extern "C" int diam_psrf(diam_ctx* c, double* out, double* worst) {
+  if (!c) return fail(DIAM_E_ARG, "null context");
+  if (!c->psrf_on) return fail(DIAM_E_STATE, "the PSRF diagnostic is not enabled");
+  const int d = c->cfg.d, P = c->cfg.P;
+  if (P < 2) return fail(DIAM_E_STATE, "the PSRF needs at least two chains");
+  if (c->psrf_n < 2.0) return fail(DIAM_E_STATE, "the PSRF needs at least two folded states per chain (%g)", c->psrf_n);
+  double* o = out ? out : c->pout;
+  HIPCHK(dk::psrf_finalize(c->pmean, c->pm2, d, P, c->psrf_n, o, c->stream));
+  if (worst) {
+    std::vector<double> h(d);
+    HIPCHK(hipMemcpyAsync(h.data(), o, d * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double w = -INFINITY;
+    for (int i = 0; i < d; ++i) {
+      if (std::isnan(h[i])) { w = NAN; break; }
+      w = std::max(w, h[i] - 1.0);
+    }
+    *worst = w;
+  }
   return DIAM_OK;
 }
 

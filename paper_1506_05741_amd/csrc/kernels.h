@@ -146,6 +146,13 @@ struct StepArgs {
   int ldw;                                // leading dimension of Xi and W (0: d)
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
+// PSRF accumulators (Section 2.4.2, M = 1): merge the nw stored states of
+// each chain of the window (store shifted by xr, column p + P t) into the
+// running per-chain means and sums of squared deviations (d x P each) that
+// already hold n0 states per chain; finalize writes sqrt(R_i) for i < d.
+hipError_t psrf_accumulate(Prec prec, const void* win, int d, int P, int nw, const double* xr, double n0, double* mean,
+                           double* m2, hipStream_t s);
+hipError_t psrf_finalize(const double* mean, const double* m2, int d, int P, double n, double* out, hipStream_t s);
 
 // V = X - mu (mu may be null; FP64 or FP32 V), Z = X, for the initial evaluation.
 hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);

@@ -968,6 +968,138 @@ hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s) 
   return hipGetLastError();
 }
 
+// ============================================================================
+// Potential scale reduction factor (Section 2.4.2, eqs. winco, btwco, psrf,
+// M = 1).  Per chain p and coordinate i the running mean and the sum of
+// squared deviations of the visited states, merged window by window from the
+// window store (state = pivot of the window + stored shift, in the store's
+// precision) with the pairwise update of Chan, Golub and LeVeque (1979), so
+// no raw second moment is ever formed.
+// ============================================================================
+// V consecutive stored values from element e (e a multiple of V; V = 1, 2 or 4)
+template <int PR, int V>
+DEV void load_win_v(const void* win, long e, double* v) {
+  if (V == 1) {
+    if (PR == P64) v[0] = ((const double*)win)[e];
+    else if (PR == P32) v[0] = (double)((const float*)win)[e];
+    else v[0] = (double)bf16_bits_to_f32(((const u16*)win)[e]);
+  } else if (V == 2) {
+    if (PR == P64) {
+      const double2 a = *(const double2*)((const double*)win + e);
+      v[0] = a.x; v[1] = a.y;
+    } else if (PR == P32) {
+      const float2 a = *(const float2*)((const float*)win + e);
+      v[0] = a.x; v[1] = a.y;
+    } else {
+      const uint32_t a = *(const uint32_t*)((const u16*)win + e);
+      v[0] = (double)bf16_bits_to_f32((u16)(a & 0xffff));
+      v[1] = (double)bf16_bits_to_f32((u16)(a >> 16));
+    }
+  } else if (PR == P64) {
+    const double2 a = *(const double2*)((const double*)win + e), b = *(const double2*)((const double*)win + e + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  } else if (PR == P32) {
+    const float4 a = *(const float4*)((const float*)win + e);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+    const uint2 a = *(const uint2*)((const u16*)win + e);
+    v[0] = (double)bf16_bits_to_f32((u16)(a.x & 0xffff));
+    v[1] = (double)bf16_bits_to_f32((u16)(a.x >> 16));
+    v[2] = (double)bf16_bits_to_f32((u16)(a.y & 0xffff));
+    v[3] = (double)bf16_bits_to_f32((u16)(a.y >> 16));
+  }
+}
+
+// elements e = i + d p, V consecutive coordinates of one chain per thread
+// (V = 4 needs d % 4 == 0); window column of chain p at step t: p + P t
+template <int PR, int V>
+__global__ __launch_bounds__(256) void k_psrf_acc(const void* __restrict__ win, int d, int P, int nw,
+                                                  const double* __restrict__ xr, double n0, double* __restrict__ mean,
+                                                  double* __restrict__ m2) {
+  const long e0 = ((long)blockIdx.x * 256 + threadIdx.x) * V;
+  if (e0 >= (long)d * P) return;
+  const int i0 = (int)(e0 % d), p = (int)(e0 / d);
+  double s1[V], s2[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) s1[k] = s2[k] = 0.0;
+  // loads of 16 steps in flight per thread for 4-wide rows (measured best at
+  // d = 4096, P = 256: 71 % of the HBM peak), 4 for single coordinates
+  constexpr int UNR = V == 4 ? 16 : 4;
+#pragma unroll UNR
+  for (int t = 0; t < nw; ++t) {
+    double v[V];
+    load_win_v<PR, V>(win, i0 + (long)(p + (long)P * t) * d, v);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      s1[k] += v[k];
+      s2[k] = __fma_rn(v[k], v[k], s2[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const long e = e0 + k;
+    const double mw = s1[k] / nw;
+    const double qw = __fma_rn(-s1[k], mw, s2[k]);  // sum over the window of (v - mw)^2
+    const double xm = xr[i0 + k] + mw;              // the window's mean state
+    if (n0 == 0.0) {
+      mean[e] = xm;
+      m2[e] = qw;
+    } else {
+      const double nt = n0 + (double)nw;
+      const double delta = xm - mean[e];
+      mean[e] = __fma_rn(delta, (double)nw / nt, mean[e]);
+      m2[e] = m2[e] + qw + delta * delta * (n0 * (double)nw / nt);
+    }
+  }
+}
+
+template <int PR>
+static void psrf_acc_launch(const void* win, int d, int P, int nw, const double* xr, double n0, double* mean,
+                            double* m2, hipStream_t s) {
+  const long n = (long)d * P;
+  if (d % 4 == 0 && (uintptr_t)win % 16 == 0)
+    hipLaunchKernelGGL((k_psrf_acc<PR, 4>), dim3(cdiv(n / 4, 256)), dim3(256), 0, s, win, d, P, nw, xr, n0, mean, m2);
+  else
+    hipLaunchKernelGGL((k_psrf_acc<PR, 1>), dim3(cdiv(n, 256)), dim3(256), 0, s, win, d, P, nw, xr, n0, mean, m2);
+}
+
+hipError_t psrf_accumulate(Prec prec, const void* win, int d, int P, int nw, const double* xr, double n0, double* mean,
+                           double* m2, hipStream_t s) {
+  if (prec == P64) psrf_acc_launch<P64>(win, d, P, nw, xr, n0, mean, m2, s);
+  else if (prec == P32) psrf_acc_launch<P32>(win, d, P, nw, xr, n0, mean, m2, s);
+  else psrf_acc_launch<PMIX>(win, d, P, nw, xr, n0, mean, m2, s);
+  return hipGetLastError();
+}
+
+// out[i] = sqrt(R_i): B_i = n/(P-1) sum_p (m^p - mbar)_i^2 with mbar the mean
+// of the chain means, W_i = sum_p m2[i, p] / ((n - 1) P) (the average of the
+// chains' 1/n variances times n/(n-1)), R_i = (n-1)/n + (P+1)/(P n) B_i/W_i.
+__global__ __launch_bounds__(256) void k_psrf_final(const double* __restrict__ mean, const double* __restrict__ m2,
+                                                    int d, int P, double n, double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d) return;
+  double sm = 0.0, sq = 0.0;
+  for (int p = 0; p < P; ++p) {
+    sm += mean[i + (long)p * d];
+    sq += m2[i + (long)p * d];
+  }
+  const double mbar = sm / P;
+  double sb = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const double u = mean[i + (long)p * d] - mbar;
+    sb = __fma_rn(u, u, sb);
+  }
+  const double B = n / (double)(P - 1) * sb;
+  const double W = sq / ((n - 1.0) * (double)P);
+  const double R = (n - 1.0) / n + (double)(P + 1) / ((double)P * n) * (B / W);
+  out[i] = sqrt(R);
+}
+
+hipError_t psrf_finalize(const double* mean, const double* m2, int d, int P, double n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_psrf_final, dim3(cdiv(d, 256)), dim3(256), 0, s, mean, m2, d, P, n, out);
+  return hipGetLastError();
+}
+
 // ---- whitening Z = L^-1 (X - xr) ------------------------------------------
 DEV void sub_ref_elem(const double* __restrict__ X, const double* __restrict__ xr, double* __restrict__ Z, int d,
                       long e) {

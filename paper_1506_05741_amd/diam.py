@@ -29,12 +29,13 @@ EXPORTED = (
     "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
+    "diam_psrf_enable", "diam_psrf",
     "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
     "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_field_bytes",
     "diam_batch_get", "diam_batch_get_stats", "diam_batch_destroy",
 )
 BATCH_TILES = ("32x2", "64x1", "64x2", "128x2", "32x4")   # target tile rows x k-groups
-STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten", "surrogate", "train")
+STAGES = ("rng", "proposal", "target", "step", "merge", "chol", "whiten", "surrogate", "train", "psrf")
 
 
 class Config(ctypes.Structure):
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
                                  ctypes.c_int),
         "diam_surrogate_eval": ([vp, vp, i32, vp], ctypes.c_int),
         "diam_set_delayed_acceptance": ([vp, i32], ctypes.c_int),
+        "diam_psrf_enable": ([vp, i32], ctypes.c_int),
+        "diam_psrf": ([vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "diam_batch_workspace_bytes": ([ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(sz)], ctypes.c_int),
         "diam_batch_init": ([ctypes.POINTER(vp), ctypes.POINTER(BatchConfig), vp, vp, vp, vp, sz, vp, vp],
                             ctypes.c_int),
@@ -263,6 +266,19 @@ class Sampler:
     def set_delayed_acceptance(self, on=True):
         _check(self.lib.diam_set_delayed_acceptance(self.ctx, 1 if on else 0))
         self.da_on = bool(on)
+
+    # -- convergence diagnostic ------------------------------------------------------
+    def psrf_enable(self, on=True):
+        """Start (zeroing the accumulators) or stop folding merged windows into the PSRF."""
+        _check(self.lib.diam_psrf_enable(self.ctx, 1 if on else 0))
+
+    def psrf(self):
+        """(sqrt(R_i) for every coordinate as a CUDA float64 tensor, max_i sqrt(R_i) - 1)."""
+        torch = self.torch
+        out = torch.empty(self.d, dtype=torch.float64, device=self.ws.device)
+        worst = ctypes.c_double()
+        _check(self.lib.diam_psrf(self.ctx, _ptr(out), ctypes.byref(worst)))
+        return out, worst.value
 
     # -- reading back ------------------------------------------------------------
     def field_bytes(self, field):

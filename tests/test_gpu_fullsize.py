@@ -15,7 +15,8 @@ by one against FP64 recomputations on the host:
   * the window's contribution to the merged moments (mean, and a 64 x 64
     block of the raw second moment) against FP64 sums of the GPU's visited
     states, read after every step;
-  * the factor against numpy's Cholesky of the GPU's own moments.
+  * the factor against numpy's Cholesky of the GPU's own moments;
+  * the PSRF of the window on the sampled coordinates against the oracle.
 The logistic-regression posterior of the learned form at its full size
 (n = 200000, d = 512, P = 128) gets the same per-chain checks of log pi and
 of one step.
@@ -28,6 +29,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+from oracle import psrf as op
 from paper_1506_05741_amd import diam, synth
 
 D, P, NL, BETA = 4096, 256, 256, 0.3
@@ -97,6 +99,9 @@ def test_full_size_window_against_fp64_recomputation(setup):
     xsum = torch.zeros(D, dtype=torch.float64, device="cuda")
     sblk = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
     nties = 0
+    s.psrf_enable(True)
+    xr_t = torch.as_tensor(xr, device="cuda")
+    chains_I = []                                  # the states the bf16 window store represents, coordinates I
     for k in range(NL):
         s.step_batch(1)
         if k == 0:
@@ -122,6 +127,7 @@ def test_full_size_window_against_fp64_recomputation(setup):
         xsum += X.sum(0)
         XI = X[:, It]
         sblk += XI.T @ XI
+        chains_I.append(host(xr_t[It] + (XI - xr_t[It]).float().bfloat16().double()))
     n = P * NL
     s.merge_moments()
     S_after = s.get_f64(diam.F_S, (D, D))[It][:, It]
@@ -135,6 +141,12 @@ def test_full_size_window_against_fp64_recomputation(setup):
     em = np.linalg.norm(mw - mw_ref) / np.linalg.norm(mw_ref)
     log(f"window contribution to the merge: S block rel {eS:.2e}, mean rel {em:.2e}")
     assert eS < 1e-4 and em < 1e-6
+    ps, worst = s.psrf()
+    ref = op.psrf(np.stack(chains_I, axis=1))
+    eP = np.max(np.abs(host(ps)[I] - ref))
+    log(f"PSRF of the window on coordinates I: max |GPU - oracle| {eP:.2e}, worst sqrt(R) - 1 = {worst:.3e}")
+    assert eP < 1e-11
+    s.psrf_enable(False)
 
     st, jit = s.update_proposal()
     assert st == diam.OK and jit == -1
