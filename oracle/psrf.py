@@ -53,3 +53,21 @@ def psrf_terms(chains: np.ndarray):
 def psrf(chains: np.ndarray) -> np.ndarray:
     """sqrt(R_i) for every coordinate i."""
     return np.sqrt(psrf_terms(chains)[2])
+
+
+# ---- stopping rules of the experiments -----------------------------------------
+# Section 3.3 stops a run when the sample covariance is within a relative
+# Frobenius-norm TOL of the true covariance (TOL = 1e-3), or, when n_lag is
+# tuned, when the sample mean is within a Euclidean-norm TOL of the true mean
+# (TOL = 0.01).  The sample moments are the merged raw second moment S and
+# mean m: C = S - m m^T (eq. sampcov).
+
+def cov_rel_error(S: np.ndarray, m: np.ndarray, Sigma: np.ndarray) -> float:
+    """|S - m m^T - Sigma|_F / |Sigma|_F."""
+    C = np.asarray(S, dtype=np.float64) - np.outer(m, m)
+    return float(np.linalg.norm(C - Sigma) / np.linalg.norm(Sigma))
+
+
+def mean_abs_error(m: np.ndarray, mu: np.ndarray) -> float:
+    """|m - mu|_2."""
+    return float(np.linalg.norm(np.asarray(m, dtype=np.float64) - mu))

@@ -4,6 +4,8 @@
   chain mean and within-chain variance is exact), whose B, W and R are worked
   out on paper below.
 * Identical chains: no between-chain spread, R = (n - 1)/n.
+* Stopping errors (Section 3.3): a covariance scaled by 1 + eps, a mean off by
+  a 3-4-5 vector.
 * Independent draws from one Gaussian: sqrt(R) - 1 is O(1/n) (Gelman and
   Rubin's statistic tends to 1); chains offset by a known shift fail it.
 """
@@ -54,3 +56,18 @@ def test_rejects_degenerate_sizes():
         op.psrf(np.zeros((1, 10, 2)))
     with pytest.raises(ValueError):
         op.psrf(np.zeros((3, 1, 2)))
+
+
+def test_stopping_errors_on_known_perturbations():
+    # C = (1 + eps) Sigma exactly gives a relative Frobenius error of eps;
+    # a mean off by (3, 4, 0, ...) is 5 away in the Euclidean norm
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((6, 6))
+    Sigma = G @ G.T + 6 * np.eye(6)
+    mu = rng.standard_normal(6)
+    eps = 0.125
+    S = (1 + eps) * Sigma + np.outer(mu, mu)
+    assert op.cov_rel_error(S, mu, Sigma) == pytest.approx(eps, rel=1e-13)
+    assert op.cov_rel_error(Sigma + np.outer(mu, mu), mu, Sigma) < 1e-15
+    off = mu + np.array([3.0, 4.0, 0, 0, 0, 0])
+    assert op.mean_abs_error(off, mu) == pytest.approx(5.0, rel=1e-15)
