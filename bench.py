@@ -97,6 +97,10 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     nacc = s.get(diam.F_NACC).view(torch.int32).sum().item()
+    # stopping errors of Section 3.3 (after the timed windows, outside the timing)
+    Sig = torch.as_tensor(tgt["S0"] - np.outer(tgt["m0"], tgt["m0"]), device=dev)
+    cov_err, mean_err = s.moment_error(Sig, torch.as_tensor(tgt["mu"], device=dev))
+    del Sig
     prof = None
     if profile:
         # stage breakdown from HIP events on extra windows (events add small
@@ -127,6 +131,7 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         "acceptance": nacc / (P * (n_timed + args.warmup * nl)),
         "profile": prof,
         "psrf_worst": psrf_worst if profile else None,
+        "stopping": {"cov_rel_fro": cov_err, "mean_abs": mean_err, "tol": {"cov_rel_fro": 1e-3, "mean_abs": 1e-2}},
     }
 
 
@@ -500,6 +505,7 @@ def main():
         "stage_ms_per_window": stages,
         "roofline": roofline,
         "psrf": psrf,
+        "stopping": res["stopping"],
     }
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],

@@ -256,6 +256,13 @@ int diam_psrf_enable(diam_ctx* ctx, int32_t on);
  * DIAM_E_STATE unless the diagnostic is enabled, P >= 2 and at least two
  * states per chain have been folded. */
 int diam_psrf(diam_ctx* ctx, double* out, double* worst);
+/* Stopping errors of the experiments (Section 3.3) against a known target:
+ * cov_rel (host) = |S - m m^T - Sigma|_F / |Sigma|_F with the merged raw
+ * second moment S and mean m (eq. sampcov), and mean_abs (host, may be NULL)
+ * = |m - mu|_2 when mu is non-NULL, else NaN.  Sigma: device d x d f64
+ * (symmetric, so either layout), mu: device d f64.  FP64 sums in a fixed
+ * order; synchronises the stream. */
+int diam_moment_error(diam_ctx* ctx, const double* Sigma, const double* mu, double* cov_rel, double* mean_abs);
 
 /* ---- batched form ---------------------------------------------------------
  * G independent Gaussian problems of dimensions dims[g] (each target as in

@@ -53,7 +53,7 @@ struct Layout {
   // split-bf16 target (mixed form, Gaussian)
   size_t R3, V3, Yp;
   // PSRF accumulators
-  size_t pmean, pm2, pout;
+  size_t pmean, pm2, pout, merr;
   size_t total;
 };
 
@@ -120,6 +120,7 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.pmean = take(dP * 8);
   L.pm2 = take(dP * 8);
   L.pout = take(d * 8);
+  L.merr = take(dk::moment_err_scratch_bytes());
   if (c.surrogate) {
     const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
     const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
@@ -178,7 +179,7 @@ struct diam_ctx {
   float* Yp;
   double prior_w;
   // PSRF
-  double *pmean, *pm2, *pout;
+  double *pmean, *pm2, *pout, *merr;
   int psrf_on;
   double psrf_n;  // states per chain folded since enabling
   // learned-part form
@@ -452,6 +453,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->pmean = dptr(c, lay.pmean);
   c->pm2 = dptr(c, lay.pm2);
   c->pout = dptr(c, lay.pout);
+  c->merr = dptr(c, lay.merr);
   c->psrf_on = 0;
   c->psrf_n = 0.0;
   c->wint = c->ws + lay.wint;
@@ -813,6 +815,18 @@ extern "C" int diam_psrf(diam_ctx* c, double* out, double* worst) {
     }
     *worst = w;
   }
+  return DIAM_OK;
+}
+
+extern "C" int diam_moment_error(diam_ctx* c, const double* Sigma, const double* mu, double* cov_rel,
+                                 double* mean_abs) {
+  if (!c || !Sigma || !cov_rel) return fail(DIAM_E_ARG, "null argument");
+  HIPCHK(dk::moment_error(c->S, c->m, Sigma, mu, c->cfg.d, c->merr, c->stream));
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, c->merr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *cov_rel = h[0];
+  if (mean_abs) *mean_abs = mu ? h[1] : NAN;
   return DIAM_OK;
 }
 

@@ -153,6 +153,11 @@ hipError_t step(const StepArgs& a, hipStream_t s);
 hipError_t psrf_accumulate(Prec prec, const void* win, int d, int P, int nw, const double* xr, double n0, double* mean,
                            double* m2, hipStream_t s);
 hipError_t psrf_finalize(const double* mean, const double* m2, int d, int P, double n, double* out, hipStream_t s);
+// Stopping errors (Section 3.3): scratch[0] = |S - m m^T - Sigma|_F / |Sigma|_F,
+// scratch[1] = |m - mu|_2 (0 when mu is null); scratch of moment_err_scratch_bytes().
+size_t moment_err_scratch_bytes();
+hipError_t moment_error(const double* S, const double* m, const double* Sigma, const double* mu, int d, double* scratch,
+                        hipStream_t s);
 
 // V = X - mu (mu may be null; FP64 or FP32 V), Z = X, for the initial evaluation.
 hipError_t init_eval(int v64, const double* X, const double* mu, void* V, double* Z, int d, int P, hipStream_t s);

@@ -1486,6 +1486,68 @@ DEV double block_sum_f64(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Stopping errors of the experiments (Section 3.3): |S - m m^T - Sigma|_F^2,
+// |Sigma|_F^2 and |m - mu|^2, as per-block FP64 partial sums (fixed order)
+// reduced by one more block: deterministic.
+constexpr int MERR_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_moment_err(const double* __restrict__ S, const double* __restrict__ m,
+                                                    const double* __restrict__ Sigma, const double* __restrict__ mu,
+                                                    int d, double* __restrict__ part) {
+  __shared__ double red[4];
+  const long n = (long)d * d;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    const int i = (int)(e % d), j = (int)(e / d);
+    const double sg = Sigma[e];
+    const double u = (S[e] - m[i] * m[j]) - sg;
+    a = __fma_rn(u, u, a);
+    b = __fma_rn(sg, sg, b);
+  }
+  if (mu)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < d; i += gridDim.x * 256) {
+      const double u = m[i] - mu[i];
+      c = __fma_rn(u, u, c);
+    }
+  a = block_sum_f64(a, red);
+  b = block_sum_f64(b, red);
+  c = block_sum_f64(c, red);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = a;
+    part[3 * blockIdx.x + 1] = b;
+    part[3 * blockIdx.x + 2] = c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_moment_err_final(const double* __restrict__ part, int nb,
+                                                          double* __restrict__ out) {
+  __shared__ double red[4];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    a += part[3 * k];
+    b += part[3 * k + 1];
+    c += part[3 * k + 2];
+  }
+  a = block_sum_f64(a, red);
+  b = block_sum_f64(b, red);
+  c = block_sum_f64(c, red);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(a / b);
+    out[1] = sqrt(c);
+  }
+}
+
+size_t moment_err_scratch_bytes() { return (size_t)(2 + 3 * MERR_BLOCKS) * sizeof(double); }
+
+hipError_t moment_error(const double* S, const double* m, const double* Sigma, const double* mu, int d, double* scratch,
+                        hipStream_t s) {
+  const int nb = min(MERR_BLOCKS, cdiv((long)d * d, 256));
+  hipLaunchKernelGGL(k_moment_err, dim3(nb), dim3(256), 0, s, S, m, Sigma, mu, d, scratch + 2);
+  hipLaunchKernelGGL(k_moment_err_final, dim3(1), dim3(256), 0, s, (const double*)(scratch + 2), nb, scratch);
+  return hipGetLastError();
+}
+
+
 // Decision of chain p by one workgroup of 256 threads: the target partials
 // (thousands of row blocks for the logistic target) are summed by all
 // threads, then MH (or the second stage of delayed acceptance) decides.

@@ -29,7 +29,7 @@ EXPORTED = (
     "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
-    "diam_psrf_enable", "diam_psrf",
+    "diam_psrf_enable", "diam_psrf", "diam_moment_error",
     "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
     "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_field_bytes",
     "diam_batch_get", "diam_batch_get_stats", "diam_batch_destroy",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "diam_set_delayed_acceptance": ([vp, i32], ctypes.c_int),
         "diam_psrf_enable": ([vp, i32], ctypes.c_int),
         "diam_psrf": ([vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
+        "diam_moment_error": ([vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
         "diam_batch_workspace_bytes": ([ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(sz)], ctypes.c_int),
         "diam_batch_init": ([ctypes.POINTER(vp), ctypes.POINTER(BatchConfig), vp, vp, vp, vp, sz, vp, vp],
                             ctypes.c_int),
@@ -279,6 +280,16 @@ class Sampler:
         worst = ctypes.c_double()
         _check(self.lib.diam_psrf(self.ctx, _ptr(out), ctypes.byref(worst)))
         return out, worst.value
+
+    def moment_error(self, Sigma, mu=None):
+        """(|S - m m^T - Sigma|_F / |Sigma|_F, |m - mu|_2 or NaN) of the merged moments."""
+        torch = self.torch
+        assert Sigma.dtype == torch.float64 and Sigma.is_cuda and Sigma.numel() == self.d * self.d
+        assert mu is None or (mu.dtype == torch.float64 and mu.is_cuda and mu.numel() == self.d)
+        cov, mean = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.diam_moment_error(self.ctx, _ptr(Sigma.contiguous()), _ptr(mu) if mu is not None else None,
+                                          ctypes.byref(cov), ctypes.byref(mean)))
+        return cov.value, mean.value
 
     # -- reading back ------------------------------------------------------------
     def field_bytes(self, field):

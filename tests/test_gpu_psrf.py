@@ -106,3 +106,30 @@ def test_psrf_state_errors_and_restart():
     one.merge_moments()
     with pytest.raises(diam.DiamError):
         one.psrf()                                # one chain: no between-chain variance
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_moment_error_matches_oracle(prec):
+    """Stopping errors of Section 3.3 on the GPU's merged moments against the
+    oracle's evaluation of the same moments."""
+    d, P, n_lag = 48, 8, 12
+    t = synth.gaussian_target(d, 6)
+    x0 = synth.gaussian_exact_draws(t, P, 7)
+    rdt = torch.float64 if prec == "fp64" else torch.float32
+    s = diam.Sampler(diam.make_config(d, P, n_lag, prec, seed=2), dev(t.mu), dev(t.R, rdt), dev(x0.T))
+    S0, m0 = synth.gaussian_warm_moments(t)
+    assert s.seed_moments(dev(S0), dev(m0), 2 * P * n_lag)[0] == diam.OK
+    for _ in range(3):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+    S = host(s.get_f64(diam.F_S, (d, d))).T
+    m = host(s.get_f64(diam.F_M, (d,)))
+    cov, mean = s.moment_error(dev(t.Sigma), dev(t.mu))
+    cov_ref, mean_ref = op.cov_rel_error(S, m, t.Sigma), op.mean_abs_error(m, t.mu)
+    print(f"\n[{prec}] covariance rel. Frobenius error {cov:.4e} (oracle {cov_ref:.4e}), "
+          f"mean error {mean:.4e} (oracle {mean_ref:.4e})", flush=True)
+    assert cov == pytest.approx(cov_ref, rel=1e-10)
+    assert mean == pytest.approx(mean_ref, rel=1e-10)
+    cov2, mean2 = s.moment_error(dev(t.Sigma))
+    assert cov2 == cov and math.isnan(mean2)
