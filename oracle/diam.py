@@ -38,6 +38,11 @@ OK = 0
 E_NOT_PD = -4
 
 
+def initial_beta(d):
+    """Algorithm 1's initial step size min(2.4 / sqrt(d), 0.5)."""
+    return min(2.4 / math.sqrt(d), 0.5)
+
+
 def diam_proposal(X, x_ref, A, W, beta, alpha=1.0):
     """x' = x_ref + sqrt(1 - beta^2) (x - x_ref) + beta alpha A W
     (Section 2.3.4, eq. diam; the inflation alpha of eq. diamnl)."""
@@ -151,6 +156,10 @@ class DiamOracle:
     window: list = field(default_factory=list)
     n_accepted: np.ndarray = None
     last_jitter: int = -1
+    # step-size adaptation of Algorithm 1: None, or (acc_min, acc_max, factor, beta_max)
+    adapt: tuple = None
+    win_acc: int = 0
+    win_steps: int = 0
 
     def __post_init__(self):
         d, P = self.d, self.P
@@ -186,6 +195,8 @@ class DiamOracle:
         self.Z[:, acc] = Zp[:, acc]
         self.lp[acc] = lpp[acc]
         self.n_accepted += acc
+        self.win_acc += int(acc.sum())
+        self.win_steps += 1
         self.window.append(self.X.copy())
         return acc, la
 
@@ -217,6 +228,8 @@ class DiamOracle:
         s_new = s_cur.copy()
         s_new[acc] = sp[acc]
         self.n_accepted += acc
+        self.win_acc += int(acc.sum())
+        self.win_steps += 1
         self.window.append(self.X.copy())
         return acc, pass1, s_new
 
@@ -230,7 +243,22 @@ class DiamOracle:
         self.S_glob, self.m_glob, self.N = merge_global(self.S_glob, self.m_glob, self.N, locals_, n)
         self.window = []
 
+    def adapt_beta(self):
+        """Algorithm 1's update block: the acceptance ratio of the steps since
+        the last update, pooled over the chains, moves beta up by the factor
+        (capped at beta_max) above the band and down by it below the band."""
+        if self.adapt is not None and self.win_steps > 0:
+            acc_min, acc_max, factor, beta_max = self.adapt
+            rate = self.win_acc / (self.P * self.win_steps)
+            if rate > acc_max:
+                self.beta = min(self.beta * factor, beta_max)
+            elif rate < acc_min:
+                self.beta = self.beta / factor
+        self.win_acc = 0
+        self.win_steps = 0
+
     def update_proposal(self):
+        self.adapt_beta()
         C = sample_covariance(self.S_glob, self.m_glob)
         A, j = cholesky_jitter(C, self.jitter0, self.jitter_tries)
         self.last_jitter = j

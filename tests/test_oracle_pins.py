@@ -10,7 +10,10 @@ wrong sign or index, a transposed operand) fails it:
 * the recursive moment merge equals a two-pass covariance of all pooled
   samples (Section 2.4.1);
 * the Cholesky factor meets the backward-error bound ||L L^T - C|| <= c d u ||C||;
-* the logistic likelihood equals its textbook Bernoulli form.
+* the logistic likelihood equals its textbook Bernoulli form;
+* the step-size adaptation of Algorithm 1: with every proposal accepted
+  (exact covariance) beta grows by the factor each window up to its cap, with
+  almost none accepted (a far pivot) it shrinks by the factor each window.
 """
 import math
 
@@ -196,3 +199,47 @@ def test_twist_jacobian_is_one():
         e[k] = h
         J[:, k] = (ot.twist(x + e, 0.7) - ot.twist(x - e, 0.7)) / (2 * h)
     assert abs(np.linalg.det(J) - 1.0) < 1e-8
+
+
+def _adapting_oracle(t, P, n_lag, beta0, adapt, pivot_shift=0.0, seed=3):
+    o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), t.d, P, n_lag, beta0,
+                      X=synth.gaussian_exact_draws(t, P, seed))
+    o.adapt = adapt
+    S, m = synth.gaussian_warm_moments(t)
+    shifted = m + pivot_shift
+    assert o.seed_moments(S - np.outer(m, m) + np.outer(shifted, shifted), shifted, 1e12) == od.OK
+    return o
+
+
+def test_beta_adaptation_grows_when_every_proposal_is_accepted():
+    # exact covariance and pivot (N0 = 1e12 keeps them fixed): log alpha = 0, every proposal accepted,
+    # so each window multiplies beta by the factor until the cap
+    t = synth.gaussian_target(8, 4)
+    o = _adapting_oracle(t, 4, 10, 0.2, (0.3, 0.5, 1.5, 0.9))
+    betas = []
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        acc = o.run_window(rng.standard_normal((10, 4, 8)), synth.draw_uniforms(4, 10, int(rng.integers(1 << 30))))
+        assert acc.sum() == 40
+        betas.append(o.beta)
+    expect, b = [], 0.2
+    for _ in range(5):
+        b = min(b * 1.5, 0.9)
+        expect.append(b)
+    assert betas == expect
+
+
+def test_beta_adaptation_shrinks_when_almost_nothing_is_accepted():
+    # a pivot 30 standard deviations away along every axis: proposals around it are all rejected
+    t = synth.gaussian_target(8, 4)
+    o = _adapting_oracle(t, 4, 10, 0.5, (0.3, 0.5, 2.0, 1.0), pivot_shift=30.0)
+    rng = np.random.default_rng(2)
+    for k in range(3):
+        acc = o.run_window(rng.standard_normal((10, 4, 8)), synth.draw_uniforms(4, 10, 5 + k))
+        assert acc.sum() < 0.3 * 40
+    assert o.beta == 0.5 / 2.0 / 2.0 / 2.0
+
+
+def test_initial_beta_of_algorithm_1():
+    assert od.initial_beta(16) == 0.5
+    assert od.initial_beta(100) == pytest.approx(0.24)
