@@ -145,6 +145,7 @@ typedef struct {
   double n_samples;       /* N: sample count of the global moments (incl. seeded N0) */
   int64_t windows;        /* merges since init */
   int64_t last_call_steps;/* n_steps of the last diam_step_batch */
+  double beta;            /* current step size (changes under diam_set_beta_adaptation) */
 } diam_stats;
 
 /* Bytes of workspace diam_init needs for cfg (host).  Returns DIAM_E_ARG on a
@@ -235,6 +236,17 @@ int diam_surrogate_eval(diam_ctx* ctx, const double* X, int32_t n, double* out);
  * The network must stay fixed while it is on.  U per step then holds two
  * rows of P uniforms (stage 1, stage 2). */
 int diam_set_delayed_acceptance(diam_ctx* ctx, int32_t on);
+
+/* Step-size adaptation of Algorithm 1 (its update block): at every
+ * diam_update_proposal the acceptance ratio of the steps since the previous
+ * update, pooled over the P chains, moves beta to min(beta * factor,
+ * beta_max) when it exceeds acc_max and to beta / factor when it is below
+ * acc_min (the paper's band for DIAM is 0.3 .. 0.5, Section 3.2; it gives no
+ * factor).  beta is constant within a window, so the proposal and the
+ * z-recurrence of every step use one beta.  on = 0 keeps the current beta.
+ * DIAM_E_ARG unless 0 <= acc_min < acc_max <= 1, factor > 1 and
+ * 0 < beta_max <= 1.  The current beta is in diam_stats. */
+int diam_set_beta_adaptation(diam_ctx* ctx, int32_t on, double acc_min, double acc_max, double factor, double beta_max);
 
 /* ---- convergence diagnostic -------------------------------------------------
  * Potential scale reduction factor of the P chains (Section 2.4.2, eqs. winco,

@@ -44,7 +44,7 @@ struct Status {  // device-side status words, read back by update_proposal
 };
 
 struct Layout {
-  size_t X, Z, V, lp, zq, lpp_part, zq_part, pq_part, nacc, la, acc, U, W, Wlo, Xi, win, wint, xr, S, m, L, Lnew, Llow,
+  size_t X, Z, V, lp, zq, lpp_part, zq_part, pq_part, nacc, wacc, la, acc, U, W, Wlo, Xi, win, wint, xr, S, m, L, Lnew, Llow,
       h, syrk, status, proj_part, linv;
   // learned-part form
   size_t mlp_master, mlp_eff, mlp_grad, mlp_m, mlp_in_mean, mlp_in_scale, mlp_stats, mlp_Xs, mlp_ts, mlp_xb, mlp_tb,
@@ -94,6 +94,7 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.zq_part = take(2 * (size_t)nch * P * 8);
   L.pq_part = take(2 * (size_t)nch * P * 8);
   L.nacc = take(P * 4);
+  L.wacc = take(P * 4);
   L.la = take(nl * P * 8);
   L.acc = take(nl * P);
   L.U = take(2 * nl * P * 8);
@@ -193,6 +194,7 @@ struct diam_ctx {
   int32_t last_batch;
   void *V, *W, *Wlo, *Xi, *win, *wint, *Llow, *syrk;
   int32_t* nacc;
+  int32_t* wacc;  // accepted proposals per chain since the last update (step-size adaptation)
   uint8_t* acc;
   Status* status;
   int nrb, nch;
@@ -204,6 +206,10 @@ struct diam_ctx {
   double N;
   int64_t windows;
   int64_t last_call_steps;
+  int64_t win_steps;  // steps since the last update
+  // step-size adaptation (Algorithm 1): band, factor, cap
+  int adapt_on;
+  double acc_min, acc_max, adapt_factor, beta_max;
   int last_call_stages;
   int last_call_caller_w;   // last call's Xi is at Xi offset 0
   // event timing
@@ -443,6 +449,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
     c->t64 = c->Zs = nullptr;
   }
   c->nacc = (int32_t*)(c->ws + lay.nacc);
+  c->wacc = (int32_t*)(c->ws + lay.wacc);
   c->la = dptr(c, lay.la);
   c->acc = (uint8_t*)(c->ws + lay.acc);
   c->U = dptr(c, lay.U);
@@ -474,6 +481,8 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->steps = 0;
   c->siw = 0;
   c->last_jitter = -1;
+  c->win_steps = 0;
+  c->adapt_on = 0;
   c->N = 0.0;
   c->windows = 0;
   c->last_call_steps = 0;
@@ -507,6 +516,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   hipLaunchKernelGGL(k_fill, dim3(nblk(d)), dim3(256), 0, s, c->m, (long)d, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nblk(dd)), dim3(256), 0, s, c->S, dd, 0.0);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->nacc, (long)P);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->wacc, (long)P);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
   HIPCHK_INIT(hipGetLastError());
   HIPCHK_INIT(dk::round_factor(c->prec, c->L, c->Llow, d, s));
@@ -588,6 +598,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.V = c->V;
   a.nrb = c->nrb;
   a.nacc = n_accepted ? n_accepted : c->nacc;
+  a.wacc = c->wacc;
   a.win = c->win;
   a.err = &c->status->err;
   a.v32 = c->logreg;
@@ -670,6 +681,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     HIPCHK(dk::proj_reduce(c->proj_part, n, c->nch, c->nproj, P, c->trace + c->trace_pos * nfun * P, nfun, s));
   if (tracing) c->trace_pos += n;
   c->siw += n;
+  c->win_steps += n;
   c->steps += n;
   c->last_call_steps = n;
   c->last_call_stages = stages;
@@ -789,6 +801,23 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
   return DIAM_OK;
 }
 
+extern "C" int diam_set_beta_adaptation(diam_ctx* c, int32_t on, double acc_min, double acc_max, double factor,
+                                        double beta_max) {
+  if (!c) return fail(DIAM_E_ARG, "null context");
+  if (on) {
+    if (!(acc_min >= 0.0 && acc_min < acc_max && acc_max <= 1.0))
+      return fail(DIAM_E_ARG, "need 0 <= acc_min < acc_max <= 1");
+    if (!(factor > 1.0) || !std::isfinite(factor)) return fail(DIAM_E_ARG, "factor must be finite and > 1");
+    if (!(beta_max > 0.0 && beta_max <= 1.0)) return fail(DIAM_E_ARG, "beta_max must lie in (0, 1]");
+    c->acc_min = acc_min;
+    c->acc_max = acc_max;
+    c->adapt_factor = factor;
+    c->beta_max = beta_max;
+  }
+  c->adapt_on = on ? 1 : 0;
+  return DIAM_OK;
+}
+
 extern "C" int diam_psrf_enable(diam_ctx* c, int32_t on) {
   if (!c) return fail(DIAM_E_ARG, "null context");
   if (on) c->psrf_n = 0.0;  // zeroed lazily: the first fold after this overwrites
@@ -842,6 +871,20 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
   const int d = c->cfg.d, P = c->cfg.P;
   hipStream_t s = c->stream;
   Status st;
+  // step-size adaptation (Algorithm 1, update block): the acceptance ratio of
+  // the steps since the last update, pooled over the chains, against the band
+  if (c->adapt_on && c->win_steps > 0) {
+    std::vector<int32_t> wa(P);
+    HIPCHK(hipMemcpyAsync(wa.data(), c->wacc, P * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long tot = 0;
+    for (int p = 0; p < P; ++p) tot += wa[p];
+    const double rate = (double)tot / ((double)P * (double)c->win_steps);
+    if (rate > c->acc_max) c->cfg.beta = std::min(c->cfg.beta * c->adapt_factor, c->beta_max);
+    else if (rate < c->acc_min) c->cfg.beta = c->cfg.beta / c->adapt_factor;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->wacc, (long)P);
+  c->win_steps = 0;
   int ps = prof_begin(c, DIAM_ST_CHOL);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
   HIPCHK(dk::cov_assemble(c->S, c->m, 0.0, c->Lnew, &c->status->trace, d, s));
@@ -990,6 +1033,7 @@ extern "C" int diam_get_stats(diam_ctx* c, diam_stats* out) {
   out->n_samples = c->N;
   out->windows = c->windows;
   out->last_call_steps = c->last_call_steps;
+  out->beta = c->cfg.beta;
   return DIAM_OK;
 }
 

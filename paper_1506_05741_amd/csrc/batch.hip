@@ -762,6 +762,7 @@ extern "C" int diam_batch_get_stats(diam_batch* b, diam_stats* out) {
   out->n_samples = b->N;
   out->windows = b->windows;
   out->last_call_steps = b->n;
+  out->beta = b->cfg.beta;
   return DIAM_OK;
 }
 

@@ -144,6 +144,7 @@ struct StepArgs {
   uint16_t* v3;                           // non-null: write V as three bf16 parts (d x P each) instead
   int ldv;                                // leading dimension of V (0: d)
   int ldw;                                // leading dimension of Xi and W (0: d)
+  int32_t* wacc;                          // P: accepted proposals since the last update (optional)
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
 // PSRF accumulators (Section 2.4.2, M = 1): merge the nw stored states of

@@ -1414,6 +1414,7 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
       a.lp_nxt[p] = acc ? lpp : lp;
       a.zq_nxt[p] = acc ? zs : zq;
       a.nacc[p] += acc ? 1 : 0;
+      if (a.wacc) a.wacc[p] += acc ? 1 : 0;
       a.la_out[p] = la;
       a.acc_out[p] = acc ? 1 : 0;
       if (a.da) a.s_out[p] = acc ? a.s_new[p] : a.s_in[p];
@@ -1588,6 +1589,7 @@ DEV void decide_block(const StepArgs& a, int nch, int p) {
   a.lp_nxt[p] = acc ? lpp : lp;
   a.zq_nxt[p] = acc ? zs : zq;
   a.nacc[p] += acc ? 1 : 0;
+  if (a.wacc) a.wacc[p] += acc ? 1 : 0;
   a.la_out[p] = la;
   a.acc_out[p] = acc ? 1 : 0;
   if (a.da) a.s_out[p] = acc ? a.s_new[p] : a.s_in[p];

@@ -29,7 +29,7 @@ EXPORTED = (
     "diam_seed_moments", "diam_set_trace", "diam_field_bytes", "diam_get", "diam_get_stats",
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
-    "diam_psrf_enable", "diam_psrf", "diam_moment_error",
+    "diam_set_beta_adaptation", "diam_psrf_enable", "diam_psrf", "diam_moment_error",
     "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
     "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_field_bytes",
     "diam_batch_get", "diam_batch_get_stats", "diam_batch_destroy",
@@ -63,7 +63,8 @@ class BatchConfig(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("steps_in_window", ctypes.c_int32), ("last_jitter", ctypes.c_int32),
-                ("n_samples", ctypes.c_double), ("windows", ctypes.c_int64), ("last_call_steps", ctypes.c_int64)]
+                ("n_samples", ctypes.c_double), ("windows", ctypes.c_int64), ("last_call_steps", ctypes.c_int64),
+                ("beta", ctypes.c_double)]
 
 
 class DiamError(RuntimeError):
@@ -104,6 +105,7 @@ def load(path: str = LIB_PATH):
                                  ctypes.c_int),
         "diam_surrogate_eval": ([vp, vp, i32, vp], ctypes.c_int),
         "diam_set_delayed_acceptance": ([vp, i32], ctypes.c_int),
+        "diam_set_beta_adaptation": ([vp, i32, dbl, dbl, dbl, dbl], ctypes.c_int),
         "diam_psrf_enable": ([vp, i32], ctypes.c_int),
         "diam_psrf": ([vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "diam_moment_error": ([vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
@@ -267,6 +269,12 @@ class Sampler:
     def set_delayed_acceptance(self, on=True):
         _check(self.lib.diam_set_delayed_acceptance(self.ctx, 1 if on else 0))
         self.da_on = bool(on)
+
+    # -- step-size adaptation (Algorithm 1) ----------------------------------------------
+    def set_beta_adaptation(self, on=True, acc_min=0.3, acc_max=0.5, factor=1.2, beta_max=1.0):
+        """At every update, beta *= factor (capped) above the acceptance band, /= factor below it."""
+        _check(self.lib.diam_set_beta_adaptation(self.ctx, 1 if on else 0, float(acc_min), float(acc_max),
+                                                 float(factor), float(beta_max)))
 
     # -- convergence diagnostic ------------------------------------------------------
     def psrf_enable(self, on=True):

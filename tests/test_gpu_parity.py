@@ -306,3 +306,51 @@ def test_trace_records_log_density_and_projections():
         pr.s.update_proposal()
         pr.o.merge_moments()
         pr.o.update_proposal()
+
+
+def test_beta_adaptation_follows_the_oracle():
+    """Step-size adaptation of Algorithm 1 on both sides: decisions equal step
+    for step, beta after every update bitwise equal.  The exact warm start
+    with a small beta (every proposal accepted) drives beta up; moments seeded
+    with a 9x over-dispersed covariance (proposals far too wide) drive it
+    down."""
+    d, P, n_lag = 24, 8, 12
+    adapt = (0.3, 0.5, 1.25, 0.9)
+    for warm, beta0 in ((True, 0.05), (False, 0.6)):
+        t = synth.gaussian_target(d, 9)
+        pr = Pair(d, P, n_lag, 9, warm=warm, beta=beta0, share_factor=True,
+                  x0=synth.gaussian_exact_draws(t, P, 59))
+        if not warm:
+            S9 = 9.0 * t.Sigma + np.outer(t.mu, t.mu)
+            assert pr.s.seed_moments(dev(S9), dev(t.mu), 1e12)[0] == diam.OK
+            assert pr.o.seed_moments(S9, t.mu, 1e12) == od.OK
+            pr.adopt()
+        pr.o.adapt = adapt
+        pr.s.set_beta_adaptation(True, *adapt)
+        betas = []
+        rng = np.random.default_rng(21 if warm else 22)
+        for w in range(6):
+            W = rng.standard_normal((n_lag, P, d))
+            U = synth.draw_uniforms(P, n_lag, 100 + w)
+            upto, tie = run_window(pr, W, U)
+            if tie < n_lag:
+                log(f"near-tie at step {tie} of window {w}: stopping the comparison")
+                break
+            check_merge_update(pr)
+            b = pr.s.stats()["beta"]
+            assert b == pr.o.beta, (w, b, pr.o.beta)
+            betas.append(b)
+        log(f"{'exact' if warm else 'over-dispersed'} start, beta0 {beta0}: beta after each update {betas}")
+        assert len(set(betas)) > 1                        # the rule moved beta
+    with pytest.raises(diam.DiamError):
+        pr.s.set_beta_adaptation(True, 0.5, 0.3, 1.25, 0.9)
+    with pytest.raises(diam.DiamError):
+        pr.s.set_beta_adaptation(True, 0.3, 0.5, 1.0, 0.9)
+    with pytest.raises(diam.DiamError):
+        pr.s.set_beta_adaptation(True, 0.3, 0.5, 1.25, 1.5)
+    b = pr.s.stats()["beta"]
+    pr.s.set_beta_adaptation(False)
+    pr.s.step_batch(n_lag)
+    pr.s.merge_moments()
+    assert pr.s.update_proposal()[0] == diam.OK
+    assert pr.s.stats()["beta"] == b                     # off: beta stays
