@@ -57,3 +57,36 @@ def twisted2d_logpdf(X: np.ndarray, b: float, var: np.ndarray) -> np.ndarray:
     Y = twist(X, b)
     return (-0.5 * (Y[0] ** 2 / var[0] + Y[1] ** 2 / var[1])
             - 0.5 * np.log((2.0 * np.pi) ** 2 * var[0] * var[1]))
+
+
+def twisted_logpdf(R: np.ndarray, mu: np.ndarray, c: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """The twisted Gaussians of Section 3.1 (pi_5, pi_6) in whitened form.
+
+    pi = pi_1 o V o phi o V^T with pi_1 = N(0, V Sigma V^T) and
+    phi(u)_i = u_i + b_{i-1} u_{i-1}^2 on the pairs i = 2, 4, ..., d/10 (1-based).
+    With y = R (x - mu), R = Sigma^-1/2 V^T (so y_i = u_i / sigma_i), the
+    density is -1/2 sum_i z_i^2 with z_i = y_i + c_i y_{i-1}^2 on the twisted
+    rows, c_i = b_{i-1} sigma_{i-1}^2 / sigma_i, and z_i = y_i elsewhere.  The
+    pairs are rows (2k, 2k+1) 0-based; c is read at the odd rows only.  No
+    Jacobian term: det(d phi) = 1.  Up to the normalising constant.
+    """
+    Y = R @ (X - mu[:, None])
+    Z = Y.copy()
+    Z[1::2] += c[1::2, None] * Y[0:Y.shape[0] - Y.shape[0] % 2:2] ** 2
+    return -0.5 * np.sum(Z * Z, axis=0)
+
+
+def twisted_u_moments(sig2: np.ndarray, b: float):
+    """Exact mean and variance of u = V^T x under pi_5 / pi_6 (Section 3.1):
+    for i = 2, 4, ..., d/10 (1-based), E[u_i] = -b_{i-1} sigma_{i-1}^2 and
+    Var[u_i] = sigma_i^2 + 2 b_{i-1}^2 sigma_{i-1}^4 with b_i = b sigma_i^-2 / sqrt(d);
+    mean 0 and variance sigma_i^2 for the other coordinates."""
+    d = sig2.size
+    mean = np.zeros(d)
+    var = np.array(sig2, dtype=np.float64, copy=True)
+    for i in range(2, d // 10 + 1, 2):
+        k = i - 1                                        # 0-based twisted row; k - 1 is its partner
+        bp = b / sig2[k - 1] / np.sqrt(d)
+        mean[k] = -bp * sig2[k - 1]
+        var[k] = sig2[k] + 2.0 * bp ** 2 * sig2[k - 1] ** 2
+    return mean, var

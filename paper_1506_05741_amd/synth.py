@@ -101,6 +101,49 @@ def gaussian_warm_moments(t: GaussianTarget):
 
 
 @dataclass
+class TwistedTarget:
+    d: int
+    b: float
+    V: np.ndarray        # eigenvectors of C, ascending eigenvalues (first = smallest)
+    sig2: np.ndarray     # the eigenvalues (variances of u = V^T x under pi_1)
+    R: np.ndarray        # Sigma^-1/2 V^T: y = R x has y_i = u_i / sigma_i
+    mu: np.ndarray       # zeros (the maximiser of pi_5 / pi_6 is 0)
+    c: np.ndarray        # twist weights on the odd rows (0-based) of y, zero elsewhere
+
+
+def twisted_target(d: int, seed: int, b: float) -> TwistedTarget:
+    """pi_5 (b = 0.3) / pi_6 (b = 2) of Section 3.1: pi_1 = N(0, C), C = (B + I)^-1,
+    B = A A^T with A a seeded standard normal d x d matrix; V, sigma^2 the
+    ordered eigendecomposition of C (smallest first); twist pairs i = 2, 4,
+    ..., d/10 (1-based) with b_i = b sigma_i^-2 / sqrt(d).  The weights c_i =
+    b_{i-1} sigma_{i-1}^2 / sigma_i of the whitened form are written to the
+    odd rows k = i - 1 (0-based)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((d, d))
+    lamB, U = np.linalg.eigh(A @ A.T)                  # ascending eigenvalues of B
+    sig2 = 1.0 / (lamB[::-1] + 1.0)                    # eigenvalues of C, ascending
+    V = U[:, ::-1].copy()
+    R = (V / np.sqrt(sig2)[None, :]).T.copy()
+    c = np.zeros(d)
+    for i in range(2, d // 10 + 1, 2):
+        k = i - 1
+        c[k] = (b / sig2[k - 1] / math.sqrt(d)) * sig2[k - 1] / math.sqrt(sig2[k])
+    return TwistedTarget(d=d, b=b, V=V, sig2=sig2, R=R, mu=np.zeros(d), c=c)
+
+
+def twisted_exact_draws(t: TwistedTarget, n: int, seed: int) -> np.ndarray:
+    """n exact draws as a d x n array: w ~ N(0, diag(sigma^2)), u = phi^-1(w)
+    (u_i = w_i - b_{i-1} w_{i-1}^2 on the twisted pairs), x = V u."""
+    rng = np.random.default_rng(seed)
+    w = np.sqrt(t.sig2)[:, None] * rng.standard_normal((t.d, n))
+    u = w.copy()
+    for i in range(2, t.d // 10 + 1, 2):
+        k = i - 1
+        u[k] = w[k] - (t.b / t.sig2[k - 1] / math.sqrt(t.d)) * w[k - 1] ** 2
+    return t.V @ u
+
+
+@dataclass
 class LogRegData:
     A: np.ndarray        # (n, d) float32
     y: np.ndarray        # (n,)   float32 in {0, 1}
