@@ -97,7 +97,15 @@ typedef struct {
  *   log pi(w) = sum_j [ y_j t_j - softplus(t_j) ] - |w|^2 / (2 prior_var),
  *   t = A w, A n_obs x d row-major FP32, y in {0, 1} FP32.
  * The contraction runs on FP32 MFMA (the data are FP32) with the per-row
- * terms summed in FP64; the prior is FP64. */
+ * terms summed in FP64; the prior is FP64.
+ * Twisted Gaussians (DIAM_TGT_GAUSS with twist non-NULL; Section 3.1's pi_5
+ * and pi_6, pi_1 o V o phi o V^T with det(d phi) = 1): with y = R (x - mu),
+ *   log pi(x) = -1/2 sum_i z_i^2,  z_{2k+1} = y_{2k+1} + twist[2k+1] y_{2k}^2,
+ *   z_{2k} = y_{2k}  (0-based; twist at even rows is ignored).
+ * For the paper's targets R = Sigma^-1/2 V^T (V, Sigma the eigendecomposition
+ * of pi_1's covariance, smallest first), mu = 0 and twist[i] = b / (sqrt(d)
+ * sigma_i) on the rows i = 1, 3, ..., d/10 - 1, zero elsewhere.  twist: d
+ * FP64 on the device, 8-byte aligned; the batched form does not take it. */
 typedef struct {
   int32_t kind;
   int32_t reserved;
@@ -107,6 +115,7 @@ typedef struct {
   const float* y;       /* logistic */
   int64_t n_obs;        /* logistic */
   double prior_var;     /* logistic */
+  const double* twist;  /* Gaussian, optional: twisted Gaussian weights (d) */
 } diam_target;
 
 /* Fields readable with diam_get (device-to-device copy, asynchronous). */

@@ -247,7 +247,9 @@ static int check_target(const diam_config* c, const diam_target* t) {
   if (t->kind == DIAM_TGT_GAUSS) {
     if (!t->mu || !t->R) return fail(DIAM_E_ARG, "Gaussian target needs mu and R");
     if ((uintptr_t)t->mu % 16 || (uintptr_t)t->R % 16) return fail(DIAM_E_ARG, "mu and R must be 16-byte aligned");
+    if ((uintptr_t)t->twist % 8) return fail(DIAM_E_ARG, "twist must be 8-byte aligned");
   } else if (t->kind == DIAM_TGT_LOGREG) {
+    if (t->twist) return fail(DIAM_E_ARG, "twist applies to the Gaussian target only");
     if (!t->A || !t->y || t->n_obs < 1 || t->n_obs > (1L << 30)) return fail(DIAM_E_ARG, "logistic target needs A, y, n_obs >= 1");
     if (!(t->prior_var > 0.0)) return fail(DIAM_E_ARG, "prior_var must be > 0");
   } else {
@@ -529,9 +531,9 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
     if (c->s3) {
       HIPCHK_INIT(dk::split3_f32((const float*)tgt->R, (long)d * d, c->R3, s));
       HIPCHK_INIT(dk::split3_f32((const float*)c->V, (long)d * P, c->V3, s));
-      HIPCHK_INIT(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s));
+      HIPCHK_INIT(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s, tgt->twist));
     } else {
-      HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s));
+      HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s, tgt->twist));
     }
   }
   HIPCHK_INIT(dk::init_finish(c->lpp_part, c->nrb, c->Z, c->X, c->prior_w, c->lp, c->zq, d, P, s));
@@ -634,9 +636,9 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
       HIPCHK(dk::tgt_logreg(c->tgt.A, c->tgt.y, c->tgt.n_obs, c->da_on ? c->Vs : (const float*)c->V, d, P,
                             c->da_on ? c->nsurv : nullptr, c->lpp_part, s));
     else if (c->s3)
-      HIPCHK(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s));
+      HIPCHK(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s, c->tgt.twist));
     else
-      HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s));
+      HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s, c->tgt.twist));
     prof_end(c, ps);
     a.do_accept = 1;
     a.xi_cur = at(c->Xi, (long)t * dP, eb);

@@ -21,7 +21,10 @@ inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 // contributions: log pi(x_p) = sum_rb part[p][rb] (+ the prior, for the
 // logistic target, added by the step kernel).
 // Gaussian: part[p][rb] = -1/2 sum over rows of block rb of (R (x_p - mu))_i^2.
-hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s);
+// twist (optional, d FP64): the twisted Gaussians (Section 3.1): row 2k+1's
+// y gains twist[2k+1] * y_{2k}^2 before it is squared.
+hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s,
+                     const double* twist = nullptr);
 // Mixed form, Gaussian: the same partials from three-part bf16 splits of R
 // and V (FP32-equivalent products); needs tgt_s3_ok(d, P); Yp scratch of
 // tgt_s3_scratch_bytes.  split3_f32 writes the parts of n floats at dst,
@@ -29,7 +32,8 @@ hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, doub
 bool tgt_s3_ok(int d, int P);
 size_t tgt_s3_scratch_bytes(int d, int P);
 hipError_t split3_f32(const float* src, long n, uint16_t* dst, hipStream_t s);
-hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s);
+hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s,
+                        const double* twist = nullptr);
 // Logistic: part[p][rb] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
 // (A n_obs x d row-major FP32, V d x P FP32); columns >= *nact skipped.
 int logreg_row_blocks(long n_obs);

@@ -22,7 +22,7 @@ DEV double propose1(double xr, double x, double rho, double xi) { return __fma_r
 // row-block partials are contiguous for the reader).
 template <typename T, int BK, int BM, int BN, int KG>
 DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d, int P, int bx, int by,
-                        double* __restrict__ part, int ldp) {
+                        double* __restrict__ part, int ldp, const double* __restrict__ twist = nullptr) {
   __shared__ T lds[KG * e_lds_elems<T, BM, BN, BK>()];
   __shared__ double red[2][BN];
   const int i0 = bx * BM, j0 = by * BN;
@@ -40,6 +40,16 @@ DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double y = (double)f.c[m][n][r];
+          if (twist) {
+            // twisted target: row 2k+1 gets c y_{2k}^2 added before squaring.  Its
+            // partner row sits in the same lane (FP32 layout: rows 4q + r) or in
+            // lane ^ 16 (FP64 layout: rows 4r + q)
+            const double yp = (sizeof(T) == 8) ? __shfl_xor(y, 16, 64) : (double)f.c[m][n][r & ~1];
+            int ti, tj;
+            frag_coords<BM, BN, T>(m, n, r, ti, tj);
+            const int i = i0 + ti;
+            if ((i & 1) && i < d) y = __fma_rn(twist[i], yp * yp, y);
+          }
           s = __fma_rn(y, y, s);
         }
       s += __shfl_xor(s, 16, 64);
@@ -56,8 +66,8 @@ DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d,
 
 template <typename T, int BK>
 __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, const T* __restrict__ V, int d, int P,
-                                                   double* __restrict__ part) {
-  tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, gridDim.x);
+                                                   double* __restrict__ part, const double* __restrict__ twist) {
+  tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, gridDim.x, twist);
 }
 
 // ---- split-BF16 target (mixed form): Y = R V with both operands in three
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_s3(const u16* __restrict
 
 // part[j][rb] = -1/2 sum over rows of block rb of (sum_s Yp[s])^2, one wave per (j, rb)
 __global__ __launch_bounds__(256) void k_tgt_s3_reduce(const float* __restrict__ Yp, int d, int P, int nrb,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, const double* __restrict__ twist) {
   const int lane = threadIdx.x & 63;
   const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= (long)P * nrb) return;
@@ -123,6 +133,11 @@ __global__ __launch_bounds__(256) void k_tgt_s3_reduce(const float* __restrict__
   double y = 0.0;
   if (i < d)
     for (int s = 0; s < S3_KSPLIT; ++s) y += (double)Yp[((long)s * P + j) * d + i];
+  if (twist) {
+    // twisted target: row 2k+1 (odd lane, as blocks start at even rows) gets c y_{2k}^2
+    const double yp = __shfl_xor(y, 1, 64);
+    if ((i & 1) && i < d) y = __fma_rn(twist[i], yp * yp, y);
+  }
   const double q = wave_sum_f64(y * y);
   if (lane == 0) part[(long)j * nrb + rb] = -0.5 * q;
 }
@@ -131,7 +146,8 @@ bool tgt_s3_ok(int d, int P) { return d % (S3_KSPLIT * 32) == 0 && d % 64 == 0 &
 
 size_t tgt_s3_scratch_bytes(int d, int P) { return (size_t)S3_KSPLIT * d * P * sizeof(float); }
 
-hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s) {
+hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s,
+                        const double* twist) {
   // 128 x 128 tiles on 8 waves where they fit (measured 1.45x the rate of 64 x 64)
   if (d % 128 == 0 && P % 128 == 0)
     hipLaunchKernelGGL((k_tgt_s3<128, 128, 4, 2>), dim3(d / 128, P / 128, S3_KSPLIT), dim3(512), 0, s,
@@ -142,16 +158,19 @@ hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, fl
   const int nrb = tgt_row_blocks(d);
   const long waves = (long)P * nrb;
   hipLaunchKernelGGL(k_tgt_s3_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, d, P, nrb,
-                     part);
+                     part, twist);
   return hipGetLastError();
 }
 
-hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s) {
+hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s,
+                     const double* twist) {
   dim3 grid(cdiv(d, TGT_BM), cdiv(P, 64));
   if (prec == P64)
-    hipLaunchKernelGGL((k_tgt_gauss<double, 16>), grid, dim3(512), 0, s, (const double*)R, (const double*)V, d, P, part);
+    hipLaunchKernelGGL((k_tgt_gauss<double, 16>), grid, dim3(512), 0, s, (const double*)R, (const double*)V, d, P, part,
+                       twist);
   else
-    hipLaunchKernelGGL((k_tgt_gauss<float, 32>), grid, dim3(512), 0, s, (const float*)R, (const float*)V, d, P, part);
+    hipLaunchKernelGGL((k_tgt_gauss<float, 32>), grid, dim3(512), 0, s, (const float*)R, (const float*)V, d, P, part,
+                       twist);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ class Config(ctypes.Structure):
 class Target(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu", ctypes.c_void_p),
                 ("R", ctypes.c_void_p), ("A", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_obs", ctypes.c_int64),
-                ("prior_var", ctypes.c_double)]
+                ("prior_var", ctypes.c_double), ("twist", ctypes.c_void_p)]
 
 
 class BatchConfig(ctypes.Structure):
@@ -147,13 +147,13 @@ def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitt
     return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, int(surrogate), int(train_max))
 
 
-def gauss_target(mu, R):
-    return Target(TGT_GAUSS, 0, _addr(mu), _addr(R), None, None, 0, 0.0)
+def gauss_target(mu, R, twist=None):
+    return Target(TGT_GAUSS, 0, _addr(mu), _addr(R), None, None, 0, 0.0, _addr(twist))
 
 
 def logreg_target(A, y, prior_var):
     n_obs = 0 if A is None else A.shape[0]
-    return Target(TGT_LOGREG, 0, None, None, _addr(A), _addr(y), n_obs, float(prior_var))
+    return Target(TGT_LOGREG, 0, None, None, _addr(A), _addr(y), n_obs, float(prior_var), None)
 
 
 def _addr(t):
@@ -175,7 +175,8 @@ class Sampler:
     ``Sampler(cfg, None, None, x0, A=A, y=y, prior_var=v)`` with A (n_obs, d)
     and y (n_obs,) FP32."""
 
-    def __init__(self, cfg: Config, mu, R, x0, stream=None, A=None, y=None, prior_var=None):
+    def __init__(self, cfg: Config, mu, R, x0, stream=None, A=None, y=None, prior_var=None, twist=None):
+        """twist (optional, CUDA float64, d): the twisted Gaussians of the paper's test set."""
         import torch
         lib = load()
         self.torch = torch
@@ -187,8 +188,10 @@ class Sampler:
             rdt = torch.float64 if cfg.precision == FP64 else torch.float32
             assert mu.dtype == torch.float64 and mu.is_cuda and mu.numel() == cfg.d and mu.is_contiguous()
             assert R.dtype == rdt and R.is_cuda and R.shape == (cfg.d, cfg.d) and R.is_contiguous()
-            self._keep = [mu, R, x0]
-            self.tgt = gauss_target(mu, R)
+            if twist is not None:
+                assert twist.dtype == torch.float64 and twist.is_cuda and twist.numel() == cfg.d
+            self._keep = [mu, R, x0, twist]
+            self.tgt = gauss_target(mu, R, twist)
         else:
             assert A.dtype == torch.float32 and A.is_cuda and A.dim() == 2 and A.shape[1] == cfg.d
             assert A.is_contiguous() and y.dtype == torch.float32 and y.is_cuda and y.numel() == A.shape[0]

@@ -310,3 +310,25 @@ def test_full_size_batch():
     b.close()
     for s in singles.values():
         s.close()
+
+
+def test_full_size_twisted_log_density(setup):
+    """The twisted-target pairing at the benchmark size and launch
+    configuration (split-bf16 128 x 128 tiles, K split in 4, the reduction
+    that applies the twist): log pi of sampled chains against FP64, with a
+    twist weight on every odd row."""
+    t, x0, s, N0 = setup
+    c = np.zeros(D)
+    c[1::2] = np.random.default_rng(9).uniform(-0.2, 0.2, D // 2)
+    cfg = diam.make_config(D, P, NL, "mixed", beta=BETA, seed=77)
+    s2 = diam.Sampler(cfg, dev(t.mu), dev(t.R, torch.float32), dev(x0.T), twist=dev(c))
+    lp = host(s2.get_f64(diam.F_LOGP, (P,)))
+    J = [0, 63, 128, 255]
+    for j in J:
+        y = t.R @ (x0[:, j] - t.mu)
+        z = y.copy()
+        z[1::2] += c[1::2] * y[0::2] ** 2
+        ref = -0.5 * float(z @ z)
+        assert abs(lp[j] - ref) <= 1e-5 * (1 + abs(ref)), (j, lp[j], ref)
+    s2.close()
+    log(f"twisted log pi at d={D}: matches FP64 on chains {J}")
