@@ -50,6 +50,18 @@ def diam_proposal(X, x_ref, A, W, beta, alpha=1.0):
     return x_ref[:, None] + rho * (X - x_ref[:, None]) + beta * alpha * (A @ W)
 
 
+def rw_proposal(X, A, W, beta, alpha=1.0):
+    """x' = x + beta alpha A W: the random walk of Section 2.3.1 (eq. rw), and
+    adaptive Metropolis (Section 2.3.3) when A factors the sample covariance."""
+    return X + beta * alpha * (A @ W)
+
+
+def symmetric_log_accept_ratio(lp_new, lp_old):
+    """log alpha(x, x') = log pi(x') - log pi(x): the proposal density of eq. rw
+    is symmetric in (x, x')."""
+    return lp_new - lp_old
+
+
 def whiten(A, x_ref, X):
     """A^-1 (x - x_ref) for each column, by a triangular solve against the
     lower factor A (the product Algorithm 1 applies to every state)."""
@@ -131,11 +143,21 @@ def cholesky_jitter(C, jitter0=1e-12, tries=13):
     return None, tries
 
 
+PROPOSALS = ("diam", "am", "pcn", "rw")
+
+
 @dataclass
 class DiamOracle:
     """P chains of Algorithm 1 sharing one proposal factor (M = 1).
 
     ``logpi`` maps a d x n block to n log-densities.  States are d x P.
+
+    ``proposal`` selects the family of Section 2.3 run through the same
+    logistics: "diam" (eq. diamnl, factor and pivot adapted), "am" (eq. rw
+    with the adapted factor, Section 2.3.3), "pcn" (eq. pcn: the DIAM formula
+    with the factor and pivot fixed after initialisation or a warm start) and
+    "rw" (eq. rw with a fixed factor).  Under the fixed families an update
+    adapts beta only.
     """
     logpi: object
     d: int
@@ -160,8 +182,11 @@ class DiamOracle:
     adapt: tuple = None
     win_acc: int = 0
     win_steps: int = 0
+    proposal: str = "diam"
 
     def __post_init__(self):
+        if self.proposal not in PROPOSALS:
+            raise ValueError(f"unknown proposal {self.proposal!r}")
         d, P = self.d, self.P
         if self.X is None:
             self.X = np.zeros((d, P))
@@ -177,19 +202,34 @@ class DiamOracle:
 
     # -- warm start: seed the global moments, then factorise once ----------
     def seed_moments(self, S0, m0, N0):
+        """Replace the global moments, then refactorise (under every family:
+        this is how a fixed family receives its prior factor and mean)."""
         self.S_glob = np.array(S0, dtype=np.float64, copy=True)
         self.m_glob = np.array(m0, dtype=np.float64, copy=True)
         self.N = float(N0)
-        return self.update_proposal()
+        self.adapt_beta()
+        return self.refactor()
+
+    @property
+    def walk(self):
+        return self.proposal in ("am", "rw")
 
     # -- one step of all P chains (Algorithm 1, loop body) -----------------
     def step(self, W, u):
-        Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
-        Zp = whiten(self.A, self.x_ref, Xp)
-        lpp = self.logpi(Xp)
-        if np.any(np.isposinf(lpp)):
-            raise FloatingPointError("log density returned +inf")
-        la = log_accept_ratio(lpp, self.lp, Zp, self.Z, self.alpha)
+        if self.walk:
+            Xp = rw_proposal(self.X, self.A, W, self.beta, self.alpha)
+            lpp = self.logpi(Xp)
+            if np.any(np.isposinf(lpp)):
+                raise FloatingPointError("log density returned +inf")
+            la = symmetric_log_accept_ratio(lpp, self.lp)
+            Zp = self.Z
+        else:
+            Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
+            Zp = whiten(self.A, self.x_ref, Xp)
+            lpp = self.logpi(Xp)
+            if np.any(np.isposinf(lpp)):
+                raise FloatingPointError("log density returned +inf")
+            la = log_accept_ratio(lpp, self.lp, Zp, self.Z, self.alpha)
         acc = accept_decisions(la, u)
         self.X[:, acc] = Xp[:, acc]
         self.Z[:, acc] = Zp[:, acc]
@@ -207,12 +247,19 @@ class DiamOracle:
         Stage 1 runs the DIAM acceptance with the surrogate log-density in
         place of log pi.  Survivors face stage 2 with
         log alpha_2 = (log pi(x') - log pi(x)) - (s(x') - s(x)),
-        which makes the composite kernel reversible for pi itself.  Returns
+        which makes the composite kernel reversible for pi itself.  Under the
+        random-walk families stage 1 is the symmetric ratio of s.  Returns
         (accepted, stage-1 survivors, updated s_cur)."""
-        Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
-        Zp = whiten(self.A, self.x_ref, Xp)
-        sp = surrogate(Xp)
-        la1 = log_accept_ratio(sp, s_cur, Zp, self.Z, self.alpha)
+        if self.walk:
+            Xp = rw_proposal(self.X, self.A, W, self.beta, self.alpha)
+            Zp = self.Z
+            sp = surrogate(Xp)
+            la1 = symmetric_log_accept_ratio(sp, s_cur)
+        else:
+            Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
+            Zp = whiten(self.A, self.x_ref, Xp)
+            sp = surrogate(Xp)
+            la1 = log_accept_ratio(sp, s_cur, Zp, self.Z, self.alpha)
         pass1 = accept_decisions(la1, u1)
         acc = np.zeros(self.P, dtype=bool)
         if np.any(pass1):
@@ -259,6 +306,11 @@ class DiamOracle:
 
     def update_proposal(self):
         self.adapt_beta()
+        if self.proposal in ("pcn", "rw"):
+            return OK
+        return self.refactor()
+
+    def refactor(self):
         C = sample_covariance(self.S_glob, self.m_glob)
         A, j = cholesky_jitter(C, self.jitter0, self.jitter_tries)
         self.last_jitter = j

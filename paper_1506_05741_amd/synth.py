@@ -17,6 +17,11 @@ Target recipes
   G first, then mu, from ``numpy.random.default_rng(seed)``.
   The density is carried by its whitening matrix R = diag(lambda^-1/2) Q^T,
   so that log pi(x) = -1/2 ||R (x - mu)||^2 + const.
+* The paper's Gaussian test targets (Section 3.1), mean 0: with A a seeded
+  standard normal d x r matrix and B = A A^T, pi_1 = N(0, (B + I)^-1)
+  (r = d), pi_2 = N(0, (B/d + I)^-1), pi_3 = pi_1 with r = d/10, and pi_4 =
+  N(0, V diag[(sigma^-2 n^-4 + 1)^-1] V^T) with V the eigenvectors of pi_1's
+  covariance, smallest variance first, n = 1 .. d (``paper_gaussian``).
 * Bayesian logistic regression: design A (n x d, FP32, entries N(0, 1/d)),
   true weights w ~ N(0, I), labels y ~ Bernoulli(sigmoid(A w)), prior
   N(0, prior_var I); draws in that order from ``default_rng(seed)``.
@@ -42,6 +47,10 @@ __all__ = [
     "gaussian_target",
     "gaussian_exact_draws",
     "gaussian_warm_moments",
+    "paper_gaussian",
+    "twisted_target",
+    "twisted_exact_draws",
+    "twisted_warm_moments",
     "LogRegData",
     "logreg_data",
     "batch_dims",
@@ -100,6 +109,33 @@ def gaussian_warm_moments(t: GaussianTarget):
     return t.Sigma + np.outer(t.mu, t.mu), t.mu.copy()
 
 
+def paper_gaussian(name: str, d: int, seed: int, sigma2: float = None) -> GaussianTarget:
+    """pi_1 .. pi_4 of Section 3.1 as a GaussianTarget (mu = 0; Q, lam in
+    descending order of variance).  sigma2 is pi_4's data variance (default
+    1/d, cond O(d); 1/d^2 gives cond O(d^2))."""
+    rng = np.random.default_rng(seed)
+    r = d // 10 if name == "pi3" else d
+    if r < 1:
+        raise ValueError("pi_3 needs d >= 10")
+    A = rng.standard_normal((d, r))
+    lamB, U = np.linalg.eigh(A @ A.T)          # ascending: U[:, j] has the j-th largest variance of C
+    if name in ("pi1", "pi3"):
+        lam = 1.0 / (lamB + 1.0)
+    elif name == "pi2":
+        lam = 1.0 / (lamB / d + 1.0)
+    elif name == "pi4":
+        s2 = 1.0 / d if sigma2 is None else float(sigma2)
+        n = np.arange(d, 0, -1, dtype=np.float64)  # U[:, j] is pi_1's (d - j)-th smallest-variance direction
+        lam = 1.0 / (n ** -4.0 / s2 + 1.0)
+    else:
+        raise ValueError(f"unknown target {name!r}")
+    Q = U.copy()
+    R = (Q / np.sqrt(lam)[None, :]).T.copy()
+    Sigma = (Q * lam[None, :]) @ Q.T
+    Sigma = 0.5 * (Sigma + Sigma.T)
+    return GaussianTarget(d=d, mu=np.zeros(d), Q=Q, lam=lam, R=R, Sigma=Sigma)
+
+
 @dataclass
 class TwistedTarget:
     d: int
@@ -141,6 +177,23 @@ def twisted_exact_draws(t: TwistedTarget, n: int, seed: int) -> np.ndarray:
         k = i - 1
         u[k] = w[k] - (t.b / t.sig2[k - 1] / math.sqrt(t.d)) * w[k - 1] ** 2
     return t.V @ u
+
+
+def twisted_warm_moments(t: TwistedTarget):
+    """Exact raw moments (S, m) of pi_5 / pi_6 for the warm start, from the
+    closed forms Section 3.1 gives for u = V^T x: on the twisted pairs
+    E[u_i] = -b_{i-1} sigma_{i-1}^2, Var[u_i] = sigma_i^2 + 2 b_{i-1}^2
+    sigma_{i-1}^4; elsewhere mean 0 and variance sigma_i^2 (u independent
+    across pairs)."""
+    mean = np.zeros(t.d)
+    var = t.sig2.copy()
+    for i in range(2, t.d // 10 + 1, 2):
+        k = i - 1
+        bk = t.b / t.sig2[k - 1] / math.sqrt(t.d)
+        mean[k] = -bk * t.sig2[k - 1]
+        var[k] = t.sig2[k] + 2.0 * bk * bk * t.sig2[k - 1] ** 2
+    m = t.V @ mean
+    return (t.V * var[None, :]) @ t.V.T + np.outer(m, m), m
 
 
 @dataclass
