@@ -330,6 +330,73 @@ def batch_experiment(args, torch, diam):
     return out
 
 
+FAMILY_BANDS = {"diam": (0.3, 0.5), "am": (0.1, 0.3), "pcn": (0.3, 0.5), "rw": (0.1, 0.3)}
+
+
+def families_experiment(args, torch, diam):
+    """Section 3.2's comparison (its Fig. 1) through the same kernels: DIAM,
+    AM, pCN and RW on pi_1, pi_2, pi_4 (data variance 1/d and 1/d^2) and pi_5
+    (alpha = 1.2) at d = 100, 32 chains, n_lag = 100, FP64, beta adapted from
+    2.4/sqrt(d) inside each family's acceptance band.  DIAM and AM start from
+    the exact moments (warm start); pCN and RW keep A = I, x_ref = 0.  The
+    second half of the run is traced and timed: ESS of log pi, v_d^T x and
+    v_1^T x, ESS/s = the minimum over the three / time of the traced windows."""
+    from paper_1506_05741_amd import synth
+    d, P, nl, W = 100, 32, 100, args.family_windows
+    half = W // 2
+    dev = torch.device("cuda:0")
+    out = {"workload": f"Section 3.2 comparison: d={d}, P={P}, n_lag={nl}, {W} windows (last {W - half} traced), "
+                       "fp64, beta adapted from 2.4/sqrt(d)", "targets": {}}
+    for tgt in ("pi1", "pi2", "pi4", "pi4s", "pi5"):
+        twist, alpha = None, 1.0
+        if tgt == "pi5":
+            tw = synth.twisted_target(d, 1, 0.3)
+            R, mu, twist, V = tw.R, tw.mu, tw.c, tw.V
+            x0 = synth.twisted_exact_draws(tw, P, 2)
+            S0, m0 = synth.twisted_warm_moments(tw)
+            v_d, v_1, alpha = V[:, -1], V[:, 0], 1.2
+        else:
+            name, s2 = ("pi4", 1.0 / d ** 2) if tgt == "pi4s" else (tgt, None)
+            t = synth.paper_gaussian(name, d, 1, s2)
+            R, mu = t.R, t.mu
+            x0 = synth.gaussian_exact_draws(t, P, 2)
+            S0, m0 = synth.gaussian_warm_moments(t)
+            v_d, v_1 = t.v_max, t.v_min
+        rows = {}
+        for prop in ("diam", "am", "pcn", "rw"):
+            band = FAMILY_BANDS[prop]
+            cfg = diam.make_config(d, P, nl, "fp64", beta=2.4 / math.sqrt(d), alpha=alpha, seed=31, proposal=prop)
+            smp = diam.Sampler(cfg, torch.as_tensor(mu, device=dev), torch.as_tensor(R, device=dev),
+                               torch.as_tensor(np.ascontiguousarray(x0.T), device=dev),
+                               twist=None if twist is None else torch.as_tensor(twist, device=dev))
+            smp.set_beta_adaptation(True, band[0], band[1], 1.2, 1.0)
+            if prop in ("diam", "am"):
+                assert smp.seed_moments(torch.as_tensor(S0, device=dev), torch.as_tensor(m0, device=dev),
+                                        10.0 * P * nl)[0] == diam.OK
+            for _ in range(half):
+                smp.step_batch(nl)
+                smp.merge_moments()
+                assert smp.update_proposal()[0] == diam.OK
+            trace = torch.zeros(((W - half) * nl, 3, P), dtype=torch.float64, device=dev)
+            smp.set_trace(torch.as_tensor(np.stack([v_d, v_1]), device=dev), trace)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(W - half):
+                smp.step_batch(nl)
+                smp.merge_moments()
+                assert smp.update_proposal()[0] == diam.OK
+            torch.cuda.synchronize()
+            T = time.perf_counter() - t1
+            tr = trace.cpu().numpy()
+            ess = [ess_per_chain(tr[:, f, :]) for f in range(3)]
+            rows[prop] = {"ess_per_s": min(ess) / T, "ess_per_step": [e / tr.shape[0] for e in ess],
+                          "chain_steps_per_s": P * nl * (W - half) / T, "beta": smp.stats()["beta"]}
+            smp.close()
+        out["targets"][tgt] = rows
+        log(f"families {tgt}: " + ", ".join(f"{k} {v['ess_per_s']:.4g} ESS/s" for k, v in rows.items()))
+    return out
+
+
 def cpu_baseline(tgt, args):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: a few steps of all P chains, one merge of those steps and one
@@ -396,6 +463,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form experiment")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-form experiment")
     ap.add_argument("--batch-windows", dest="batch_windows", type=int, default=6)
+    ap.add_argument("--no-families", action="store_true", help="skip the proposal-family comparison")
+    ap.add_argument("--families-only", action="store_true", help="run only the proposal-family comparison")
+    ap.add_argument("--family-windows", dest="family_windows", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -421,6 +491,9 @@ def main():
         return
     if args.learned_only:
         print(json.dumps({"learned": learned_experiment(args, torch, diam)}), flush=True)
+        return
+    if args.families_only:
+        print(json.dumps({"families": families_experiment(args, torch, diam)}), flush=True)
         return
 
     # -- synthetic workload (host), seeded as the d = 4096 configuration ------
@@ -518,6 +591,8 @@ def main():
         out["learned"] = learned_experiment(args, torch, diam)
     if not args.no_batch:
         out["batch"] = batch_experiment(args, torch, diam)
+    if not args.no_families:
+        out["families"] = families_experiment(args, torch, diam)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(tgt, args)

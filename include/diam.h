@@ -68,6 +68,27 @@ typedef enum { DIAM_FP64 = 0, DIAM_FP32 = 1, DIAM_MIXED = 2 } diam_precision;
 
 typedef enum { DIAM_TGT_GAUSS = 0, DIAM_TGT_LOGREG = 1 } diam_target_kind;
 
+/* Proposal family (Section 2.3).  W ~ N(0, I); A is the lower proposal factor
+ * and x_ref the pivot held by the context.
+ * DIAM_PROP_DIAM: eq. diamnl, x' = x_ref + rho (x - x_ref) + beta alpha A W with
+ *   rho = sqrt(1 - beta^2); log alpha adds |z'|^2/(2 alpha^2) - |z|^2/(2 alpha^2),
+ *   z = A^-1 (x - x_ref) (the reference Gaussian N(x_ref, alpha^2 A A^T) the
+ *   proposal leaves invariant).  Each diam_update_proposal refactorises A from
+ *   the merged covariance and moves x_ref to the merged mean.
+ * DIAM_PROP_AM: adaptive Metropolis (Section 2.3.3): the random walk of eq. rw,
+ *   x' = x + beta alpha A W, with A refactorised at every update as above.  The
+ *   proposal is symmetric: log alpha = log pi(x') - log pi(x).
+ * DIAM_PROP_PCN: preconditioned Crank-Nicolson (Section 2.3.2, eq. pcn): the
+ *   DIAM formula with A and x_ref fixed, i.e. reversible for the prior
+ *   N(x_ref, alpha^2 A A^T).  They start as A = I, x_ref = 0 (diam_init); a
+ *   diam_seed_moments call sets them once from the moments it is given (a
+ *   prior's covariance and mean).  diam_update_proposal adapts beta only.
+ * DIAM_PROP_RW: random walk (Section 2.3.1, eq. rw), x' = x + beta alpha A W
+ *   with A fixed as for pCN; symmetric acceptance as for AM.
+ * Under AM and RW the context still carries z (advanced as z + beta alpha W)
+ * so that fields keep their meaning; it does not enter log alpha. */
+typedef enum { DIAM_PROP_DIAM = 0, DIAM_PROP_AM = 1, DIAM_PROP_PCN = 2, DIAM_PROP_RW = 3 } diam_proposal;
+
 /* Sampler configuration (host struct, copied by diam_init). */
 typedef struct {
   int32_t d;            /* dimension of the state, >= 1 */
@@ -81,8 +102,11 @@ typedef struct {
   int32_t jitter_tries; /* number of retry levels j = 0 .. jitter_tries-1 */
   int32_t surrogate;    /* learned part (MLP d-256-256-1, delayed acceptance): 0 none; 1 the
                            surrogate is the network; 2 residual form, the surrogate is
-                           network(x) - |A^-1 (x - x_ref)|^2 / (2 alpha^2) */
+                           network(x) - |A^-1 (x - x_ref)|^2 / (2 alpha^2) (DIAM and pCN
+                           proposals only, else DIAM_E_ARG) */
   int64_t train_max;    /* most (x, log pi(x)) pairs diam_surrogate_train will be given */
+  int32_t proposal;     /* diam_proposal; 0 (DIAM) for a zero-initialised config */
+  int32_t reserved;     /* 0 */
 } diam_config;
 
 /* Target log density (Section 2.1: only the unnormalised density is needed).
@@ -197,12 +221,16 @@ int diam_merge_moments(diam_ctx* ctx);
  * then x_ref = m and z = A^-1 (x - x_ref) for every current state (FP64
  * triangular solve).  jitter_used (host, may be NULL): -1, the level j, or
  * jitter_tries when every try failed (then DIAM_E_NOT_PD, previous factor and
- * pivot kept).  Requires steps_in_window == 0.  Synchronises the stream. */
+ * pivot kept).  Requires steps_in_window == 0.  Synchronises the stream.
+ * Beta adaptation (diam_set_beta_adaptation) runs first.  Under the fixed
+ * proposals (DIAM_PROP_PCN, DIAM_PROP_RW) only beta is adapted: A, x_ref and z
+ * stay, and jitter_used gets -1. */
 int diam_update_proposal(diam_ctx* ctx, int32_t* jitter_used);
 
 /* Warm start: replace the global moments by (S0, m0) with pseudo-count N0
  * (device S0 d x d, m0 d), then diam_update_proposal.  Requires
- * steps_in_window == 0. */
+ * steps_in_window == 0.  Under the fixed proposals this is the one call that
+ * sets A = chol(S0 - m0 m0^T) and x_ref = m0 (with the jitter rule). */
 int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double N0, int32_t* jitter_used);
 
 /* Record per-step traces for effective-sample-size estimates: for each later
@@ -295,7 +323,8 @@ int diam_moment_error(diam_ctx* ctx, const double* Sigma, const double* mu, doub
  * FP32 on MFMA with FP64 states, moments, Cholesky and log-acceptance, the
  * same kernels as DIAM_FP32 of the single-problem calls: with the default
  * target tile shape and the same normals and uniforms, every problem's
- * states, moments and factor are bitwise those of a separate sampler. */
+ * states, moments and factor are bitwise those of a separate sampler.  Every
+ * problem uses the DIAM proposal (DIAM_PROP_DIAM). */
 typedef struct {
   int32_t G;            /* number of problems, 1 .. 4096 */
   int32_t P;            /* chains per problem */

@@ -239,8 +239,17 @@ static int check_cfg(const diam_config* c) {
   if ((long)c->d * c->d > (1L << 34)) return fail(DIAM_E_ARG, "d too large");
   if (c->surrogate < 0 || c->surrogate > 2) return fail(DIAM_E_ARG, "surrogate must be 0, 1 or 2");
   if (c->train_max < 0 || c->train_max > (1L << 31)) return fail(DIAM_E_ARG, "train_max out of range");
+  if (c->proposal < DIAM_PROP_DIAM || c->proposal > DIAM_PROP_RW) return fail(DIAM_E_ARG, "unknown proposal %d", c->proposal);
+  // the residual surrogate subtracts the reference Gaussian that only DIAM and pCN carry
+  if (c->surrogate == 2 && (c->proposal == DIAM_PROP_AM || c->proposal == DIAM_PROP_RW))
+    return fail(DIAM_E_ARG, "the residual surrogate needs the DIAM or pCN proposal");
   return DIAM_OK;
 }
+
+// random-walk family (eq. rw): no contraction toward the pivot, symmetric acceptance
+static bool walk_proposal(const diam_config& c) { return c.proposal == DIAM_PROP_AM || c.proposal == DIAM_PROP_RW; }
+// factor and pivot fixed after initialisation or a warm start
+static bool fixed_factor(const diam_config& c) { return c.proposal == DIAM_PROP_PCN || c.proposal == DIAM_PROP_RW; }
 
 static int check_target(const diam_config* c, const diam_target* t) {
   if (!t) return fail(DIAM_E_ARG, "null target");
@@ -590,9 +599,10 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.d = d;
   a.P = P;
   a.prec = prec;
-  a.rho = sqrt(1.0 - beta * beta);
+  const bool walk = walk_proposal(c->cfg);
+  a.rho = walk ? 1.0 : sqrt(1.0 - beta * beta);
   a.c = cc;
-  a.inv2a2 = 1.0 / (2.0 * alpha * alpha);
+  a.inv2a2 = walk ? 0.0 : 1.0 / (2.0 * alpha * alpha);
   a.xr = c->xr;
   a.mu = c->logreg ? nullptr : c->tgt.mu;
   a.X = c->X;
@@ -867,7 +877,7 @@ static int read_status(diam_ctx* c, Status* st) {
   return DIAM_OK;
 }
 
-extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
+static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
   if (!c) return fail(DIAM_E_ARG, "null context");
   if (c->siw != 0) return fail(DIAM_E_STATE, "update inside a window (steps_in_window = %d)", c->siw);
   const int d = c->cfg.d, P = c->cfg.P;
@@ -887,6 +897,18 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
   }
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->wacc, (long)P);
   c->win_steps = 0;
+  if (!refactor) {  // fixed factor: beta only; still report a target error of the past steps
+    if (jitter_used) *jitter_used = -1;
+    int r = read_status(c, &st);
+    if (r) return r;
+    r = prof_flush(c);
+    if (r) return r;
+    if (st.err) {
+      hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
+      return fail(DIAM_E_TARGET, "the target log density returned +inf");
+    }
+    return DIAM_OK;
+  }
   int ps = prof_begin(c, DIAM_ST_CHOL);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
   HIPCHK(dk::cov_assemble(c->S, c->m, 0.0, c->Lnew, &c->status->trace, d, s));
@@ -935,6 +957,11 @@ extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
   return DIAM_OK;
 }
 
+extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {
+  if (!c) return fail(DIAM_E_ARG, "null context");
+  return update_impl(c, jitter_used, !fixed_factor(c->cfg));
+}
+
 extern "C" int diam_seed_moments(diam_ctx* c, const double* S0, const double* m0, double N0, int32_t* jitter_used) {
   if (!c || !S0 || !m0) return fail(DIAM_E_ARG, "null argument");
   if (!(N0 >= 0.0)) return fail(DIAM_E_ARG, "N0 must be >= 0");
@@ -943,7 +970,7 @@ extern "C" int diam_seed_moments(diam_ctx* c, const double* S0, const double* m0
   HIPCHK(hipMemcpyAsync(c->S, S0, (size_t)d * d * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->m, m0, (size_t)d * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->N = N0;
-  return diam_update_proposal(c, jitter_used);
+  return update_impl(c, jitter_used, true);
 }
 
 extern "C" int diam_set_trace(diam_ctx* c, const double* proj, int32_t n_proj, double* trace, int64_t capacity) {

@@ -1,0 +1,194 @@
+"""The other proposal families of Section 2.3 on the GPU path: adaptive
+Metropolis, pCN and the random walk, through the same kernels.
+
+* FP64 against the oracle, decision for decision, over several windows with
+  the step-size adaptation on (the bands of Section 3.2: 0.1 - 0.3 for AM and
+  RW, 0.3 - 0.5 for pCN), at a size that fills whole tiles and at a ragged
+  one; pCN also with a prior factor set by a warm start.
+* Mixed precision: every family keeps pi_2's moments (d = 32) within 4 MC
+  standard errors.
+* The comparison of Section 3.2 (its Fig. 1): DIAM, AM, pCN and RW on
+  pi_1, pi_2, pi_4 (two data variances) and pi_5 at d = 100, effective sample
+  size per step of log pi, v_d^T x and v_1^T x.  As the paper reports, DIAM
+  has the largest minimum ESS on every target, and raising pi_4's condition
+  number from O(d) to O(d^2) leaves AM about unchanged while pCN loses on
+  every functional except the smallest-variance direction.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import diam as od
+from oracle import ess as oe
+from oracle import targets as ot
+from paper_1506_05741_amd import diam, synth
+
+BANDS = {"diam": (0.3, 0.5), "am": (0.1, 0.3), "pcn": (0.3, 0.5), "rw": (0.1, 0.3)}
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("prop,d,prior", [("am", 40, False), ("am", 130, False), ("pcn", 40, False),
+                                          ("pcn", 130, True), ("rw", 40, False), ("rw", 130, False)])
+def test_family_decision_parity(prop, d, prior):
+    P, n_lag, windows = 8, 10, 4
+    # AM adapts its factor from a warm start; pCN and RW keep A = I (or the
+    # prior's factor) and need a target of moderate condition to accept: pi_2
+    t = synth.gaussian_target(d, 3) if prop == "am" else synth.paper_gaussian("pi2", d, 3)
+    x0 = synth.gaussian_exact_draws(t, P, 4)
+    beta = od.initial_beta(d)
+    band = BANDS[prop]
+    cfg = diam.make_config(d, P, n_lag, "fp64", beta=beta, seed=5, proposal=prop)
+    s = diam.Sampler(cfg, dev(t.mu), dev(t.R), dev(x0.T))
+    s.set_beta_adaptation(True, band[0], band[1], 1.2, 1.0)
+    o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), d, P, n_lag, beta, X=x0, proposal=prop,
+                      adapt=(band[0], band[1], 1.2, 1.0))
+    if prop == "am" or prior:
+        # AM: warm start; pCN: a prior N(0, Sigma0) set once, kept by every update
+        S0, m0 = synth.gaussian_warm_moments(t) if prop == "am" else (4.0 * t.Sigma, np.zeros(d))
+        assert s.seed_moments(dev(S0), dev(m0), 10 * P * n_lag)[0] == diam.OK
+        assert o.seed_moments(S0, m0, 10 * P * n_lag) == od.OK
+        o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()    # the GPU's factor (independent FP64 roundings)
+        o.Z = od.whiten(o.A, o.x_ref, o.X)
+    L0 = host(s.get_f64(diam.F_L, (d, d)))
+    rng = np.random.default_rng(7)
+    total = 0
+    for w in range(windows):
+        W = rng.standard_normal((n_lag, P, d))
+        U = synth.draw_uniforms(P, n_lag, 60 + w)
+        s.step_batch(n_lag, dev(W), dev(U))
+        acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
+        la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
+        for k in range(n_lag):
+            acc_o, la_o = o.step(W[k].T, U[k])
+            if np.any(np.abs(la_o - np.log(U[k])) < 1e-9):
+                return                                       # near-tie: parity ends here
+            assert np.array_equal(acc_g[k], acc_o), (w, k)
+            assert np.max(np.abs(la_g[k] - la_o)) <= 1e-9, (w, k, np.max(np.abs(la_g[k] - la_o)))
+            total += int(acc_o.sum())
+        X = host(s.get_f64(diam.F_X, (P, d))).T
+        assert np.linalg.norm(X - o.X) <= 1e-12 * np.linalg.norm(o.X)
+        s.merge_moments()
+        o.merge_moments()
+        st, j = s.update_proposal()
+        assert st == diam.OK and o.update_proposal() == od.OK
+        assert s.stats()["beta"] == o.beta                   # same adaptation decisions
+        L = host(s.get_f64(diam.F_L, (d, d)))
+        if prop == "am":
+            o.A = L.T.copy()
+            o.Z = od.whiten(o.A, o.x_ref, o.X)
+        else:
+            assert j == -1 and np.array_equal(L, L0)         # fixed factor
+            assert np.array_equal(host(s.get_f64(diam.F_XREF, (d,))), o.x_ref)
+    print(f"\n[{prop} d={d}{' prior' if prior else ''}] {windows} windows decision-for-decision, "
+          f"{total} accepted of {windows * n_lag * P}, beta {o.beta:.4f}", flush=True)
+
+
+@pytest.mark.parametrize("prop", ["am", "pcn", "rw"])
+def test_family_mixed_precision_moments(prop):
+    # pi_2 (cond O(1)), on which the fixed factor A = I of pCN and RW mixes
+    d, P, n_lag, windows = 32, 64, 50, 80
+    t = synth.paper_gaussian("pi2", d, 9)
+    x0 = synth.gaussian_exact_draws(t, P, 10)
+    band = BANDS[prop]
+    cfg = diam.make_config(d, P, n_lag, "mixed", beta=od.initial_beta(d), seed=12, proposal=prop)
+    s = diam.Sampler(cfg, dev(t.mu), dev(t.R, torch.float32), dev(x0.T))
+    s.set_beta_adaptation(True, band[0], band[1], 1.2, 1.0)
+    if prop == "am":
+        S0, m0 = synth.gaussian_warm_moments(t)
+        assert s.seed_moments(dev(S0), dev(m0), 10 * P * n_lag)[0] == diam.OK
+    ends = []
+    for _ in range(windows):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+        ends.append(host(s.get_f64(diam.F_X, (P, d))).T)
+    Xs = np.stack(ends)
+    worst = 0.0
+    for v, lam in ((t.v_max, t.lam[0]), (t.v_min, t.lam[-1])):
+        f1 = np.einsum("i,wip->wp", v, Xs)
+        for f, truth in ((f1, v @ t.mu), ((f1 - v @ t.mu) ** 2, lam)):
+            ess = oe.ess_chains(f)
+            worst = max(worst, abs(f.mean() - truth) / (f.std() / math.sqrt(ess)))
+    print(f"\n[{prop} mixed d={d}] worst |z| {worst:.2f}, beta {s.stats()['beta']:.3f}", flush=True)
+    assert worst < 4.0
+
+
+def fig1_run(prop, tgt, d, P=32, n_lag=100, windows=120, prec="fp64", seed=0):
+    """One family on one target: per-step traces of log pi, v_d^T x and
+    v_1^T x over the second half of the run; returns ESS per step (total over
+    chains) for each functional and the final beta."""
+    twist = None
+    if tgt == "pi5":
+        tw = synth.twisted_target(d, 1, 0.3)
+        R, mu, twist = tw.R, tw.mu, tw.c
+        V = tw.V
+        x0 = synth.twisted_exact_draws(tw, P, 2)
+        mu_u, var_u = ot.twisted_u_moments(tw.sig2, tw.b)
+        m = V @ mu_u
+        S0, m0 = V @ np.diag(var_u) @ V.T + np.outer(m, m), m
+        v_d, v_1 = V[:, -1], V[:, 0]
+        alpha = 1.2
+    else:
+        name, s2 = (tgt, None) if tgt != "pi4s" else ("pi4", 1.0 / d ** 2)
+        t = synth.paper_gaussian(name, d, 1, s2)
+        R, mu = t.R, t.mu
+        x0 = synth.gaussian_exact_draws(t, P, 2)
+        S0, m0 = synth.gaussian_warm_moments(t)
+        v_d, v_1 = t.v_max, t.v_min
+        alpha = 1.0
+    band = BANDS[prop]
+    rdt = torch.float64 if prec == "fp64" else torch.float32
+    cfg = diam.make_config(d, P, n_lag, prec, beta=2.4 / math.sqrt(d), alpha=alpha, seed=31 + seed, proposal=prop)
+    s = diam.Sampler(cfg, dev(mu), dev(R, rdt), dev(x0.T), twist=None if twist is None else dev(twist))
+    s.set_beta_adaptation(True, band[0], band[1], 1.2, 1.0)
+    if prop in ("diam", "am"):
+        assert s.seed_moments(dev(S0), dev(m0), 10 * P * n_lag)[0] == diam.OK
+    proj = dev(np.stack([v_d, v_1]))
+    half = windows // 2
+    for _ in range(half):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+    trace = torch.zeros((half * n_lag, 3, P), dtype=torch.float64, device="cuda")
+    s.set_trace(proj, trace)
+    for _ in range(windows - half):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+    tr = host(trace)
+    n = tr.shape[0]
+    ess = [oe.ess_chains(tr[:, f, :]) / n for f in range(3)]
+    return ess, s.stats()["beta"]
+
+
+def test_fig1_comparison_on_the_paper_targets():
+    d = 100
+    table = {}
+    for tgt in ("pi1", "pi2", "pi4", "pi4s", "pi5"):
+        for prop in ("diam", "am", "pcn", "rw"):
+            table[tgt, prop] = fig1_run(prop, tgt, d)
+    print("\n[Section 3.2 comparison, d = 100, P = 32, ESS per step (log pi, v_d^T x, v_1^T x), final beta]")
+    for (tgt, prop), (ess, beta) in table.items():
+        print(f"  {tgt:5s} {prop:5s} " + " ".join(f"{e:8.4f}" for e in ess) + f"   min {min(ess):8.4f}  beta {beta:.3f}",
+              flush=True)
+    mins = {k: min(v[0]) for k, v in table.items()}
+    for tgt in ("pi1", "pi2", "pi4", "pi4s", "pi5"):
+        for prop in ("am", "pcn", "rw"):
+            assert mins[tgt, "diam"] > mins[tgt, prop], (tgt, prop)
+    # raising pi_4's condition number from O(d) to O(d^2): AM about unchanged,
+    # pCN much worse overall but not along the smallest-variance direction
+    assert 0.5 < mins["pi4s", "am"] / mins["pi4", "am"] < 2.0
+    assert mins["pi4s", "pcn"] < mins["pi4", "pcn"] / 3.0
+    assert mins["pi4s", "am"] > mins["pi4s", "pcn"]
+    assert table["pi4s", "pcn"][0][2] > 0.5 * table["pi4", "pcn"][0][2]
