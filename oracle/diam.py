@@ -110,6 +110,16 @@ def merge_global(S_glob, m_glob, N, locals_, n_lag):
     return S, m, tot
 
 
+def local_global_moments(S_glob, m_glob, N, S_p, m_p, n_p):
+    """Chain p's local update of the global moments (eqs. mom2pg / mom1pg):
+    with N global samples and the chain's n_p = m n_lag samples of the current
+    batch, S^{p,glob} = (N S^glob + n_p S^p) / (N + n_p) and likewise the
+    mean; the printed weights k M P n_lag / ((k M P + m) n_lag) and
+    m n_lag / ((k M P + m) n_lag) are the case N = k M P n_lag."""
+    tot = N + n_p
+    return (N / tot) * S_glob + (n_p / tot) * S_p, (N / tot) * m_glob + (n_p / tot) * m_p
+
+
 def sample_covariance(S, m):
     """C = S - m m^T (eq. sampcov)."""
     return S - np.outer(m, m)
@@ -183,11 +193,24 @@ class DiamOracle:
     win_acc: int = 0
     win_steps: int = 0
     proposal: str = "diam"
+    # concurrent-chain logistics of Section 2.4.1: M intervals of n_lag steps
+    # per batch; between global merges every chain refactorises from its own
+    # local update of the global moments (eqs. mom2pg, mom1pg, cov2pg)
+    M: int = 1
+    Ap: np.ndarray = None          # P x d x d per-chain factors (None: all chains use A)
+    xrp: np.ndarray = None         # d x P per-chain pivots
+    loc_S: np.ndarray = None       # P x d x d chain-local second moments of the batch (eq. mom2p)
+    loc_m: np.ndarray = None       # d x P chain-local means (eq. mom1p)
+    loc_n: float = 0.0             # samples per chain in the batch so far (m n_lag)
+    m_int: int = 0                 # intervals merged in the current batch
 
     def __post_init__(self):
         if self.proposal not in PROPOSALS:
             raise ValueError(f"unknown proposal {self.proposal!r}")
+        if self.M < 1 or (self.M > 1 and self.proposal != "diam"):
+            raise ValueError("M >= 1; M > 1 runs the DIAM proposal")
         d, P = self.d, self.P
+        self._reset_local()
         if self.X is None:
             self.X = np.zeros((d, P))
         self.X = np.array(self.X, dtype=np.float64, copy=True)
@@ -207,8 +230,18 @@ class DiamOracle:
         self.S_glob = np.array(S0, dtype=np.float64, copy=True)
         self.m_glob = np.array(m0, dtype=np.float64, copy=True)
         self.N = float(N0)
+        self._reset_local()
         self.adapt_beta()
         return self.refactor()
+
+    def _reset_local(self):
+        """Start a batch: clear the chain-local accumulators.  The per-chain
+        factors stay until a global refactorisation succeeds (it recomputes
+        every z under the shared pair)."""
+        self.loc_S = np.zeros((self.P, self.d, self.d))
+        self.loc_m = np.zeros((self.d, self.P))
+        self.loc_n = 0.0
+        self.m_int = 0
 
     @property
     def walk(self):
@@ -224,8 +257,16 @@ class DiamOracle:
             la = symmetric_log_accept_ratio(lpp, self.lp)
             Zp = self.Z
         else:
-            Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
-            Zp = whiten(self.A, self.x_ref, Xp)
+            if self.Ap is None:
+                Xp = diam_proposal(self.X, self.x_ref, self.A, W, self.beta, self.alpha)
+                Zp = whiten(self.A, self.x_ref, Xp)
+            else:                                   # every chain with its own factor and pivot
+                Xp = np.empty_like(self.X)
+                Zp = np.empty_like(self.Z)
+                for p in range(self.P):
+                    A, xr = self.Ap[p], self.xrp[:, p]
+                    Xp[:, p:p + 1] = diam_proposal(self.X[:, p:p + 1], xr, A, W[:, p:p + 1], self.beta, self.alpha)
+                    Zp[:, p:p + 1] = whiten(A, xr, Xp[:, p:p + 1])
             lpp = self.logpi(Xp)
             if np.any(np.isposinf(lpp)):
                 raise FloatingPointError("log density returned +inf")
@@ -250,6 +291,8 @@ class DiamOracle:
         which makes the composite kernel reversible for pi itself.  Under the
         random-walk families stage 1 is the symmetric ratio of s.  Returns
         (accepted, stage-1 survivors, updated s_cur)."""
+        if self.M > 1:
+            raise ValueError("delayed acceptance runs with M = 1")
         if self.walk:
             Xp = rw_proposal(self.X, self.A, W, self.beta, self.alpha)
             Zp = self.Z
@@ -286,9 +329,24 @@ class DiamOracle:
             raise RuntimeError("empty window")
         n = len(self.window)
         Xw = np.stack(self.window, axis=2)            # d x P x n
-        locals_ = [local_moments(Xw[:, p, :]) for p in range(self.P)]
-        self.S_glob, self.m_glob, self.N = merge_global(self.S_glob, self.m_glob, self.N, locals_, n)
         self.window = []
+        if self.M == 1:
+            locals_ = [local_moments(Xw[:, p, :]) for p in range(self.P)]
+            self.S_glob, self.m_glob, self.N = merge_global(self.S_glob, self.m_glob, self.N, locals_, n)
+            return
+        # M > 1: fold the interval into the running chain-local moments (eqs.
+        # mom2p / mom1p, sample-count weights); every M intervals merge them
+        for p in range(self.P):
+            S_w, m_w = local_moments(Xw[:, p, :])
+            tot = self.loc_n + n
+            self.loc_S[p] = (self.loc_n / tot) * self.loc_S[p] + (n / tot) * S_w
+            self.loc_m[:, p] = (self.loc_n / tot) * self.loc_m[:, p] + (n / tot) * m_w
+        self.loc_n += n
+        self.m_int += 1
+        if self.m_int == self.M:
+            locals_ = [(self.loc_S[p], self.loc_m[:, p]) for p in range(self.P)]
+            self.S_glob, self.m_glob, self.N = merge_global(self.S_glob, self.m_glob, self.N, locals_, self.loc_n)
+            self._reset_local()
 
     def adapt_beta(self):
         """Algorithm 1's update block: the acceptance ratio of the steps since
@@ -308,7 +366,32 @@ class DiamOracle:
         self.adapt_beta()
         if self.proposal in ("pcn", "rw"):
             return OK
+        if self.M > 1 and self.m_int > 0:
+            return self.refactor_local()
         return self.refactor()
+
+    def refactor_local(self):
+        """Between global merges: chain p's factor A_p = chol(C^{p,glob}) and
+        pivot m^{p,glob} (eqs. mom2pg, mom1pg, cov2pg), with the jitter rule
+        per chain; a chain whose every try fails keeps its factor and pivot.
+        Its z is recomputed under the new pair."""
+        if self.Ap is None:
+            self.Ap = np.repeat(self.A[None, :, :], self.P, axis=0)
+            self.xrp = np.repeat(self.x_ref[:, None], self.P, axis=1)
+        status, jmax = OK, -1
+        for p in range(self.P):
+            S_pg, m_pg = local_global_moments(self.S_glob, self.m_glob, self.N, self.loc_S[p], self.loc_m[:, p],
+                                              self.loc_n)
+            A, j = cholesky_jitter(sample_covariance(S_pg, m_pg), self.jitter0, self.jitter_tries)
+            jmax = max(jmax, j)
+            if A is None:
+                status = E_NOT_PD
+                continue
+            self.Ap[p] = A
+            self.xrp[:, p] = m_pg
+            self.Z[:, p:p + 1] = whiten(A, m_pg, self.X[:, p:p + 1])
+        self.last_jitter = jmax
+        return status
 
     def refactor(self):
         C = sample_covariance(self.S_glob, self.m_glob)
@@ -319,6 +402,8 @@ class DiamOracle:
         self.A = A
         self.x_ref = self.m_glob.copy()
         self.Z = whiten(self.A, self.x_ref, self.X)
+        self.Ap = None
+        self.xrp = None
         return OK
 
     def run_window(self, W, U):
