@@ -106,7 +106,12 @@ typedef struct {
                            proposals only, else DIAM_E_ARG) */
   int64_t train_max;    /* most (x, log pi(x)) pairs diam_surrogate_train will be given */
   int32_t proposal;     /* diam_proposal; 0 (DIAM) for a zero-initialised config */
-  int32_t reserved;     /* 0 */
+  int32_t M;            /* intervals of n_lag steps per batch (Section 2.4.1); 0 or 1: every
+                           merge is global and all chains share one factor.  M > 1: between
+                           global merges (every M-th diam_merge_moments) each chain
+                           proposes with its own factor and pivot from its local update of
+                           the global moments (eqs. mom2pg, mom1pg, cov2pg).  M > 1 needs
+                           DIAM_FP64, DIAM_PROP_DIAM, no surrogate and P <= 65535. */
 } diam_config;
 
 /* Target log density (Section 2.1: only the unnormalised density is needed).
@@ -168,7 +173,11 @@ typedef enum {
   DIAM_F_MLP_PARAMS = 17, /* nparam f32 master weights W1 (256 x d), b1, W2 (256 x 256), b2, W3 (256), b3 */
   DIAM_F_MLP_GRAD = 18,   /* nparam f32 gradient of the last training step */
   DIAM_F_MLP_BATCH = 19,  /* batch int32 training-pair indices of the last training step */
-  DIAM_F_MLP_STATS = 20   /* 2d + 2 f32: input mean, input 1/std, output mean, output std */
+  DIAM_F_MLP_STATS = 20,  /* 2d + 2 f32: input mean, input 1/std, output mean, output std */
+  DIAM_F_LP = 21,         /* P x d x d f64 per-chain factors (M > 1; chain p at p d^2,
+                             column-major, lower; meaningful while per-chain factors are
+                             in use, i.e. after a local update) */
+  DIAM_F_XREFP = 22       /* d x P f64 per-chain pivots (M > 1, as DIAM_F_LP) */
 } diam_field;
 
 typedef struct {
@@ -213,7 +222,11 @@ int diam_step_batch(diam_ctx* ctx, int32_t n_steps, const double* W, const doubl
  * repeats after rejection included) into the global moments, eqs. mom2p,
  * mom1p, mom2g, mom1g with sample-count weights:
  *   S <- (N S + sum x x^T) / (N + K),  m <- (N m + sum x) / (N + K),  N += K.
- * Requires steps_in_window >= 1 (else DIAM_E_STATE). */
+ * Requires steps_in_window >= 1 (else DIAM_E_STATE).
+ * M > 1: the window is folded into each chain's local sums instead (eqs.
+ * mom2p, mom1p); every M-th call merges the P chains' local sums of the
+ * batch into the global moments as above (eqs. mom2g, mom1g) and starts a
+ * new batch. */
 int diam_merge_moments(diam_ctx* ctx);
 
 /* Refactorise: C = S - m m^T (eq. sampcov); A = chol(C) in FP64, retrying on
@@ -224,13 +237,21 @@ int diam_merge_moments(diam_ctx* ctx);
  * pivot kept).  Requires steps_in_window == 0.  Synchronises the stream.
  * Beta adaptation (diam_set_beta_adaptation) runs first.  Under the fixed
  * proposals (DIAM_PROP_PCN, DIAM_PROP_RW) only beta is adapted: A, x_ref and z
- * stay, and jitter_used gets -1. */
+ * stay, and jitter_used gets -1.
+ * M > 1, inside a batch (after a merge that was not global): every chain p
+ * gets C_p = S^{p,glob} - m^{p,glob} m^{p,glob}^T from its local update of
+ * the global moments, A_p = chol(C_p) with the jitter rule, x_ref_p =
+ * m^{p,glob} and z_p = A_p^-1 (x_p - x_ref_p); a chain failing every level
+ * keeps its pair (DIAM_E_NOT_PD is returned, the others are updated);
+ * jitter_used gets the largest level used.  After a global merge the update
+ * above runs and, on success, all chains share the new factor again. */
 int diam_update_proposal(diam_ctx* ctx, int32_t* jitter_used);
 
 /* Warm start: replace the global moments by (S0, m0) with pseudo-count N0
  * (device S0 d x d, m0 d), then diam_update_proposal.  Requires
  * steps_in_window == 0.  Under the fixed proposals this is the one call that
- * sets A = chol(S0 - m0 m0^T) and x_ref = m0 (with the jitter rule). */
+ * sets A = chol(S0 - m0 m0^T) and x_ref = m0 (with the jitter rule).  With
+ * M > 1 it also starts a new batch (chain-local sums cleared). */
 int diam_seed_moments(diam_ctx* ctx, const double* S0, const double* m0, double N0, int32_t* jitter_used);
 
 /* Record per-step traces for effective-sample-size estimates: for each later

@@ -54,6 +54,8 @@ struct Layout {
   size_t R3, V3, Yp;
   // PSRF accumulators
   size_t pmean, pm2, pout, merr;
+  // per-chain factors and local sums (M > 1)
+  size_t Lp, Gp, hp, xrp, Spg, mpg;
   size_t total;
 };
 
@@ -122,6 +124,13 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.pm2 = take(dP * 8);
   L.pout = take(d * 8);
   L.merr = take(dk::moment_err_scratch_bytes());
+  const bool lg = c.M > 1;
+  L.Lp = take(lg ? P * dd * 8 : 0);
+  L.Gp = take(lg ? P * dd * 8 : 0);
+  L.hp = take(lg ? dP * 8 : 0);
+  L.xrp = take(lg ? dP * 8 : 0);
+  L.Spg = take(lg ? dd * 8 : 0);
+  L.mpg = take(lg ? d * 8 : 0);
   if (c.surrogate) {
     const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
     const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
@@ -181,6 +190,11 @@ struct diam_ctx {
   double prior_w;
   // PSRF
   double *pmean, *pm2, *pout, *merr;
+  // local-global logistics (M > 1): per-chain pairs, chain-local sums of the batch
+  double *Lp, *Gp, *hp, *xrp, *Spg, *mpg;
+  int m_int;      // intervals merged in the current batch
+  double loc_n;   // samples per chain in the current batch
+  int pc_on;      // chains propose with their own pairs
   int psrf_on;
   double psrf_n;  // states per chain folded since enabling
   // learned-part form
@@ -240,6 +254,9 @@ static int check_cfg(const diam_config* c) {
   if (c->surrogate < 0 || c->surrogate > 2) return fail(DIAM_E_ARG, "surrogate must be 0, 1 or 2");
   if (c->train_max < 0 || c->train_max > (1L << 31)) return fail(DIAM_E_ARG, "train_max out of range");
   if (c->proposal < DIAM_PROP_DIAM || c->proposal > DIAM_PROP_RW) return fail(DIAM_E_ARG, "unknown proposal %d", c->proposal);
+  if (c->M < 0) return fail(DIAM_E_ARG, "M must be >= 0");
+  if (c->M > 1 && (c->precision != DIAM_FP64 || c->proposal != DIAM_PROP_DIAM || c->surrogate || c->P > 65535))
+    return fail(DIAM_E_ARG, "M > 1 needs DIAM_FP64, the DIAM proposal, no surrogate and P <= 65535");
   // the residual surrogate subtracts the reference Gaussian that only DIAM and pCN carry
   if (c->surrogate == 2 && (c->proposal == DIAM_PROP_AM || c->proposal == DIAM_PROP_RW))
     return fail(DIAM_E_ARG, "the residual surrogate needs the DIAM or pCN proposal");
@@ -291,6 +308,7 @@ __global__ void k_fill_i32(int32_t* p, long n) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e < n) p[e] = 0;
 }
+
 // Clears the Cholesky words; the target error word only when clear_err.
 __global__ void k_clear_status(Status* s, int clear_err) {
   if (threadIdx.x == 0) {
@@ -301,6 +319,15 @@ __global__ void k_clear_status(Status* s, int clear_err) {
 }
 
 static unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+
+// start a batch of the local-global logistics: chain-local sums cleared
+static void reset_local(diam_ctx* c) {
+  const long dd = (long)c->cfg.d * c->cfg.d, dP = (long)c->cfg.d * c->cfg.P;
+  hipLaunchKernelGGL(k_fill, dim3(nblk(dd * c->cfg.P)), dim3(256), 0, c->stream, c->Gp, dd * c->cfg.P, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(dP)), dim3(256), 0, c->stream, c->hp, dP, 0.0);
+  c->m_int = 0;
+  c->loc_n = 0.0;
+}
 
 static int prof_flush(diam_ctx* c) {
   if (c->ev_used == 0) return DIAM_OK;
@@ -474,6 +501,15 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->merr = dptr(c, lay.merr);
   c->psrf_on = 0;
   c->psrf_n = 0.0;
+  c->Lp = dptr(c, lay.Lp);
+  c->Gp = dptr(c, lay.Gp);
+  c->hp = dptr(c, lay.hp);
+  c->xrp = dptr(c, lay.xrp);
+  c->Spg = dptr(c, lay.Spg);
+  c->mpg = dptr(c, lay.mpg);
+  c->m_int = 0;
+  c->loc_n = 0.0;
+  c->pc_on = 0;
   c->wint = c->ws + lay.wint;
   c->xr = dptr(c, lay.xr);
   c->S = dptr(c, lay.S);
@@ -526,6 +562,7 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   hipLaunchKernelGGL(k_fill, dim3(nblk(d)), dim3(256), 0, s, c->xr, (long)d, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nblk(d)), dim3(256), 0, s, c->m, (long)d, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nblk(dd)), dim3(256), 0, s, c->S, dd, 0.0);
+  if (cfg->M > 1) reset_local(c);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->nacc, (long)P);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->wacc, (long)P);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
@@ -588,7 +625,11 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   const void* Lmat = (prec == dk::P64) ? (const void*)c->L : (const void*)c->Llow;
   // search directions of the whole batch (Algorithm 1: beta alpha A [W ... W])
   ps = prof_begin(c, DIAM_ST_PROPOSAL);
-  HIPCHK(dk::trigemm(prec, Lmat, Wp, Wlop, c->Xi, d, (long)n * P, cc, s));
+  if (c->pc_on)  // every chain about its own pair (M > 1, FP64)
+    HIPCHK(dk::pc_gemm(c->Lp, (const double*)Wp, c->xrp, c->xr, (double*)c->Xi, d, P, n, cc,
+                       1.0 - sqrt(1.0 - beta * beta), s));
+  else
+    HIPCHK(dk::trigemm(prec, Lmat, Wp, Wlop, c->Xi, d, (long)n * P, cc, s));
   prof_end(c, ps);
 
   auto at = [](const void* base, long elem, int bytes) { return (const void*)((const char*)base + elem * bytes); };
@@ -797,8 +838,23 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
     Xs = c->wint;
   }
   double* G = c->Lnew;  // scratch until the next factorisation
-  HIPCHK(dk::syrk_window(c->prec, Xs, d, K, G, c->h, c->syrk, s));
-  HIPCHK(dk::fold_moments(G, c->h, c->xr, c->N, K, c->S, c->m, d, s));
+  bool global = true;
+  long Kg = K;
+  if (c->cfg.M > 1) {
+    // chain-local sums of the batch (eqs. mom2p, mom1p); every M-th interval
+    // the P chains' sums are merged into the global moments (eqs. mom2g, mom1g)
+    HIPCHK(dk::pc_scatter((const double*)c->win, c->Gp, c->hp, d, P, c->siw, s));
+    c->loc_n += (double)c->siw;
+    c->m_int += 1;
+    global = c->m_int == c->cfg.M;
+    if (global) {
+      HIPCHK(dk::pc_sum(c->Gp, c->hp, G, c->h, d, P, s));
+      Kg = (long)llround(c->loc_n) * P;
+    }
+  } else {
+    HIPCHK(dk::syrk_window(c->prec, Xs, d, K, G, c->h, c->syrk, s));
+  }
+  if (global) HIPCHK(dk::fold_moments(G, c->h, c->xr, c->N, Kg, c->S, c->m, d, s));
   prof_end(c, ps);
   if (c->psrf_on) {
     // the store still holds the window's states and xr its pivot
@@ -807,7 +863,10 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
     prof_end(c, pp);
     c->psrf_n += (double)c->siw;
   }
-  c->N += (double)K;
+  if (global) {
+    c->N += (double)Kg;
+    if (c->cfg.M > 1) reset_local(c);
+  }
   c->siw = 0;
   c->windows += 1;
   return DIAM_OK;
@@ -877,6 +936,93 @@ static int read_status(diam_ctx* c, Status* st) {
   return DIAM_OK;
 }
 
+// C = S - m m^T (eq. sampcov) assembled into Lnew and factored in place,
+// retrying on C + eps_j I, eps_j = 10^j jitter0 tr(C)/d (1 if not > 0), when a
+// pivot is not positive.  *j: -1, the level used, or jitter_tries when every
+// try failed.  Also reports a target error flagged by the steps before.
+static int factor_jitter(diam_ctx* c, const double* S, const double* m, int* j) {
+  const int d = c->cfg.d;
+  hipStream_t s = c->stream;
+  Status st;
+  int ps = prof_begin(c, DIAM_ST_CHOL);
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
+  HIPCHK(dk::cov_assemble(S, m, 0.0, c->Lnew, &c->status->trace, d, s));
+  HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
+  prof_end(c, ps);
+  int r = read_status(c, &st);
+  if (r) return r;
+  r = prof_flush(c);
+  if (r) return r;
+  if (st.err) {
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
+    return fail(DIAM_E_TARGET, "the target log density returned +inf");
+  }
+  *j = -1;
+  if (st.info != 0) {
+    const double tr = st.trace / d;
+    const double sc = (tr > 0.0 && isfinite(tr)) ? tr : 1.0;
+    *j = c->cfg.jitter_tries;
+    for (int q = 0; q < c->cfg.jitter_tries; ++q) {
+      const double eps = pow(10.0, q) * c->cfg.jitter0 * sc;
+      ps = prof_begin(c, DIAM_ST_CHOL);
+      hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
+      HIPCHK(dk::cov_assemble(S, m, eps, c->Lnew, nullptr, d, s));
+      HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
+      prof_end(c, ps);
+      r = read_status(c, &st);
+      if (r) return r;
+      if (st.info == 0) {
+        *j = q;
+        break;
+      }
+    }
+  }
+  return DIAM_OK;
+}
+
+// M > 1 inside a batch: every chain's factor and pivot from its local update
+// of the global moments (eqs. mom2pg, mom1pg, cov2pg), chain by chain with the
+// jitter rule; z of the chain recomputed under its new pair.
+static int update_local(diam_ctx* c, int32_t* jitter_used) {
+  const int d = c->cfg.d, P = c->cfg.P;
+  const long dd = (long)d * d;
+  hipStream_t s = c->stream;
+  if (!c->pc_on) {  // first local update of the batch: every chain starts from the shared pair
+    for (int p = 0; p < P; ++p) {
+      HIPCHK(hipMemcpyAsync(c->Lp + p * dd, c->L, dd * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(c->xrp + (long)p * d, c->xr, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    c->pc_on = 1;
+  }
+  int jmax = -1, failed = 0;
+  for (int p = 0; p < P; ++p) {
+    HIPCHK(dk::pc_moments(c->S, c->m, c->N, c->Gp + p * dd, c->hp + (long)p * d, c->xr, c->loc_n, c->Spg, c->mpg,
+                          d, s));
+    int j = -1;
+    const int r = factor_jitter(c, c->Spg, c->mpg, &j);
+    if (r) return r;
+    jmax = std::max(jmax, j);
+    if (j == c->cfg.jitter_tries) {
+      failed += 1;
+      continue;
+    }
+    double* Lq = c->Lp + p * dd;
+    double* xq = c->xrp + (long)p * d;
+    const int ps = prof_begin(c, DIAM_ST_WHITEN);
+    HIPCHK(hipMemcpyAsync(Lq, c->Lnew, dd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(xq, c->mpg, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(dk::trsm_whiten(Lq, c->X + (long)p * d, xq, c->Z + (long)p * d, c->zq + (long)c->cur * P + p, c->linv, d,
+                           1, s));
+    prof_end(c, ps);
+  }
+  c->last_jitter = jmax;
+  if (jitter_used) *jitter_used = jmax;
+  if (failed)
+    return fail(DIAM_E_NOT_PD, "%d chain covariances not positive definite at any of %d jitter levels", failed,
+                c->cfg.jitter_tries);
+  return DIAM_OK;
+}
+
 static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
   if (!c) return fail(DIAM_E_ARG, "null context");
   if (c->siw != 0) return fail(DIAM_E_STATE, "update inside a window (steps_in_window = %d)", c->siw);
@@ -909,39 +1055,10 @@ static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
     }
     return DIAM_OK;
   }
-  int ps = prof_begin(c, DIAM_ST_CHOL);
-  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
-  HIPCHK(dk::cov_assemble(c->S, c->m, 0.0, c->Lnew, &c->status->trace, d, s));
-  HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
-  prof_end(c, ps);
-  int r = read_status(c, &st);
-  if (r) return r;
-  r = prof_flush(c);
-  if (r) return r;
-  if (st.err) {
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
-    return fail(DIAM_E_TARGET, "the target log density returned +inf");
-  }
+  if (c->cfg.M > 1 && c->m_int > 0) return update_local(c, jitter_used);
   int j = -1;
-  if (st.info != 0) {
-    const double tr = st.trace / d;
-    const double sc = (tr > 0.0 && isfinite(tr)) ? tr : 1.0;
-    j = c->cfg.jitter_tries;
-    for (int q = 0; q < c->cfg.jitter_tries; ++q) {
-      const double eps = pow(10.0, q) * c->cfg.jitter0 * sc;
-      ps = prof_begin(c, DIAM_ST_CHOL);
-      hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 0);
-      HIPCHK(dk::cov_assemble(c->S, c->m, eps, c->Lnew, nullptr, d, s));
-      HIPCHK(dk::potrf(c->Lnew, d, &c->status->info, c->linv, s));
-      prof_end(c, ps);
-      r = read_status(c, &st);
-      if (r) return r;
-      if (st.info == 0) {
-        j = q;
-        break;
-      }
-    }
-  }
+  int r = factor_jitter(c, c->S, c->m, &j);
+  if (r) return r;
   c->last_jitter = j;
   if (jitter_used) *jitter_used = j;
   if (j == c->cfg.jitter_tries)
@@ -949,7 +1066,8 @@ static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
   double* t = c->L;
   c->L = c->Lnew;
   c->Lnew = t;
-  ps = prof_begin(c, DIAM_ST_WHITEN);
+  c->pc_on = 0;  // every chain shares the new pair again
+  const int ps = prof_begin(c, DIAM_ST_WHITEN);
   HIPCHK(dk::round_factor(c->prec, c->L, c->Llow, d, s));
   HIPCHK(hipMemcpyAsync(c->xr, c->m, d * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(dk::trsm_whiten(c->L, c->X, c->xr, c->Z, c->zq + (long)c->cur * P, c->linv, d, P, s));
@@ -970,6 +1088,7 @@ extern "C" int diam_seed_moments(diam_ctx* c, const double* S0, const double* m0
   HIPCHK(hipMemcpyAsync(c->S, S0, (size_t)d * d * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->m, m0, (size_t)d * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->N = N0;
+  if (c->cfg.M > 1) reset_local(c);
   return update_impl(c, jitter_used, true);
 }
 
@@ -1007,6 +1126,12 @@ static int field_info(diam_ctx* c, int32_t f, const void** src, size_t* bytes) {
       if (c->prec != dk::PMIX) return fail(DIAM_E_ARG, "DIAM_F_WLO exists only in DIAM_MIXED");
       *src = c->Wlo; *bytes = d * P * n * 2; break;
     case DIAM_F_U: *src = c->U; *bytes = n * P * 8 * c->last_call_stages; break;
+    case DIAM_F_LP:
+    case DIAM_F_XREFP:
+      if (c->cfg.M <= 1) return fail(DIAM_E_ARG, "field %d exists only with M > 1", f);
+      if (f == DIAM_F_LP) { *src = c->Lp; *bytes = P * d * d * 8; }
+      else { *src = c->xrp; *bytes = d * P * 8; }
+      break;
     case DIAM_F_SURR:
     case DIAM_F_NPASS:
     case DIAM_F_MLP_PARAMS:

@@ -220,4 +220,18 @@ hipError_t g_colnorm(const BProb* pr, const BTile* tl, int n, hipStream_t s);
 hipError_t g_rng(uint64_t seed, const long* win, long nW, long nU, int P, float* W, double* U, hipStream_t s);
 hipError_t g_bump(long* win, double* N, double K, hipStream_t s);
 
+// ---- concurrent-chain logistics with M > 1 (local.hip), FP64 ------------------
+// Xi[:, tP+p] = c L_p W[:, tP+p] + one_minus_rho (xrp[:, p] - xr), n steps
+// (step-major columns); Lp: P lower d x d column-major factors.  P <= 65535.
+hipError_t pc_gemm(const double* Lp, const double* W, const double* xrp, const double* xr, double* Xi, int d, int P,
+                   int n, double c, double one_minus_rho, hipStream_t s);
+// Gp[p] += sum_t y y^T, hp[:, p] += sum_t y over n stored steps (y = win column tP+p).
+hipError_t pc_scatter(const double* win, double* Gp, double* hp, int d, int P, int n, hipStream_t s);
+// Chain-local update of the global moments (S, m, N) with the chain's sums
+// (G, h) of n samples shifted by sft: Spg, mpg.
+hipError_t pc_moments(const double* S, const double* m, double N, const double* G, const double* h,
+                      const double* sft, double n, double* Spg, double* mpg, int d, hipStream_t s);
+// G = sum_p Gp[p], h = sum_p hp[:, p].
+hipError_t pc_sum(const double* Gp, const double* hp, double* G, double* h, int d, int P, hipStream_t s);
+
 }  // namespace dk

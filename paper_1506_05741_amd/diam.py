@@ -19,7 +19,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
 OK, E_ARG, E_STATE, E_HIP, E_NOT_PD, E_TARGET = 0, -1, -2, -3, -4, -5
 
 (F_X, F_Z, F_LOGP, F_ZQ, F_XREF, F_L, F_S, F_M, F_XI, F_LA, F_ACC, F_NACC, F_W, F_WLO, F_U,
- F_SURR, F_NPASS, F_MLP_PARAMS, F_MLP_GRAD, F_MLP_BATCH, F_MLP_STATS) = range(21)
+ F_SURR, F_NPASS, F_MLP_PARAMS, F_MLP_GRAD, F_MLP_BATCH, F_MLP_STATS, F_LP, F_XREFP) = range(23)
 
 TGT_GAUSS, TGT_LOGREG = 0, 1
 PROPOSALS = {"diam": 0, "am": 1, "pcn": 2, "rw": 3}
@@ -44,7 +44,7 @@ class Config(ctypes.Structure):
         ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("n_lag", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("jitter0", ctypes.c_double), ("jitter_tries", ctypes.c_int32), ("surrogate", ctypes.c_int32),
-        ("train_max", ctypes.c_int64), ("proposal", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("train_max", ctypes.c_int64), ("proposal", ctypes.c_int32), ("M", ctypes.c_int32),
     ]
 
 
@@ -142,13 +142,15 @@ def _ptr(t):
 
 
 def make_config(d, P, n_lag, precision="fp64", beta=0.3, alpha=1.0, seed=0, jitter0=1e-12, jitter_tries=13,
-                surrogate=0, train_max=0, proposal="diam"):
+                surrogate=0, train_max=0, proposal="diam", M=1):
     """surrogate: 0 none, 1 (or True) network surrogate, 2 residual form.
-    proposal: "diam", "am", "pcn" or "rw" (the C header's diam_proposal)."""
+    proposal: "diam", "am", "pcn" or "rw" (the C header's diam_proposal).
+    M: intervals of n_lag steps per batch (Section 2.4.1; > 1 gives every
+    chain its own factor between global merges)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prop = PROPOSALS[proposal] if isinstance(proposal, str) else int(proposal)
     return Config(d, P, n_lag, prec, beta, alpha, seed, jitter0, jitter_tries, int(surrogate), int(train_max),
-                  prop, 0)
+                  prop, int(M))
 
 
 def gauss_target(mu, R, twist=None):

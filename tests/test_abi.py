@@ -50,6 +50,15 @@ def test_workspace_bytes_scales_with_precision():
     assert diam.workspace_bytes(diam.make_config(1, 1, 1), GAUSS) > 0
 
 
+def test_workspace_bytes_of_the_local_global_form():
+    # M > 1 adds the per-chain factors and local sums, 2 P d^2 + 2 d P + d^2 + d
+    # doubles, in six regions that hold a 256-byte placeholder otherwise
+    d, P = 64, 4
+    base = diam.workspace_bytes(diam.make_config(d, P, 4, "fp64"), GAUSS)
+    lg = diam.workspace_bytes(diam.make_config(d, P, 4, "fp64", M=3), GAUSS)
+    assert lg - base == (2 * P * d * d + 2 * d * P + d * d + d) * 8 - 6 * 256
+
+
 def test_workspace_bytes_of_the_learned_form():
     cfg = diam.make_config(512, 256, 64, "fp32")
     base = diam.workspace_bytes(cfg, logreg(200000))
@@ -84,6 +93,12 @@ def test_bad_target_is_rejected(tgt, msg):
     (dict(precision=7), "precision"),
     (dict(jitter0=-1.0), "jitter0"),
     (dict(train_max=-5), "train_max"),
+    (dict(proposal=9), "unknown proposal"),
+    (dict(proposal="rw", surrogate=2, train_max=10), "residual surrogate"),
+    (dict(M=-1), "M must be"),
+    (dict(M=3, precision="fp32"), "M > 1 needs"),
+    (dict(M=3, proposal="am"), "M > 1 needs"),
+    (dict(M=3, surrogate=1, train_max=10), "M > 1 needs"),
 ])
 def test_bad_config_is_rejected(kw, msg):
     base = dict(d=8, P=2, n_lag=4, precision="fp64", beta=0.3, alpha=1.0)

@@ -1,0 +1,118 @@
+"""Local-global logistics with M > 1 intervals per batch (Section 2.4.1) on
+the GPU path, FP64, against the oracle.
+
+* Decision for decision and log alpha over two batches and the start of a
+  third (M = 3), at a size that fills whole tiles and at a ragged one: after
+  every interval the per-chain factors and pivots (eqs. mom2pg, mom1pg,
+  cov2pg) and, after every M-th, the global moments (eqs. mom2g, mom1g)
+  match the oracle's.
+* The sampler with M = 4 keeps a Gaussian's moments within 4 MC standard
+  errors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import diam as od
+from oracle import ess as oe
+from oracle import targets as ot
+from paper_1506_05741_amd import diam, synth
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("d,P", [(64, 6), (130, 5)])
+def test_local_global_decision_parity(d, P):
+    n_lag, M, intervals = 10, 3, 7
+    t = synth.gaussian_target(d, 7)
+    x0 = synth.gaussian_exact_draws(t, P, 8)
+    beta = 0.4
+    s = diam.Sampler(diam.make_config(d, P, n_lag, "fp64", beta=beta, seed=3, M=M), dev(t.mu), dev(t.R), dev(x0.T))
+    o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), d, P, n_lag, beta, X=x0, M=M)
+    S0, m0 = synth.gaussian_warm_moments(t)
+    N0 = 2 * P * n_lag                                       # small: the chains' local moments matter
+    assert s.seed_moments(dev(S0), dev(m0), N0)[0] == diam.OK
+    assert o.seed_moments(S0, m0, N0) == od.OK
+    o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()        # the GPU's factor (independent FP64 roundings)
+    o.Z = od.whiten(o.A, o.x_ref, o.X)
+    rng = np.random.default_rng(9)
+    total = 0
+    for k in range(intervals):
+        W = rng.standard_normal((n_lag, P, d))
+        U = synth.draw_uniforms(P, n_lag, 70 + k)
+        s.step_batch(n_lag, dev(W), dev(U))
+        acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
+        la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
+        for q in range(n_lag):
+            acc_o, la_o = o.step(W[q].T, U[q])
+            if np.any(np.abs(la_o - np.log(U[q])) < 1e-9):
+                print(f"\n[M={M} d={d}] near-tie at interval {k} step {q}: parity ends there", flush=True)
+                return
+            assert np.array_equal(acc_g[q], acc_o), (k, q)
+            assert np.max(np.abs(la_g[q] - la_o)) <= 1e-9, (k, q, np.max(np.abs(la_g[q] - la_o)))
+            total += int(acc_o.sum())
+        X = host(s.get_f64(diam.F_X, (P, d))).T
+        assert rel(X, o.X) <= 1e-12, k
+        s.merge_moments()
+        o.merge_moments()
+        if o.m_int == 0:                                     # a global merge
+            S = host(s.get_f64(diam.F_S, (d, d))).T
+            m = host(s.get_f64(diam.F_M, (d,)))
+            assert rel(S, o.S_glob) <= 1e-12 and rel(m, o.m_glob) <= 1e-12, k
+        assert s.update_proposal()[0] == diam.OK
+        assert o.update_proposal() == od.OK
+        if o.Ap is not None:                                 # per-chain pairs
+            Lp = host(s.get_f64(diam.F_LP, (P, d, d))).transpose(0, 2, 1)
+            xrp = host(s.get_f64(diam.F_XREFP, (P, d))).T
+            for p in range(P):
+                assert rel(Lp[p], o.Ap[p]) <= 1e-9, (k, p, rel(Lp[p], o.Ap[p]))
+            assert rel(xrp, o.xrp) <= 1e-12, k
+            o.Ap = Lp.copy()
+            for p in range(P):
+                o.Z[:, p:p + 1] = od.whiten(o.Ap[p], o.xrp[:, p], o.X[:, p:p + 1])
+        else:
+            L = host(s.get_f64(diam.F_L, (d, d))).T
+            assert rel(L, o.A) <= 1e-9, k
+            o.A = L.copy()
+            o.Z = od.whiten(o.A, o.x_ref, o.X)
+    print(f"\n[M={M} d={d} P={P}] {intervals} intervals decision-for-decision, {total} accepted of "
+          f"{intervals * n_lag * P}", flush=True)
+
+
+def test_local_global_moments_within_4se():
+    d, P, n_lag, M, windows = 32, 16, 50, 4, 80
+    t = synth.gaussian_target(d, 21)
+    x0 = synth.gaussian_exact_draws(t, P, 22)
+    s = diam.Sampler(diam.make_config(d, P, n_lag, "fp64", beta=0.4, seed=23, M=M), dev(t.mu), dev(t.R), dev(x0.T))
+    S0, m0 = synth.gaussian_warm_moments(t)
+    assert s.seed_moments(dev(S0), dev(m0), P * n_lag)[0] == diam.OK
+    ends = []
+    for _ in range(windows):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+        ends.append(host(s.get_f64(diam.F_X, (P, d))).T)
+    Xs = np.stack(ends)
+    worst = 0.0
+    for v, lam in ((t.v_max, t.lam[0]), (t.v_min, t.lam[-1])):
+        f1 = np.einsum("i,wip->wp", v, Xs)
+        for f, truth in ((f1, v @ t.mu), ((f1 - v @ t.mu) ** 2, lam)):
+            ess = oe.ess_chains(f)
+            worst = max(worst, abs(f.mean() - truth) / (f.std() / math.sqrt(ess)))
+    acc = host(s.get(diam.F_NACC).view(torch.int32)).sum() / (P * n_lag * windows)
+    print(f"\n[M={M} d={d}] worst |z| {worst:.2f}, acceptance {acc:.3f}", flush=True)
+    assert worst < 4.0
