@@ -397,6 +397,62 @@ def families_experiment(args, torch, diam):
     return out
 
 
+def local_global_experiment(args, torch, diam):
+    """Section 2.4.1's logistics with M intervals per batch: M = 1 (every
+    merge global, one shared factor) against M = 4 (each chain refactorised
+    from its local update of the global moments between global merges), FP64,
+    Gaussian target d = 1024 (seed 1, lambda_i = i^-2), P = 64, n_lag = 200,
+    warm start with N0 = 10 P n_lag.  Timed: whole batches (one window = one
+    interval); the stage split comes from HIP events on one further batch."""
+    from paper_1506_05741_amd import synth
+    d, P, nl = 1024, 64, 200
+    dev = torch.device("cuda:0")
+    t = synth.gaussian_target(d, 1)
+    x0 = torch.as_tensor(np.ascontiguousarray(synth.gaussian_exact_draws(t, P, 2).T), device=dev)
+    S0, m0 = synth.gaussian_warm_moments(t)
+    mu, R = torch.as_tensor(t.mu, device=dev), torch.as_tensor(t.R, device=dev)
+    proj = torch.as_tensor(np.stack([t.v_max, t.v_min]), device=dev).contiguous()
+    out = {"workload": f"Gaussian d={d} (seed 1), P={P}, n_lag={nl}, fp64, beta=0.3, warm start N0=10 P n_lag; "
+                       "window = one interval of n_lag steps", "M": {}}
+    for M in (1, 4):
+        smp = diam.Sampler(diam.make_config(d, P, nl, "fp64", beta=0.3, seed=41, M=M), mu, R, x0)
+        assert smp.seed_moments(torch.as_tensor(S0, device=dev), torch.as_tensor(m0, device=dev),
+                                10.0 * P * nl)[0] == diam.OK
+
+        def window():
+            smp.step_batch(nl)
+            smp.merge_moments()
+            assert smp.update_proposal()[0] == diam.OK
+
+        for _ in range(4):
+            window()
+        nwin = args.lg_windows
+        trace = torch.empty((nwin * nl, 3, P), dtype=torch.float64, device=dev)
+        smp.set_trace(proj, trace)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(nwin):
+            window()
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t1
+        smp.set_trace(None, None)
+        smp.profile(True)
+        smp.profile_read(reset=True)
+        for _ in range(4):
+            window()
+        prof = smp.profile_read(reset=True)
+        smp.profile(False)
+        tr = trace.cpu().numpy()
+        ess = [ess_per_chain(tr[:, f, :]) for f in range(3)]
+        out["M"][str(M)] = {"windows": nwin, "ms_per_window": 1e3 * T / nwin,
+                            "chain_steps_per_s": P * nl * nwin / T, "ess_per_s": min(ess) / T,
+                            "stage_ms_per_window": {k: v[0] / 4 for k, v in prof.items() if v[1]}}
+        smp.close()
+        log(f"local-global M={M}: {out['M'][str(M)]['ms_per_window']:.2f} ms/window, "
+            f"{out['M'][str(M)]['ess_per_s']:.4g} ESS/s")
+    return out
+
+
 def cpu_baseline(tgt, args):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: a few steps of all P chains, one merge of those steps and one
@@ -466,6 +522,9 @@ def main():
     ap.add_argument("--no-families", action="store_true", help="skip the proposal-family comparison")
     ap.add_argument("--families-only", action="store_true", help="run only the proposal-family comparison")
     ap.add_argument("--family-windows", dest="family_windows", type=int, default=120)
+    ap.add_argument("--no-local-global", action="store_true", help="skip the M > 1 logistics experiment")
+    ap.add_argument("--local-global-only", action="store_true", help="run only the M > 1 logistics experiment")
+    ap.add_argument("--lg-windows", dest="lg_windows", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -494,6 +553,9 @@ def main():
         return
     if args.families_only:
         print(json.dumps({"families": families_experiment(args, torch, diam)}), flush=True)
+        return
+    if args.local_global_only:
+        print(json.dumps({"local_global": local_global_experiment(args, torch, diam)}), flush=True)
         return
 
     # -- synthetic workload (host), seeded as the d = 4096 configuration ------
@@ -593,6 +655,8 @@ def main():
         out["batch"] = batch_experiment(args, torch, diam)
     if not args.no_families:
         out["families"] = families_experiment(args, torch, diam)
+    if not args.no_local_global:
+        out["local_global"] = local_global_experiment(args, torch, diam)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(tgt, args)

@@ -55,7 +55,7 @@ struct Layout {
   // PSRF accumulators
   size_t pmean, pm2, pout, merr;
   // per-chain factors and local sums (M > 1)
-  size_t Lp, Gp, hp, xrp, Spg, mpg;
+  size_t Lp, Gp, hp, xrp, Spg, mpg, Cp, mpgp, pinfo, linvb;
   size_t total;
 };
 
@@ -131,6 +131,10 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.xrp = take(lg ? dP * 8 : 0);
   L.Spg = take(lg ? dd * 8 : 0);
   L.mpg = take(lg ? d * 8 : 0);
+  L.Cp = take(lg ? P * dd * 8 : 0);
+  L.mpgp = take(lg ? dP * 8 : 0);
+  L.pinfo = take(lg ? P * 4 : 0);
+  L.linvb = take(lg ? P * dk::chol_scratch_bytes(c.d) : 0);
   if (c.surrogate) {
     const size_t np = dk::mlp_nparam(c.d, MLP_H), H = MLP_H;
     const size_t nmax = P > (size_t)MLP_NMIN ? P : (size_t)MLP_NMIN, nt = (size_t)c.train_max;
@@ -191,7 +195,8 @@ struct diam_ctx {
   // PSRF
   double *pmean, *pm2, *pout, *merr;
   // local-global logistics (M > 1): per-chain pairs, chain-local sums of the batch
-  double *Lp, *Gp, *hp, *xrp, *Spg, *mpg;
+  double *Lp, *Gp, *hp, *xrp, *Spg, *mpg, *Cp, *mpgp, *linvb;
+  int32_t* pinfo;  // per-chain factorisation status (0: factored)
   int m_int;      // intervals merged in the current batch
   double loc_n;   // samples per chain in the current batch
   int pc_on;      // chains propose with their own pairs
@@ -507,6 +512,10 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->xrp = dptr(c, lay.xrp);
   c->Spg = dptr(c, lay.Spg);
   c->mpg = dptr(c, lay.mpg);
+  c->Cp = dptr(c, lay.Cp);
+  c->mpgp = dptr(c, lay.mpgp);
+  c->linvb = dptr(c, lay.linvb);
+  c->pinfo = (int32_t*)(c->ws + lay.pinfo);
   c->m_int = 0;
   c->loc_n = 0.0;
   c->pc_on = 0;
@@ -981,40 +990,56 @@ static int factor_jitter(diam_ctx* c, const double* S, const double* m, int* j) 
 }
 
 // M > 1 inside a batch: every chain's factor and pivot from its local update
-// of the global moments (eqs. mom2pg, mom1pg, cov2pg), chain by chain with the
-// jitter rule; z of the chain recomputed under its new pair.
+// of the global moments (eqs. mom2pg, mom1pg, cov2pg) and z of the chain under
+// its new pair.  All chains are assembled, factored and whitened in batched
+// launches; a chain whose factorisation fails gets the jitter rule alone, and
+// keeps its pair if every level fails.
 static int update_local(diam_ctx* c, int32_t* jitter_used) {
   const int d = c->cfg.d, P = c->cfg.P;
-  const long dd = (long)d * d;
+  const long dd = (long)d * d, sL = (long)(dk::chol_scratch_bytes(d) / sizeof(double));
   hipStream_t s = c->stream;
+  int ps = prof_begin(c, DIAM_ST_CHOL);
   if (!c->pc_on) {  // first local update of the batch: every chain starts from the shared pair
-    for (int p = 0; p < P; ++p) {
-      HIPCHK(hipMemcpyAsync(c->Lp + p * dd, c->L, dd * sizeof(double), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(c->xrp + (long)p * d, c->xr, d * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
+    HIPCHK(dk::pc_bcast(c->L, c->xr, c->Lp, c->xrp, d, P, s));
     c->pc_on = 1;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(P)), dim3(256), 0, s, c->pinfo, (long)P);
+  HIPCHK(dk::pc_cov(c->S, c->m, c->N, c->Gp, c->hp, c->xr, c->loc_n, c->Cp, c->mpgp, d, P, s));
+  HIPCHK(dk::potrf_batched(c->Cp, dd, d, c->pinfo, c->linvb, sL, P, s));
+  prof_end(c, ps);
+  std::vector<int32_t> info(P);
+  HIPCHK(hipMemcpyAsync(info.data(), c->pinfo, P * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  Status st;
+  int r = read_status(c, &st);  // synchronises: info is on the host
+  if (r) return r;
+  r = prof_flush(c);
+  if (r) return r;
+  if (st.err) {
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
+    return fail(DIAM_E_TARGET, "the target log density returned +inf");
   }
   int jmax = -1, failed = 0;
   for (int p = 0; p < P; ++p) {
+    if (info[p] == 0) continue;
     HIPCHK(dk::pc_moments(c->S, c->m, c->N, c->Gp + p * dd, c->hp + (long)p * d, c->xr, c->loc_n, c->Spg, c->mpg,
                           d, s));
     int j = -1;
-    const int r = factor_jitter(c, c->Spg, c->mpg, &j);
+    r = factor_jitter(c, c->Spg, c->mpg, &j);
     if (r) return r;
     jmax = std::max(jmax, j);
     if (j == c->cfg.jitter_tries) {
-      failed += 1;
+      failed += 1;  // its status word stays set: factor and pivot kept
       continue;
     }
-    double* Lq = c->Lp + p * dd;
-    double* xq = c->xrp + (long)p * d;
-    const int ps = prof_begin(c, DIAM_ST_WHITEN);
-    HIPCHK(hipMemcpyAsync(Lq, c->Lnew, dd * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(xq, c->mpg, d * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(dk::trsm_whiten(Lq, c->X + (long)p * d, xq, c->Z + (long)p * d, c->zq + (long)c->cur * P + p, c->linv, d,
-                           1, s));
-    prof_end(c, ps);
+    HIPCHK(hipMemcpyAsync(c->Cp + p * dd, c->Lnew, dd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->mpgp + (long)p * d, c->mpg, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(c->pinfo + p, 0, sizeof(int32_t), s));
   }
+  ps = prof_begin(c, DIAM_ST_WHITEN);
+  HIPCHK(dk::pc_adopt(c->Cp, c->mpgp, c->pinfo, c->Lp, c->xrp, d, P, s));
+  HIPCHK(dk::trsm_whiten_batched(c->Lp, dd, c->X, c->xrp, c->Z, c->zq + (long)c->cur * P, c->linvb, sL, d, P,
+                                 c->pinfo, s));
+  prof_end(c, ps);
   c->last_jitter = jmax;
   if (jitter_used) *jitter_used = jmax;
   if (failed)

@@ -231,6 +231,21 @@ hipError_t pc_scatter(const double* win, double* Gp, double* hp, int d, int P, i
 // (G, h) of n samples shifted by sft: Spg, mpg.
 hipError_t pc_moments(const double* S, const double* m, double N, const double* G, const double* h,
                       const double* sft, double n, double* Spg, double* mpg, int d, hipStream_t s);
+// All chains at once: C_p (lower, zeros above) and m_pg into Cp (P x d x d) and
+// mpgp (d x P), bitwise the one-chain pc_moments + cov_assemble.
+hipError_t pc_cov(const double* S, const double* m, double N, const double* Gp, const double* hp, const double* sft,
+                  double n, double* Cp, double* mpgp, int d, int P, hipStream_t s);
+// Lp[p] = L, xrp[:, p] = xr for every chain.
+hipError_t pc_bcast(const double* L, const double* xr, double* Lp, double* xrp, int d, int P, hipStream_t s);
+// Lp[p] = Cp[p], xrp[:, p] = mpgp[:, p] for the chains with skip[p] == 0.
+hipError_t pc_adopt(const double* Cp, const double* mpgp, const int* skip, double* Lp, double* xrp, int d, int P,
+                    hipStream_t s);
+// nprob independent potrf (problem z: A + z sA, Linv + z sL, info[z]; info
+// zeroed by the caller) and whitenings (z_p = L_p^-1 (x_p - xr_p) and |z_p|^2
+// for the chains with skip[p] == 0), bitwise the one-problem calls.
+hipError_t potrf_batched(double* A, long sA, int d, int* info, double* Linv, long sL, int nprob, hipStream_t s);
+hipError_t trsm_whiten_batched(const double* L, long sA, const double* X, const double* xrp, double* Z, double* zq,
+                               double* Linv, long sL, int d, int P, const int* skip, hipStream_t s);
 // G = sum_p Gp[p], h = sum_p hp[:, p].
 hipError_t pc_sum(const double* Gp, const double* hp, double* G, double* h, int d, int P, hipStream_t s);
 

@@ -1222,6 +1222,104 @@ hipError_t trsm_whiten(const double* L, const double* X, const double* xr, doubl
   return hipGetLastError();
 }
 
+// ---- batches of independent factorisations and whitenings -------------------
+// One problem per blockIdx.z (the per-chain pairs of the local-global
+// logistics), through the same device cores as potrf / trsm_whiten, so every
+// problem's arithmetic is bitwise that of a separate call.  Problem z owns A
+// + z sA, Linv + z sL, info[z]; the whitening works on column z of X and Z.
+// skip (whitening): problem z is left untouched when skip[z] != 0.
+__global__ __launch_bounds__(64) void kb_chol_diag(double* __restrict__ A, long sA, int d, int j0, int jn,
+                                                   double* __restrict__ Linv, long sL, int* __restrict__ info) {
+  const int z = blockIdx.z;
+  chol_diag_block(A + z * sA, d, j0, jn, Linv + z * sL, info + z);
+}
+
+__global__ __launch_bounds__(256) void kb_chol_panel(double* __restrict__ A, long sA, int d, int j0, int jn,
+                                                     const double* __restrict__ Linv, long sL) {
+  const int z = blockIdx.z;
+  chol_panel_tile(A + z * sA, d, j0, jn, Linv + z * sL, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void kb_chol_update_diag(double* __restrict__ A, long sA, int d, int j0, int jn,
+                                                           int t0, double* __restrict__ Linv_next, long sL,
+                                                           int* __restrict__ info) {
+  constexpr int NLDS = CHOL_UPD_LDS > CHOL_DIAG_LDS ? CHOL_UPD_LDS : CHOL_DIAG_LDS;
+  __shared__ double lds[NLDS];
+  const int z = blockIdx.z;
+  double* Az = A + z * sA;
+  chol_update_core(Az, d, j0, jn, t0, blockIdx.x, lds);
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    const int j1 = t0 * CHOL_NB;
+    chol_diag_core(Az, d, j1, min(CHOL_NB, d - j1), Linv_next + z * sL, info + z, lds);
+  }
+}
+
+hipError_t potrf_batched(double* A, long sA, int d, int* info, double* Linv, long sL, int nprob, hipStream_t s) {
+  if (nprob < 1 || nprob > 65535) return hipErrorInvalidValue;
+  const int nb = cdiv(d, CHOL_NB);
+  hipLaunchKernelGGL(kb_chol_diag, dim3(1, 1, nprob), dim3(64), 0, s, A, sA, d, 0, min(CHOL_NB, d), Linv, sL, info);
+  for (int jb = 0; jb + 1 < nb; ++jb) {
+    const int j0 = jb * CHOL_NB, jn = CHOL_NB;
+    const int m = nb - jb - 1;
+    hipLaunchKernelGGL(kb_chol_panel, dim3(m, 1, nprob), dim3(256), 0, s, A, sA, d, j0, jn,
+                       (const double*)(Linv + (long)jb * CHOL_NB * CHOL_NB), sL);
+    hipLaunchKernelGGL(kb_chol_update_diag, dim3(m * (m + 1) / 2, 1, nprob), dim3(256), 0, s, A, sA, d, j0, jn,
+                       jb + 1, Linv + (long)(jb + 1) * CHOL_NB * CHOL_NB, sL, info);
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_sub_ref(const double* __restrict__ X, const double* __restrict__ xrp,
+                                                  double* __restrict__ Z, int d, int P, const int* __restrict__ skip) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < (long)d * P && !skip[e / d]) Z[e] = X[e] - xrp[e];
+}
+
+__global__ __launch_bounds__(64) void kb_tri_inv(const double* __restrict__ L, long sA, int d,
+                                                 double* __restrict__ Linv, long sL, const int* __restrict__ skip) {
+  const int z = blockIdx.z;
+  if (skip[z]) return;
+  tri_inv_block(L + z * sA, d, Linv + z * sL, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void kb_trsm_diag(const double* __restrict__ Linv, long sL, double* __restrict__ Z,
+                                                    int d, int j0, int jn, const int* __restrict__ skip) {
+  const int z = blockIdx.z;
+  if (skip[z]) return;
+  trsm_diag_tile(Linv + z * sL, Z + (long)z * d, d, 1, j0, jn, 0);
+}
+
+__global__ __launch_bounds__(256) void kb_trsm_update(const double* __restrict__ L, long sA, double* __restrict__ Z,
+                                                      int d, int j0, int jn, const int* __restrict__ skip) {
+  const int z = blockIdx.z;
+  if (skip[z]) return;
+  trsm_update_tile(L + z * sA, Z + (long)z * d, d, 1, j0, jn, blockIdx.x, 0);
+}
+
+__global__ __launch_bounds__(256) void kb_colnorm(const double* __restrict__ Z, int d, double* __restrict__ zq,
+                                                  const int* __restrict__ skip) {
+  if (skip[blockIdx.x]) return;
+  colnorm_block(Z, d, zq, blockIdx.x);
+}
+
+hipError_t trsm_whiten_batched(const double* L, long sA, const double* X, const double* xrp, double* Z, double* zq,
+                               double* Linv, long sL, int d, int P, const int* skip, hipStream_t s) {
+  if (P < 1 || P > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kb_sub_ref, dim3(cdiv((long)d * P, 256)), dim3(256), 0, s, X, xrp, Z, d, P, skip);
+  const int nb = cdiv(d, CHOL_NB);
+  hipLaunchKernelGGL(kb_tri_inv, dim3(nb, 1, P), dim3(64), 0, s, L, sA, d, Linv, sL, skip);
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
+    hipLaunchKernelGGL(kb_trsm_diag, dim3(1, 1, P), dim3(256), 0, s,
+                       (const double*)(Linv + (long)jb * CHOL_NB * CHOL_NB), sL, Z, d, j0, jn, skip);
+    const int rem = d - (j0 + jn);
+    if (rem > 0) hipLaunchKernelGGL(kb_trsm_update, dim3(cdiv(rem, 64), 1, P), dim3(256), 0, s, L, sA, Z, d, j0, jn, skip);
+  }
+  hipLaunchKernelGGL(kb_colnorm, dim3(P), dim3(256), 0, s, Z, d, zq, skip);
+  return hipGetLastError();
+}
+
 // ============================================================================
 // random numbers: Philox4x32-10 counters (stream 0 = W, 1 + g = U stage g)
 // ============================================================================

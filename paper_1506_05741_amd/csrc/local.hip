@@ -171,6 +171,53 @@ __global__ __launch_bounds__(256) void k_pc_sum(const double* __restrict__ Gp, c
   }
 }
 
+// Every chain's covariance C_p = S_pg - m_pg m_pg^T (lower triangle, zeros
+// above) and pivot m_pg at once, blockIdx.z = chain: the arithmetic of
+// k_pc_moments followed by the covariance assembly, operation for operation,
+// so a chain's C_p is bitwise what the one-chain path assembles.
+__global__ __launch_bounds__(256) void k_pc_cov(const double* __restrict__ S, const double* __restrict__ m, double N,
+                                                const double* __restrict__ Gp, const double* __restrict__ hp,
+                                                const double* __restrict__ sft, double n, double* __restrict__ Cp,
+                                                double* __restrict__ mpgp, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x, dd = (long)d * d;
+  const int z = blockIdx.z;
+  const double* h = hp + (long)z * d;
+  const double inv = 1.0 / (N + n);
+  if (e < dd) {
+    const int i = (int)(e % d), j = (int)(e / d);
+    double v = 0.0;
+    if (i >= j) {
+      const double raw = Gp[e + z * dd] + h[i] * sft[j] + sft[i] * h[j] + n * sft[i] * sft[j];
+      const double Spg = (N * S[e] + raw) * inv;
+      const double mi = (N * m[i] + (h[i] + n * sft[i])) * inv;
+      const double mj = (N * m[j] + (h[j] + n * sft[j])) * inv;
+      v = Spg - mi * mj;
+    }
+    Cp[e + z * dd] = v;
+  }
+  if (e < d) mpgp[e + (long)z * d] = (N * m[e] + (h[e] + n * sft[e])) * inv;
+}
+
+// Every chain starts the batch's local updates from the shared pair.
+__global__ __launch_bounds__(256) void k_pc_bcast(const double* __restrict__ L, const double* __restrict__ xr,
+                                                  double* __restrict__ Lp, double* __restrict__ xrp, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x, dd = (long)d * d;
+  const int z = blockIdx.z;
+  if (e < dd) Lp[e + z * dd] = L[e];
+  if (e < d) xrp[e + (long)z * d] = xr[e];
+}
+
+// Chains whose factorisation succeeded (skip[z] == 0) adopt factor and pivot.
+__global__ __launch_bounds__(256) void k_pc_adopt(const double* __restrict__ Cp, const double* __restrict__ mpgp,
+                                                  const int* __restrict__ skip, double* __restrict__ Lp,
+                                                  double* __restrict__ xrp, int d) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x, dd = (long)d * d;
+  const int z = blockIdx.z;
+  if (skip[z]) return;
+  if (e < dd) Lp[e + z * dd] = Cp[e + z * dd];
+  if (e < d) xrp[e + (long)z * d] = mpgp[e + (long)z * d];
+}
+
 long cdiv_l(long a, long b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -195,6 +242,29 @@ hipError_t pc_moments(const double* S, const double* m, double N, const double* 
                       const double* sft, double n, double* Spg, double* mpg, int d, hipStream_t s) {
   hipLaunchKernelGGL(k_pc_moments, dim3((unsigned)cdiv_l((long)d * d, 256)), dim3(256), 0, s, S, m, N, G, h, sft,
                      n, Spg, mpg, d);
+  return hipGetLastError();
+}
+
+hipError_t pc_cov(const double* S, const double* m, double N, const double* Gp, const double* hp, const double* sft,
+                  double n, double* Cp, double* mpgp, int d, int P, hipStream_t s) {
+  if (P < 1 || P > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pc_cov, dim3((unsigned)cdiv_l((long)d * d, 256), 1, (unsigned)P), dim3(256), 0, s, S, m, N, Gp,
+                     hp, sft, n, Cp, mpgp, d);
+  return hipGetLastError();
+}
+
+hipError_t pc_bcast(const double* L, const double* xr, double* Lp, double* xrp, int d, int P, hipStream_t s) {
+  if (P < 1 || P > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pc_bcast, dim3((unsigned)cdiv_l((long)d * d, 256), 1, (unsigned)P), dim3(256), 0, s, L, xr, Lp,
+                     xrp, d);
+  return hipGetLastError();
+}
+
+hipError_t pc_adopt(const double* Cp, const double* mpgp, const int* skip, double* Lp, double* xrp, int d, int P,
+                    hipStream_t s) {
+  if (P < 1 || P > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pc_adopt, dim3((unsigned)cdiv_l((long)d * d, 256), 1, (unsigned)P), dim3(256), 0, s, Cp, mpgp,
+                     skip, Lp, xrp, d);
   return hipGetLastError();
 }
 

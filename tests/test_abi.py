@@ -51,12 +51,16 @@ def test_workspace_bytes_scales_with_precision():
 
 
 def test_workspace_bytes_of_the_local_global_form():
-    # M > 1 adds the per-chain factors and local sums, 2 P d^2 + 2 d P + d^2 + d
-    # doubles, in six regions that hold a 256-byte placeholder otherwise
+    # M > 1 adds ten regions (each a 256-byte placeholder otherwise): per-chain
+    # factors, local sums G_p and h_p, pivots, one chain's S_pg and m_pg, all
+    # chains' covariances and pivots, status words, block inverses (64 x 64
+    # per block of 64 rows)
     d, P = 64, 4
     base = diam.workspace_bytes(diam.make_config(d, P, 4, "fp64"), GAUSS)
     lg = diam.workspace_bytes(diam.make_config(d, P, 4, "fp64", M=3), GAUSS)
-    assert lg - base == (2 * P * d * d + 2 * d * P + d * d + d) * 8 - 6 * 256
+    sizes = [P * d * d * 8, P * d * d * 8, d * P * 8, d * P * 8, d * d * 8, d * 8, P * d * d * 8, d * P * 8, P * 4,
+             P * 64 * 64 * 8]
+    assert lg - base == sum((b + 255) // 256 * 256 for b in sizes) - 10 * 256
 
 
 def test_workspace_bytes_of_the_learned_form():
