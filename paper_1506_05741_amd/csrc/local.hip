@@ -9,120 +9,89 @@
 // of y y^T and y over the batch so far, y = x - s with s the shared pivot of
 // the batch (the shift the window store already carries).
 #include "common.h"
+#include "gemm.h"
 #include "kernels.h"
+
+using namespace gemm;
 
 namespace dk {
 
 namespace {
 
-constexpr int PC_TM = 64;   // rows per tile
-constexpr int PC_TN = 32;   // steps per tile of the proposal contraction
-constexpr int PC_TK = 32;   // contraction chunk
+constexpr int PC_T = 64;    // 64 x 64 output tiles on the FP64 MFMA engine
+constexpr int PC_BK = 16;   // K slice
+
+// lower tile t of the row-by-row enumeration: (0,0), (1,0), (1,1), (2,0), ...
+DEV void lower_tile(int t, int& bi, int& bj) {
+  int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((b + 1) * (b + 2) / 2 <= t) ++b;
+  while (b * (b + 1) / 2 > t) --b;
+  bi = b;
+  bj = t - b * (b + 1) / 2;
+}
 
 // Xi[:, tP+p] = c L_p W[:, tP+p] + (1 - rho)(xr_p - xr).  With the step's
 // x' = xr + rho (x - xr) + Xi this is eq. diam about chain p's own pivot:
-// x' = xr_p + rho (x - xr_p) + c L_p W.  Tile: 64 rows x 32 steps of one
-// chain, 256 threads holding 4 rows x 2 steps each; only the lower triangle
-// of L_p is read (the upper part of the buffer is not a factor entry).
+// x' = xr_p + rho (x - xr_p) + c L_p W.  One workgroup per (64 rows, 64
+// steps, chain) on the FP64 MFMA engine; chain p's normals are the d x n
+// operand at W + p d with leading dimension P d.  K stops at the tile's last
+// row: the factor buffers hold zeros above the diagonal.
 __global__ __launch_bounds__(256) void k_pc_gemm(const double* __restrict__ Lp, const double* __restrict__ W,
                                                  const double* __restrict__ xrp, const double* __restrict__ xr,
                                                  double* __restrict__ Xi, int d, int P, int n, double c,
                                                  double omr) {
-  __shared__ double As[PC_TK][PC_TM + 1];
-  __shared__ double Bs[PC_TK][PC_TN + 1];
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  const int i0 = blockIdx.x * PC_TM, t0 = blockIdx.y * PC_TN, p = blockIdx.z;
-  const double* L = Lp + (long)p * d * d;
-  double acc[4][2] = {};
-  const int kend = min(d, i0 + PC_TM);
-  for (int k0 = 0; k0 < kend; k0 += PC_TK) {
+  __shared__ double lds[e_lds_elems<double, PC_T, PC_T, PC_BK>()];
+  const int i0 = blockIdx.x * PC_T, t0 = blockIdx.y * PC_T, p = blockIdx.z;
+  const long ldw = (long)P * d;
+  EFrag<double, PC_T, PC_T> f;
+  f.zero();
+  e_gemm<double, PC_T, PC_T, PC_BK, false, true>(f, Lp + (long)p * d * d, d, d, W + (long)p * d, ldw, n, i0, t0, 0,
+                                                 min(d, i0 + PC_T), lds);
 #pragma unroll
-    for (int e = 0; e < PC_TM * PC_TK / 256; ++e) {
-      const int idx = tid + e * 256, r = idx % PC_TM, k = idx / PC_TM;
-      const int i = i0 + r, kk = k0 + k;
-      As[k][r] = (i < d && kk <= i) ? L[i + (long)kk * d] : 0.0;
-    }
+  for (int m = 0; m < EFrag<double, PC_T, PC_T>::FM; ++m)
 #pragma unroll
-    for (int e = 0; e < PC_TK * PC_TN / 256; ++e) {
-      const int idx = tid + e * 256, k = idx % PC_TK, tt = idx / PC_TK;
-      const int kk = k0 + k, t = t0 + tt;
-      Bs[k][tt] = (kk < d && t < n) ? W[kk + ((long)t * P + p) * d] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < PC_TK; ++k) {
-      double a[4], b[2];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[k][tr * 4 + r];
-      b[0] = Bs[k][tc * 2];
-      b[1] = Bs[k][tc * 2 + 1];
+    for (int q = 0; q < EFrag<double, PC_T, PC_T>::FN; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        acc[r][0] = __fma_rn(a[r], b[0], acc[r][0]);
-        acc[r][1] = __fma_rn(a[r], b[1], acc[r][1]);
+        int ti, tj;
+        frag_coords<PC_T, PC_T, double>(m, q, r, ti, tj);
+        const int i = i0 + ti, t = t0 + tj;
+        if (i < d && t < n)
+          Xi[i + ((long)t * P + p) * d] = __fma_rn(c, f.c[m][q][r], omr * (xrp[i + (long)p * d] - xr[i]));
       }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tr * 4 + r;
-    if (i >= d) continue;
-    const double corr = omr * (xrp[i + (long)p * d] - xr[i]);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int t = t0 + tc * 2 + q;
-      if (t < n) Xi[i + ((long)t * P + p) * d] = __fma_rn(c, acc[r][q], corr);
-    }
-  }
 }
 
 // G_p += sum_t y_t y_t^T over one window (y = the stored shifted states of
-// chain p).  Tile 64 x 64 of G_p, 256 threads with 4 x 4 entries each; each
-// tile is owned by one workgroup, so the update is a plain read-add-write.
+// chain p: the d x n operand at win + p d, leading dimension P d).  Lower
+// 64 x 64 tiles only, on the FP64 MFMA engine; entry (i, j), i >= j, is added
+// at (i, j) and (j, i) by the one workgroup that owns it, so G_p stays
+// exactly symmetric and needs no atomics.
 __global__ __launch_bounds__(256) void k_pc_scatter(const double* __restrict__ win, double* __restrict__ Gp, int d,
                                                     int P, int n) {
-  __shared__ double Yi[PC_TK][PC_TM + 1];
-  __shared__ double Yj[PC_TK][PC_TM + 1];
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  const int i0 = blockIdx.x * PC_TM, j0 = blockIdx.y * PC_TM, p = blockIdx.z;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < n; k0 += PC_TK) {
-#pragma unroll
-    for (int e = 0; e < PC_TM * PC_TK / 256; ++e) {
-      const int idx = tid + e * 256, r = idx % PC_TM, k = idx / PC_TM;
-      const int t = k0 + k;
-      const long col = ((long)t * P + p) * d;
-      Yi[k][r] = (t < n && i0 + r < d) ? win[i0 + r + col] : 0.0;
-      Yj[k][r] = (t < n && j0 + r < d) ? win[j0 + r + col] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < PC_TK; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[r] = Yi[k][tr * 4 + r];
-        b[r] = Yj[k][tc * 4 + r];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] = __fma_rn(a[r], b[q], acc[r][q]);
-    }
-    __syncthreads();
-  }
+  __shared__ double lds[e_lds_elems<double, PC_T, PC_T, PC_BK>()];
+  int bi, bj;
+  lower_tile(blockIdx.x, bi, bj);
+  const int i0 = bi * PC_T, j0 = bj * PC_T, p = blockIdx.z;
+  const double* Y = win + (long)p * d;
+  const long ld = (long)P * d;
+  EFrag<double, PC_T, PC_T> f;
+  f.zero();
+  e_gemm<double, PC_T, PC_T, PC_BK, false, false>(f, Y, ld, d, Y, ld, d, i0, j0, 0, n, lds);
   double* G = Gp + (long)p * d * d;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + tr * 4 + r;
-    if (i >= d) continue;
+  for (int m = 0; m < EFrag<double, PC_T, PC_T>::FM; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tc * 4 + q;
-      if (j < d) G[i + (long)j * d] += acc[r][q];
-    }
-  }
+    for (int q = 0; q < EFrag<double, PC_T, PC_T>::FN; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int ti, tj;
+        frag_coords<PC_T, PC_T, double>(m, q, r, ti, tj);
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < d && j <= i) {
+          G[i + (long)j * d] += f.c[m][q][r];
+          if (j < i) G[j + (long)i * d] += f.c[m][q][r];
+        }
+      }
 }
 
 // h_p += sum_t y_t: one thread per (row, chain), the window's steps in order.
@@ -225,15 +194,16 @@ long cdiv_l(long a, long b) { return (a + b - 1) / b; }
 hipError_t pc_gemm(const double* Lp, const double* W, const double* xrp, const double* xr, double* Xi, int d, int P,
                    int n, double c, double one_minus_rho, hipStream_t s) {
   if (d < 1 || P < 1 || n < 1 || P > 65535) return hipErrorInvalidValue;
-  dim3 grid((unsigned)cdiv_l(d, PC_TM), (unsigned)cdiv_l(n, PC_TN), (unsigned)P);
+  dim3 grid((unsigned)cdiv_l(d, PC_T), (unsigned)cdiv_l(n, PC_T), (unsigned)P);
   hipLaunchKernelGGL(k_pc_gemm, grid, dim3(256), 0, s, Lp, W, xrp, xr, Xi, d, P, n, c, one_minus_rho);
   return hipGetLastError();
 }
 
 hipError_t pc_scatter(const double* win, double* Gp, double* hp, int d, int P, int n, hipStream_t s) {
   if (d < 1 || P < 1 || n < 1 || P > 65535) return hipErrorInvalidValue;
-  const unsigned tiles = (unsigned)cdiv_l(d, PC_TM);
-  hipLaunchKernelGGL(k_pc_scatter, dim3(tiles, tiles, (unsigned)P), dim3(256), 0, s, win, Gp, d, P, n);
+  const long nb = cdiv_l(d, PC_T);
+  hipLaunchKernelGGL(k_pc_scatter, dim3((unsigned)(nb * (nb + 1) / 2), 1, (unsigned)P), dim3(256), 0, s, win, Gp, d, P,
+                     n);
   hipLaunchKernelGGL(k_pc_rowsum, dim3((unsigned)cdiv_l(d, 256), (unsigned)P), dim3(256), 0, s, win, hp, d, P, n);
   return hipGetLastError();
 }
