@@ -397,6 +397,34 @@ def families_experiment(args, torch, diam):
     return out
 
 
+def precision_experiment(args, torch, diam):
+    """The d = 1024 configuration: Gaussian target seed 1 (lambda_i = i^-2,
+    cond 1.05e6), P = 64, n_lag = 200, beta = 0.3, warm start with N0 = P 1e5;
+    FP64 against FP32 (and the mixed form), each timed over whole windows with
+    ESS over the second half."""
+    import argparse as _ap
+    from paper_1506_05741_amd import synth
+    d, P, nl = 1024, 64, 200
+    t = synth.gaussian_target(d, 1)
+    x0 = synth.gaussian_exact_draws(t, P, 2)
+    S0, m0 = synth.gaussian_warm_moments(t)
+    tgt = dict(mu=t.mu, R=t.R, x0=x0, S0=S0, m0=m0, N0=float(P) * 1e5, v_max=t.v_max, v_min=t.v_min)
+    sub = _ap.Namespace(**vars(args))
+    sub.d, sub.P, sub.n_lag, sub.beta, sub.steps, sub.warmup = d, P, nl, 0.3, args.c2_windows, 2
+    out = {"workload": f"Gaussian d={d} (seed 1), P={P}, n_lag={nl}, beta=0.3, warm start N0=P*1e5; "
+                       f"{args.c2_windows} timed windows", "precisions": {}}
+    for prec in ("fp64", "fp32", "mixed"):
+        r = run_sampler(prec, tgt, sub, torch, diam, profile=False)
+        out["precisions"][prec] = {k: r[k] for k in ("chain_steps_per_s", "ess_per_s", "ms_per_window", "acceptance")}
+        log(f"d=1024 {prec}: {r['chain_steps_per_s']:.4g} chain-steps/s, ESS/s {r['ess_per_s']:.4g}, "
+            f"{r['ms_per_window']:.2f} ms/window")
+    f64 = out["precisions"]["fp64"]
+    out["speedup_vs_fp64"] = {p: {"chain_steps": v["chain_steps_per_s"] / f64["chain_steps_per_s"],
+                                  "ess": v["ess_per_s"] / f64["ess_per_s"]}
+                              for p, v in out["precisions"].items() if p != "fp64"}
+    return out
+
+
 def local_global_experiment(args, torch, diam):
     """Section 2.4.1's logistics with M intervals per batch: M = 1 (every
     merge global, one shared factor) against M = 4 (each chain refactorised
@@ -525,6 +553,9 @@ def main():
     ap.add_argument("--no-local-global", action="store_true", help="skip the M > 1 logistics experiment")
     ap.add_argument("--local-global-only", action="store_true", help="run only the M > 1 logistics experiment")
     ap.add_argument("--lg-windows", dest="lg_windows", type=int, default=8)
+    ap.add_argument("--no-d1024", action="store_true", help="skip the d = 1024 precision comparison")
+    ap.add_argument("--d1024-only", action="store_true", help="run only the d = 1024 precision comparison")
+    ap.add_argument("--c2-windows", dest="c2_windows", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -553,6 +584,9 @@ def main():
         return
     if args.families_only:
         print(json.dumps({"families": families_experiment(args, torch, diam)}), flush=True)
+        return
+    if args.d1024_only:
+        print(json.dumps({"d1024": precision_experiment(args, torch, diam)}), flush=True)
         return
     if args.local_global_only:
         print(json.dumps({"local_global": local_global_experiment(args, torch, diam)}), flush=True)
@@ -655,6 +689,8 @@ def main():
         out["batch"] = batch_experiment(args, torch, diam)
     if not args.no_families:
         out["families"] = families_experiment(args, torch, diam)
+    if not args.no_d1024:
+        out["d1024"] = precision_experiment(args, torch, diam)
     if not args.no_local_global:
         out["local_global"] = local_global_experiment(args, torch, diam)
     if not args.no_cpu:

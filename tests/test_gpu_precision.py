@@ -55,11 +55,13 @@ LP_TOL = {"fp32": 1e-4, "mixed": 1e-4}
 S_TOL = {"fp32": 1e-5, "mixed": 5e-3}
 
 
-@pytest.mark.parametrize("prec,P", [("fp32", 32), ("mixed", 32), ("mixed", 64), ("mixed", 128)])
-def test_per_stage_error_against_fp64(prec, P):
-    # P = 64 and 128 take the mixed form's split-bf16 target contraction (64 and 128 tiles)
-    d, n_lag = 256, 16
-    t, x0, s = make(d, P, n_lag, prec)
+@pytest.mark.parametrize("prec,P,d,tseed", [("fp32", 32, 256, 3), ("mixed", 32, 256, 3), ("mixed", 64, 256, 3),
+                                            ("mixed", 128, 256, 3), ("fp32", 64, 1024, 1), ("mixed", 64, 1024, 1)])
+def test_per_stage_error_against_fp64(prec, P, d, tseed):
+    # P = 64 and 128 take the mixed form's split-bf16 target contraction (64 and
+    # 128 tiles); d = 1024, seed 1, P = 64 is the d = 1024 configuration's target
+    n_lag = 16
+    t, x0, s = make(d, P, n_lag, prec, tseed=tseed)
     o = od.DiamOracle(lambda X: ot.gaussian_logpdf(t.R, t.mu, X), d, P, n_lag, 0.3, X=x0)
     S0, m0 = synth.gaussian_warm_moments(t)
     o.seed_moments(S0, m0, 10 * P * n_lag)
