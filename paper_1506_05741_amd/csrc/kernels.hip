@@ -1182,9 +1182,19 @@ DEV void trsm_update_tile(const double* __restrict__ L, double* __restrict__ Z, 
       }
 }
 
-__global__ __launch_bounds__(256) void k_trsm_update(const double* __restrict__ L, double* __restrict__ Z, int d, int P,
-                                                     int j0, int jn) {
+// The update of block column j fused with the diagonal solve of block j + 1:
+// the first row tile of the update is that block, so the workgroup that
+// finishes it applies Linv_{j+1} to its own column tile at once (the barrier
+// orders the tile's stores before the solve's loads in one workgroup; no
+// other workgroup touches that tile before the next launch).
+__global__ __launch_bounds__(256) void k_trsm_update_diag(const double* __restrict__ L, double* __restrict__ Z, int d,
+                                                          int P, int j0, int jn, const double* __restrict__ Linv_next) {
   trsm_update_tile(L, Z, d, P, j0, jn, blockIdx.x, blockIdx.y);
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    const int j1 = j0 + jn;
+    trsm_diag_tile(Linv_next, Z, d, P, j1, min(CHOL_NB, d - j1), blockIdx.y);
+  }
 }
 
 DEV void colnorm_block(const double* __restrict__ Z, int d, double* __restrict__ zq, int p) {
@@ -1212,13 +1222,15 @@ hipError_t trsm_whiten(const double* L, const double* X, const double* xr, doubl
   hipLaunchKernelGGL(k_sub_ref, dim3(cdiv((long)d * P, 256)), dim3(256), 0, s, X, xr, Z, d, P);
   const int nb = cdiv(d, CHOL_NB);
   hipLaunchKernelGGL(k_tri_inv, dim3(nb), dim3(64), 0, s, L, d, Linv);
+  // block 0's solve, then per block column the update fused with the next block's solve
+  hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(P, 64)), dim3(256), 0, s, (const double*)Linv, Z, d, P, 0,
+                     min(CHOL_NB, d));
   for (int jb = 0; jb < nb; ++jb) {
     const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, d - j0);
-    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(P, 64)), dim3(256), 0, s, (const double*)(Linv + (long)jb * CHOL_NB * CHOL_NB),
-                       Z, d, P, j0, jn);
     const int rem = d - (j0 + jn);
     if (rem > 0)
-      hipLaunchKernelGGL(k_trsm_update, dim3(cdiv(rem, 64), cdiv(P, 64)), dim3(256), 0, s, L, Z, d, P, j0, jn);
+      hipLaunchKernelGGL(k_trsm_update_diag, dim3(cdiv(rem, 64), cdiv(P, 64)), dim3(256), 0, s, L, Z, d, P, j0, jn,
+                         (const double*)(Linv + (long)(jb + 1) * CHOL_NB * CHOL_NB));
   }
   if (zq) hipLaunchKernelGGL(k_colnorm, dim3(P), dim3(256), 0, s, Z, d, zq);
   return hipGetLastError();
