@@ -145,6 +145,7 @@ struct StepArgs {
   const double* s_in; double* s_out;      // P: surrogate at the current states
   const double* u2;                       // P
   int da_resid;                           // residual surrogate r(x) - |z|^2/(2 alpha^2)
+  int fuse_dec;                           // set by step(): the update kernel takes the decision itself
   uint16_t* v3;                           // non-null: write V as three bf16 parts (d x P each) instead
   int ldv;                                // leading dimension of V (0: d)
   int ldw;                                // leading dimension of Xi and W (0: d)

@@ -1730,6 +1730,40 @@ DEV void decide_block(const StepArgs& a, int nch, int p) {
 
 __global__ __launch_bounds__(256) void k_decide(StepArgs a, int nch) { decide_block(a, nch, blockIdx.x); }
 
+// The decision of chain p taken by one wavefront inside the update launch
+// (no delayed acceptance; at most 64 target row blocks and 64 row chunks).
+// With that many partials decide_block's block sums reduce to wave 0's
+// shuffle sum plus exact zeros, so these sums, log alpha and the verdict are
+// bitwise decide_block's.  Every row-chunk workgroup of the chain takes the
+// (cheap, L2-resident) decision; only `write` stores its outputs.
+DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write) {
+  const int lane = threadIdx.x & 63;
+  double s = lane < a.nrb ? 0.0 + a.lpp_part[(long)p * a.nrb + lane] : 0.0;
+  s = wave_sum_f64(s);
+  if (a.prior_w > 0.0) {
+    double pq = lane < nch ? 0.0 + a.pq_part_cur[(long)p * nch + lane] : 0.0;
+    pq = wave_sum_f64(pq);
+    s = __fma_rn(-a.prior_w, pq, s);
+  }
+  const double lpp = s;
+  double zs = lane < nch ? 0.0 + a.zq_part_cur[(long)p * nch + lane] : 0.0;
+  zs = wave_sum_f64(zs);
+  const double lp = a.lp_cur[p], zq = a.zq_cur[p];
+  const double la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
+  const bool acc = log(a.u[p]) < la;  // NaN compares false: rejected
+  if (write && lane == 0) {
+    a.lp_nxt[p] = acc ? lpp : lp;
+    a.zq_nxt[p] = acc ? zs : zq;
+    a.nacc[p] += acc ? 1 : 0;
+    if (a.wacc) a.wacc[p] += acc ? 1 : 0;
+    a.la_out[p] = la;
+    a.acc_out[p] = acc ? 1 : 0;
+    if (a.trace_lp) a.trace_lp[p] = acc ? lpp : lp;
+    if (isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
+  }
+  return acc;
+}
+
 // Paired-row loads and stores for the update half (d even, so that every
 // chain's column starts on an even element): lane l owns rows 2l, 2l + 1 of
 // its 128-row chunk and moves them with 16-, 8- or 4-byte accesses.
@@ -1784,7 +1818,7 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
   const int i = ch * STEP_RCH + 2 * lane;
   const bool in = i < d;  // d even: the pair lies wholly inside or outside
   const long e = i + (long)p * d;
-  const bool acc = a.do_accept && a.acc_out[p] != 0;
+  const bool acc = a.do_accept && (a.fuse_dec ? decide_wave(a, nch, p, ch == 0) : a.acc_out[p] != 0);
   double x0 = 0, x1 = 0, z0 = 0, z1 = 0, r0 = 0, r1 = 0;
   double c0 = 0, c1 = 0, wc0 = 0, wc1 = 0, n0 = 0, n1 = 0, wn0 = 0, wn1 = 0, m0 = 0, m1 = 0;
   if (in) {
@@ -1870,10 +1904,13 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a, int nch) {
 hipError_t step(const StepArgs& a, hipStream_t s) {
   const int nch = step_chunks(a.d);
   const dim3 gupd(nch, cdiv(a.P, 4));
-  if (a.do_accept) hipLaunchKernelGGL(k_decide, dim3(a.P), dim3(256), 0, s, a, nch);
-  if (a.prec == P64) hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, a, nch);
-  else if (a.prec == P32) hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, a, nch);
-  else hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, a, nch);
+  // the decision moves into the update launch where one wavefront can take it
+  StepArgs b = a;
+  b.fuse_dec = a.do_accept && !a.da && a.nrb <= 64 && nch <= 64 && (a.d & 1) == 0;
+  if (a.do_accept && !b.fuse_dec) hipLaunchKernelGGL(k_decide, dim3(a.P), dim3(256), 0, s, b, nch);
+  if (a.prec == P64) hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, b, nch);
+  else if (a.prec == P32) hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, b, nch);
+  else hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, b, nch);
   return hipGetLastError();
 }
 
