@@ -270,7 +270,10 @@ def batch_experiment(args, torch, diam):
     xs = [torch.as_tensor(np.ascontiguousarray(x.T), device=dev) for x in x0]
     S0 = [torch.as_tensor(t.Sigma + np.outer(t.mu, t.mu), device=dev) for t in ts]
     m0 = [torch.as_tensor(t.mu, device=dev) for t in ts]
-    N0 = 10.0 * P * nl
+    # warm start with N0 = P x the run's samples per chain (100 windows of 128
+    # steps): with only 10 windows the adaptation at d ~ 3000 degrades the
+    # acceptance and the window-end variances within tens of windows
+    N0 = float(P) * 12800
     cfg = diam.make_batch_config(48, P, nl, beta=0.3, seed=77)
     b = diam.Batch(cfg, mus, Rs, xs)
     assert b.seed_moments(S0, m0, N0)[0] == diam.OK
@@ -286,13 +289,38 @@ def batch_experiment(args, torch, diam):
     T = time.perf_counter() - t1
     nacc = sum(int(b.get(g, diam.F_NACC).view(torch.int32).sum()) for g in range(48))
     acc = nacc / (48 * P * nl * (args.batch_windows + 1))
+    # ESS and per-target moments from window-end states of further, untimed
+    # windows: projections on each target's largest- and smallest-variance
+    # eigenvectors; ESS per window (minimum of the two) summed over the 48
+    # targets, times the timed windows per second
+    proj = [np.stack([t.Q[:, 0], t.Q[:, -1]]) for t in ts]
+    series = [[] for _ in ts]
+    for _ in range(args.batch_ess_windows):
+        assert b.window()[0] == diam.OK
+        for g, t in enumerate(ts):
+            series[g].append(b.get_f64(g, diam.F_X, (P, t.d)).cpu().numpy() @ proj[g].T)
+    ess_win, worst = 0.0, 0.0
+    for g, t in enumerate(ts):
+        Y = np.stack(series[g])                               # windows x P x 2
+        es = []
+        for f, lam in ((0, t.lam[0]), (1, t.lam[-1])):
+            y, m = Y[:, :, f], proj[g][f] @ t.mu
+            es.append(ess_per_chain(y))
+            for h, truth in ((y, m), ((y - m) ** 2, lam)):
+                worst = max(worst, abs(h.mean() - truth) / (h.std() / math.sqrt(ess_per_chain(h))))
+        ess_win += min(es) / Y.shape[0]
     b.close()
     chain_steps = 48 * P * nl * args.batch_windows
     flops = 2.0 * sum(d * d for d in dims) * P
     out = {"workload": "48 Gaussian targets, d log-uniform in [128, 3072] (sum d = %d), 32 chains each, "
-                       "n_lag=128, beta=0.3, fp32 with fp64 Cholesky, warm start" % sum(dims),
+                       "n_lag=128, beta=0.3, fp32 with fp64 Cholesky, warm start N0=32*12800" % sum(dims),
            "windows": args.batch_windows, "ms_per_window": 1e3 * T / args.batch_windows,
            "chain_steps_per_s": chain_steps / T, "acceptance": acc,
+           "ess_per_s_summed": ess_win * args.batch_windows / T,
+           "ess": {"windows": args.batch_ess_windows, "per_window_summed": ess_win,
+                   "worst_z_moments": worst,
+                   "note": "window-end states of the 48 targets, v_max^T x and v_min^T x; worst |z| of their "
+                           "means and variances against the exact values over all targets"},
            "autotune_us_per_target_launch": us, "tile_choice": diam.BATCH_TILES[choice],
            "target_roofline": {"kernel": "gk_tgt (grouped fp32 MFMA target contraction)", "bound": "mfma",
                                "achieved": flops / (us[diam.BATCH_TILES[choice]] * 1e-6) / 1e12,
@@ -326,7 +354,8 @@ def batch_experiment(args, torch, diam):
                          "chain_steps_per_s": 48 * P * nl * nseq / Ts}
     out["speedup_vs_sequential"] = out["chain_steps_per_s"] / out["sequential"]["chain_steps_per_s"]
     log(f"batch: {out['chain_steps_per_s']:.4g} chain-steps/s ({out['ms_per_window']:.2f} ms/window, tiles "
-        f"{out['tile_choice']}), sequential {out['sequential']['chain_steps_per_s']:.4g}")
+        f"{out['tile_choice']}), sequential {out['sequential']['chain_steps_per_s']:.4g}, ESS/s summed "
+        f"{out['ess_per_s_summed']:.4g}, worst |z| {worst:.2f}")
     return out
 
 
@@ -430,7 +459,7 @@ def local_global_experiment(args, torch, diam):
     merge global, one shared factor) against M = 4 (each chain refactorised
     from its local update of the global moments between global merges), FP64,
     Gaussian target d = 1024 (seed 1, lambda_i = i^-2), P = 64, n_lag = 200,
-    warm start with N0 = 10 P n_lag.  Timed: whole batches (one window = one
+    warm start with N0 = P 1e5 as the d = 1024 configuration.  Timed: whole batches (one window = one
     interval); the stage split comes from HIP events on one further batch."""
     from paper_1506_05741_amd import synth
     d, P, nl = 1024, 64, 200
@@ -440,12 +469,12 @@ def local_global_experiment(args, torch, diam):
     S0, m0 = synth.gaussian_warm_moments(t)
     mu, R = torch.as_tensor(t.mu, device=dev), torch.as_tensor(t.R, device=dev)
     proj = torch.as_tensor(np.stack([t.v_max, t.v_min]), device=dev).contiguous()
-    out = {"workload": f"Gaussian d={d} (seed 1), P={P}, n_lag={nl}, fp64, beta=0.3, warm start N0=10 P n_lag; "
+    out = {"workload": f"Gaussian d={d} (seed 1), P={P}, n_lag={nl}, fp64, beta=0.3, warm start N0=P*1e5; "
                        "window = one interval of n_lag steps", "M": {}}
     for M in (1, 4):
         smp = diam.Sampler(diam.make_config(d, P, nl, "fp64", beta=0.3, seed=41, M=M), mu, R, x0)
         assert smp.seed_moments(torch.as_tensor(S0, device=dev), torch.as_tensor(m0, device=dev),
-                                10.0 * P * nl)[0] == diam.OK
+                                float(P) * 1e5)[0] == diam.OK
 
         def window():
             smp.step_batch(nl)
@@ -547,6 +576,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form experiment")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-form experiment")
     ap.add_argument("--batch-windows", dest="batch_windows", type=int, default=6)
+    ap.add_argument("--batch-ess-windows", dest="batch_ess_windows", type=int, default=40)
     ap.add_argument("--no-families", action="store_true", help="skip the proposal-family comparison")
     ap.add_argument("--families-only", action="store_true", help="run only the proposal-family comparison")
     ap.add_argument("--family-windows", dest="family_windows", type=int, default=120)
