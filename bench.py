@@ -661,7 +661,7 @@ def main():
                     "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK[tdt] / 1e12, "unit": "TFLOP/s",
                     "frac": useful / dt / PEAK[tdt], "traffic": TRAFFIC.get(f"k_tgt_gauss_{tdt}"),
                     "avg_us": dt * 1e6, "launches": n_t}
-    # the proposal contraction of the window (the benchmark spec: >= 60 % of bf16 peak)
+    # the proposal contraction of the window (aim: >= 60 % of the bf16 peak)
     ms_p, n_p = prof["proposal"]
     if args.precision == "mixed" and n_p:
         pf = 4.0 * args.d * (args.d + 1) * args.P * args.n_lag   # four bf16 hi/lo products, triangular
