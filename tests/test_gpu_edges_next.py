@@ -6,7 +6,7 @@ oracle, FP64:
 * AM, pCN and RW with one chain in one dimension;
 * PSRF with the fewest chains it accepts (P = 2) in one dimension;
 * a twisted target of odd dimension (d = 41: twisted rows 1 and 3, the last
-  row unpaired).
+  row unpaired), and per-chain factors (M = 2) on a twisted target.
 """
 import numpy as np
 import pytest
@@ -141,3 +141,21 @@ def test_twisted_target_odd_dimension():
     o.Z = od.whiten(o.A, o.x_ref, o.X)
     total = run_parity(s, o, d, P, n_lag, 3, 3, adopt_shared=True)
     print(f"\n[twisted d=41] parity, {total} accepted", flush=True)
+
+
+def test_local_global_on_a_twisted_target():
+    # per-chain factors (M = 2) with the non-Gaussian pi_6 target and inflation
+    d, P, n_lag, M = 40, 6, 10, 2
+    t = synth.twisted_target(d, 11, 2.0)
+    x0 = synth.twisted_exact_draws(t, P, 12)
+    s = diam.Sampler(diam.make_config(d, P, n_lag, "fp64", beta=0.4, alpha=1.3, seed=5, M=M), dev(t.mu), dev(t.R),
+                     dev(x0.T), twist=dev(t.c))
+    o = od.DiamOracle(lambda X: ot.twisted_logpdf(t.R, t.mu, t.c, X), d, P, n_lag, 0.4, alpha=1.3, X=x0, M=M)
+    S0, m0 = synth.twisted_warm_moments(t)
+    assert s.seed_moments(dev(S0), dev(m0), 2 * P * n_lag)[0] == diam.OK
+    assert o.seed_moments(S0, m0, 2 * P * n_lag) == od.OK
+    o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()
+    o.Z = od.whiten(o.A, o.x_ref, o.X)
+    total = run_parity(s, o, d, P, n_lag, 5, 4, adopt_shared=True)
+    print(f"\n[M=2 twisted d={d}] parity, {total} accepted", flush=True)
+    assert total > 0
