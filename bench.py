@@ -33,7 +33,7 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of the target kernels from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE runs scaled by a device copy's counters (see profiles/); a
 # kernel missing here has changed since its counters were taken.
-TRAFFIC = {"k_tgt_s3": 188.1e6}   # profiles/hbm_traffic_k_tgt_s3_d4096_P256.md (d=4096, P=256)
+TRAFFIC = {"k_tgt_s3": 187.3e6}   # profiles/hbm_traffic_k_tgt_s3_d4096_P256.md (d=4096, P=256)
 
 
 def log(msg):
