@@ -285,3 +285,28 @@ def test_delayed_acceptance_biased_surrogate_is_exact():
     # the biased first stage does reject, and the second stage repairs it
     assert o.n_accepted.sum() < passed < n_w * n_lag * P
     _moment_check(t, X)
+
+
+def test_he_init_scales_by_fan_in():
+    """He-normal initialisation (He et al. 2015): weights of the layer from
+    fan_in to fan_out inputs are N(0, 2 / fan_in), stored fan_out x fan_in,
+    and biases start at zero.  Layers with fan_in != fan_out make a fan-out
+    scale (or a transposed shape) fail; each variance is tested against a
+    chi-square band of 5 standard deviations, each mean at 5 standard errors."""
+    layers = (512, 256, 64, 1)
+    params = om.he_init(11, layers)
+    assert len(params) == 2 * (len(layers) - 1)
+    for k, (fi, fo) in enumerate(zip(layers[:-1], layers[1:])):
+        W, b = params[2 * k], params[2 * k + 1]
+        assert W.shape == (fo, fi) and b.shape == (fo,)
+        assert np.array_equal(b, np.zeros(fo))
+        n = W.size
+        var = 2.0 / fi
+        s2 = float(np.mean(W * W))                     # the mean is known to be 0
+        assert abs(s2 / var - 1.0) <= 5.0 * math.sqrt(2.0 / n), (k, s2, var)
+        assert abs(W.mean()) <= 5.0 * math.sqrt(var / n), (k, W.mean())
+    # the default network is the 512-256-256-1 surrogate
+    assert [p.shape for p in om.he_init(0)] == [(256, 512), (256,), (256, 256), (256,), (1, 256), (1,)]
+    # reproducible from the seed, different across seeds
+    assert all(np.array_equal(a, b) for a, b in zip(om.he_init(5, layers), om.he_init(5, layers)))
+    assert not np.array_equal(om.he_init(5, layers)[0], om.he_init(6, layers)[0])
