@@ -18,6 +18,7 @@ from oracle import diam as od
 from oracle import psrf as op
 from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
+from tests.gpu_parity import assert_few_forced, oracle_follow
 
 
 def dev(a, dtype=torch.float64):
@@ -33,23 +34,19 @@ def rel(a, b):
 
 
 def run_parity(s, o, d, P, n_lag, windows, seed, adopt_shared, tie=1e-9):
-    """Windows of decision parity; after each update the oracle takes the
-    GPU's factors (independent FP64 roundings).  Returns accepted count."""
+    """Windows of decision parity (the oracle following the GPU through
+    near-ties); after each update the oracle takes the GPU's factors
+    (independent FP64 roundings).  Returns the accepted count."""
     rng = np.random.default_rng(seed)
-    total = 0
+    total = forced = 0
     for k in range(windows):
         W = rng.standard_normal((n_lag, P, d))
         U = synth.draw_uniforms(P, n_lag, 300 + k + 17 * seed)
         s.step_batch(n_lag, dev(W), dev(U))
         acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
         la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
-        for q in range(n_lag):
-            acc_o, la_o = o.step(W[q].T, U[q])
-            if np.any(np.abs(la_o - np.log(U[q])) < tie):
-                return total
-            assert np.array_equal(acc_g[q], acc_o), (k, q)
-            assert np.max(np.abs(la_g[q] - la_o)) <= tie, (k, q)
-            total += int(acc_o.sum())
+        a, f = oracle_follow(o, W, U, acc_g, la_g, tie, where=f"d={d} P={P} window {k}")
+        total, forced = total + a, forced + f
         assert rel(host(s.get_f64(diam.F_X, (P, d))).T, o.X) <= 1e-12, k
         s.merge_moments()
         o.merge_moments()
@@ -66,6 +63,9 @@ def run_parity(s, o, d, P, n_lag, windows, seed, adopt_shared, tie=1e-9):
             assert rel(L, o.A) <= 1e-10
             o.A = L.copy()
             o.Z = od.whiten(o.A, o.x_ref, o.X)
+    print(f"\n  compared {windows} windows of {n_lag} steps x {P} chains, each merged and updated; "
+          f"{forced} forced near-ties", flush=True)
+    assert_few_forced(forced, windows * n_lag * P)
     return total
 
 
@@ -141,6 +141,7 @@ def test_twisted_target_odd_dimension():
     o.Z = od.whiten(o.A, o.x_ref, o.X)
     total = run_parity(s, o, d, P, n_lag, 3, 3, adopt_shared=True)
     print(f"\n[twisted d=41] parity, {total} accepted", flush=True)
+    assert total > 0
 
 
 def test_local_global_on_a_twisted_target():

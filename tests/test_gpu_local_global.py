@@ -1,11 +1,11 @@
 """Local-global logistics with M > 1 intervals per batch (Section 2.4.1) on
 the GPU path, FP64, against the oracle.
 
-* Decision for decision and log alpha over two batches and the start of a
-  third (M = 3), at a size that fills whole tiles and at a ragged one: after
-  every interval the per-chain factors and pivots (eqs. mom2pg, mom1pg,
-  cov2pg) and, after every M-th, the global moments (eqs. mom2g, mom1g)
-  match the oracle's.
+* Decision for decision (the oracle following the GPU through near-ties) and
+  log alpha over two batches and the start of a third (M = 3), at a size
+  that fills whole tiles and at a ragged one: after every interval the
+  per-chain factors and pivots (eqs. mom2pg, mom1pg, cov2pg) and, after
+  every M-th, the global moments (eqs. mom2g, mom1g) match the oracle's.
 * The sampler with M = 4 keeps a Gaussian's moments within 4 MC standard
   errors.
 """
@@ -21,6 +21,7 @@ from oracle import diam as od
 from oracle import ess as oe
 from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
+from tests.gpu_parity import assert_few_forced, oracle_follow
 
 
 def dev(a, dtype=torch.float64):
@@ -39,9 +40,9 @@ def rel(a, b):
 def test_local_global_decision_parity(d, P, cold):
     # cold: no seeded moments, pi_2 (on which A = I accepts); the first local
     # updates factor rank-deficient chain covariances (10 states in d = 40)
-    # through the jitter rule, after which the conditioning ends the comparison
-    # at a near-tie (a chain from the identity never fills the missing
-    # directions: the cold-start degeneracy)
+    # through the jitter rule, and the jittered factors are ill-conditioned
+    # (a chain from the identity never fills the missing directions: the
+    # cold-start degeneracy), which widens the log alpha tolerance below
     n_lag, M, intervals = 10, 3, 7
     t = synth.paper_gaussian("pi2", d, 7) if cold else synth.gaussian_target(d, 7)
     x0 = synth.gaussian_exact_draws(t, P, 8)
@@ -56,25 +57,24 @@ def test_local_global_decision_parity(d, P, cold):
         o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()    # the GPU's factor (independent FP64 roundings)
         o.Z = od.whiten(o.A, o.x_ref, o.X)
     jitters = []
-    tie = 1e-9        # near-tie threshold and log alpha tolerance, max(1e-9, 10 kappa(C) u d)
+    # near-tie threshold and log alpha tolerance.  Both sides use the same
+    # factors (the oracle adopts the GPU's after every update), but the oracle
+    # computes z' by a triangular solve (the plain definition) where the GPU
+    # runs the recurrence rho z + beta alpha W; the two differ by about
+    # kappa(L) u relative, which |z|^2 (about d at equilibrium) carries into
+    # log alpha: max(1e-9, 10 kappa(L) u max(d, |z|^2)), the fixed 1e-9 while
+    # the factors are well conditioned (the warm cases throughout)
+    tie = 1e-9
     rng = np.random.default_rng(9)
-    total = 0
+    total = forced = 0
     for k in range(intervals):
         W = rng.standard_normal((n_lag, P, d))
         U = synth.draw_uniforms(P, n_lag, 70 + k)
         s.step_batch(n_lag, dev(W), dev(U))
         acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
         la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
-        for q in range(n_lag):
-            acc_o, la_o = o.step(W[q].T, U[q])
-            if np.any(np.abs(la_o - np.log(U[q])) < tie):
-                assert not cold or (k > 0 and jitters[0] >= 0), jitters    # the jitter path was reached
-                print(f"\n[M={M} d={d}] near-tie at interval {k} step {q}: parity ends there, jitter levels {jitters}",
-                      flush=True)
-                return
-            assert np.array_equal(acc_g[q], acc_o), (k, q)
-            assert np.max(np.abs(la_g[q] - la_o)) <= tie, (k, q, np.max(np.abs(la_g[q] - la_o)), tie)
-            total += int(acc_o.sum())
+        a, f = oracle_follow(o, W, U, acc_g, la_g, tie, where=f"M={M} d={d} interval {k}")
+        total, forced = total + a, forced + f
         X = host(s.get_f64(diam.F_X, (P, d))).T
         assert rel(X, o.X) <= 1e-12, k
         s.merge_moments()
@@ -95,8 +95,8 @@ def test_local_global_decision_parity(d, P, cold):
             kap = 1.0
             for p in range(P):
                 assert rel(Lp[p] @ Lp[p].T, o.Ap[p] @ o.Ap[p].T) <= 1e-11, (k, p)
-                kp = np.linalg.cond(Lp[p]) ** 2
-                if kp < 1e8:
+                kp = np.linalg.cond(Lp[p])
+                if kp < 1e4:
                     assert rel(Lp[p], o.Ap[p]) <= 1e-9, (k, p, rel(Lp[p], o.Ap[p]))
                 kap = max(kap, kp)
             assert rel(xrp, o.xrp) <= 1e-12, k
@@ -106,14 +106,22 @@ def test_local_global_decision_parity(d, P, cold):
         else:
             L = host(s.get_f64(diam.F_L, (d, d))).T
             assert rel(L @ L.T, o.A @ o.A.T) <= 1e-11, k
-            kap = np.linalg.cond(L) ** 2
-            if kap < 1e8:
+            kap = np.linalg.cond(L)
+            if kap < 1e4:
                 assert rel(L, o.A) <= 1e-9, k
             o.A = L.copy()
             o.Z = od.whiten(o.A, o.x_ref, o.X)
-        tie = max(1e-9, 10 * kap * np.finfo(float).eps * d)
-    print(f"\n[M={M} d={d} P={P}{' cold' if cold else ''}] {intervals} intervals decision-for-decision, "
-          f"{total} accepted of {intervals * n_lag * P}, jitter levels {jitters}", flush=True)
+        zq = float(np.max(np.sum(o.Z * o.Z, axis=0)))
+        tie = max(1e-9, 10 * kap * np.finfo(float).eps * max(d, zq))
+        if not cold:
+            assert tie == 1e-9, (k, kap)
+    if cold:
+        assert jitters[0] >= 0, jitters                   # the jitter path was reached
+    print(f"\n[M={M} d={d} P={P}{' cold' if cold else ''}] compared {intervals} intervals decision-for-decision, "
+          f"each merged and refactorised: {total} accepted of {intervals * n_lag * P}, {forced} forced near-ties, "
+          f"jitter levels {jitters}", flush=True)
+    assert_few_forced(forced, intervals * n_lag * P)
+    assert total > 0
 
 
 def test_local_global_moments_within_4se():

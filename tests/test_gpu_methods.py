@@ -1,7 +1,8 @@
 """The other proposal families of Section 2.3 on the GPU path: adaptive
 Metropolis, pCN and the random walk, through the same kernels.
 
-* FP64 against the oracle, decision for decision, over several windows with
+* FP64 against the oracle, decision for decision (the oracle following the
+  GPU through near-ties), over several windows with
   the step-size adaptation on (the bands of Section 3.2: 0.1 - 0.3 for AM and
   RW, 0.3 - 0.5 for pCN), at a size that fills whole tiles and at a ragged
   one; pCN also with a prior factor set by a warm start.
@@ -26,6 +27,7 @@ from oracle import diam as od
 from oracle import ess as oe
 from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
+from tests.gpu_parity import assert_few_forced, oracle_follow
 
 BANDS = {"diam": (0.3, 0.5), "am": (0.1, 0.3), "pcn": (0.3, 0.5), "rw": (0.1, 0.3)}
 
@@ -62,20 +64,15 @@ def test_family_decision_parity(prop, d, prior):
         o.Z = od.whiten(o.A, o.x_ref, o.X)
     L0 = host(s.get_f64(diam.F_L, (d, d)))
     rng = np.random.default_rng(7)
-    total = 0
+    total = forced = 0
     for w in range(windows):
         W = rng.standard_normal((n_lag, P, d))
         U = synth.draw_uniforms(P, n_lag, 60 + w)
         s.step_batch(n_lag, dev(W), dev(U))
         acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
         la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
-        for k in range(n_lag):
-            acc_o, la_o = o.step(W[k].T, U[k])
-            if np.any(np.abs(la_o - np.log(U[k])) < 1e-9):
-                return                                       # near-tie: parity ends here
-            assert np.array_equal(acc_g[k], acc_o), (w, k)
-            assert np.max(np.abs(la_g[k] - la_o)) <= 1e-9, (w, k, np.max(np.abs(la_g[k] - la_o)))
-            total += int(acc_o.sum())
+        a, f = oracle_follow(o, W, U, acc_g, la_g, 1e-9, where=f"{prop} d={d} window {w}")
+        total, forced = total + a, forced + f
         X = host(s.get_f64(diam.F_X, (P, d))).T
         assert np.linalg.norm(X - o.X) <= 1e-12 * np.linalg.norm(o.X)
         s.merge_moments()
@@ -90,8 +87,11 @@ def test_family_decision_parity(prop, d, prior):
         else:
             assert j == -1 and np.array_equal(L, L0)         # fixed factor
             assert np.array_equal(host(s.get_f64(diam.F_XREF, (d,))), o.x_ref)
-    print(f"\n[{prop} d={d}{' prior' if prior else ''}] {windows} windows decision-for-decision, "
-          f"{total} accepted of {windows * n_lag * P}, beta {o.beta:.4f}", flush=True)
+    print(f"\n[{prop} d={d}{' prior' if prior else ''}] compared {windows} windows decision-for-decision, each "
+          f"merged and updated: {total} accepted of {windows * n_lag * P}, {forced} forced near-ties, "
+          f"beta {o.beta:.4f}", flush=True)
+    assert_few_forced(forced, windows * n_lag * P)
+    assert total > 0
 
 
 @pytest.mark.parametrize("prop", ["am", "pcn", "rw"])

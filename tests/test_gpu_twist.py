@@ -1,8 +1,9 @@
 """Twisted Gaussian targets (Section 3.1's pi_5 / pi_6) on the GPU.
 
 * FP64 path against the oracle on pi_6 (b = 2) with an inflated proposal
-  (alpha = 1.3): log pi at the start, then decision parity, states, merged
-  moments and factor over several windows.
+  (alpha = 1.3): log pi at the start, then decision parity (the oracle
+  following the GPU through near-ties), log alpha, states, merged moments and
+  factor over several windows.
 * FP32 and mixed paths: log pi at the start against the FP64 definition, with
   a twist weight on every odd row so that every tile (and, in the mixed form,
   both split-target tile shapes) applies the pairing.
@@ -22,6 +23,7 @@ from oracle import diam as od
 from oracle import ess as oe
 from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
+from tests.gpu_parity import assert_few_forced, oracle_follow
 
 
 def dev(a, dtype=torch.float64):
@@ -51,19 +53,18 @@ def test_fp64_twisted_decision_parity(d):
     assert o.seed_moments(S0, m0, 10 * P * n_lag) == od.OK
     lp = host(s.get_f64(diam.F_LOGP, (P,)))
     np.testing.assert_allclose(lp, o.lp, rtol=1e-12, atol=1e-12)
+    o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()       # the GPU's factor (independent FP64 roundings)
+    o.Z = od.whiten(o.A, o.x_ref, o.X)
     rng = np.random.default_rng(3)
-    total = 0
+    total = forced = 0
     for w in range(3):
         W = rng.standard_normal((n_lag, P, d))
         U = synth.draw_uniforms(P, n_lag, 40 + w)
         s.step_batch(n_lag, dev(W), dev(U))
         acc_g = host(s.get(diam.F_ACC)).reshape(n_lag, P).astype(bool)
-        for k in range(n_lag):
-            acc_o, la_o = o.step(W[k].T, U[k])
-            if np.any(np.abs(la_o - np.log(U[k])) < 1e-9):
-                return                                   # near-tie: parity ends here
-            assert np.array_equal(acc_g[k], acc_o), (w, k)
-            total += int(acc_o.sum())
+        la_g = host(s.get_f64(diam.F_LA, (n_lag, P)))
+        a, f = oracle_follow(o, W, U, acc_g, la_g, 1e-9, where=f"twisted d={d} window {w}")
+        total, forced = total + a, forced + f
         X = host(s.get_f64(diam.F_X, (P, d))).T
         assert np.linalg.norm(X - o.X) <= 1e-12 * np.linalg.norm(o.X)
         s.merge_moments()
@@ -72,8 +73,10 @@ def test_fp64_twisted_decision_parity(d):
         assert o.update_proposal() == od.OK
         o.A = host(s.get_f64(diam.F_L, (d, d))).T.copy()   # adopt the GPU's factor (independent FP64 roundings)
         o.Z = od.whiten(o.A, o.x_ref, o.X)
-    print(f"\n[fp64 twisted d={d}] 3 windows decision-for-decision, {total} accepted of {3 * n_lag * P}",
-          flush=True)
+    print(f"\n[fp64 twisted d={d}] compared 3 windows decision-for-decision, each merged and refactorised: "
+          f"{total} accepted of {3 * n_lag * P}, {forced} forced near-ties", flush=True)
+    assert_few_forced(forced, 3 * n_lag * P)
+    assert total > 0
 
 
 @pytest.mark.parametrize("prec,d,P", [("fp32", 130, 16), ("mixed", 128, 64), ("mixed", 256, 128)])
