@@ -17,6 +17,7 @@ by one against FP64 recomputations on the host:
     states, read after every step;
   * the factor against numpy's Cholesky of the GPU's own moments;
   * the PSRF of the window on the sampled coordinates against the oracle.
+The plain FP64 path gets the same checks at the same size (FP64 bounds).
 The logistic-regression posterior of the learned form at its full size
 (n = 200000, d = 512, P = 128) gets the same per-chain checks of log pi and
 of one step.
@@ -159,6 +160,106 @@ def test_full_size_window_against_fp64_recomputation(setup):
     assert eL < 1e-4
     nacc = int(s.get(diam.F_NACC).view(torch.int32).sum())
     assert nacc > 0.5 * n
+
+
+def test_full_size_fp64_window_against_fp64_recomputation(setup):
+    """The plain FP64 path at the benchmark size (the denominator of the
+    mixed form's speed-up): internal Philox normals and uniforms, the FP64
+    proposal and target contractions, one window of n_lag steps in single-step
+    calls, the merge and the refactorisation.  Checks against FP64
+    recomputations on the host: log pi of sampled chains at the start; Xi
+    columns, log alpha and decisions of the first step; the window's
+    contribution to the merged moments (mean, 64 x 64 block of the raw second
+    moment) against FP64 sums of the visited states; the factor against
+    numpy's Cholesky of the GPU's own moments; z of sampled chains against a
+    triangular solve with that factor."""
+    t, x0, _, N0 = setup
+    cfg = diam.make_config(D, P, NL, "fp64", beta=BETA, seed=4321)
+    s = diam.Sampler(cfg, dev(t.mu), dev(t.R), dev(x0.T))
+    S0, m0 = synth.gaussian_warm_moments(t)
+    st, j = s.seed_moments(dev(S0), dev(m0), N0)
+    assert st == diam.OK and j == -1
+    J = [0, 1, 97, 200, 255]
+    rng = np.random.default_rng(6)
+    I = np.sort(rng.choice(D, 64, replace=False))
+    It = torch.as_tensor(I, device="cuda")
+    u = np.finfo(float).eps
+
+    lp = host(s.get_f64(diam.F_LOGP, (P,)))
+    for j in J:
+        ref = logpi(t, x0[:, j])
+        assert abs(lp[j] - ref) <= 1e-11 * (1 + abs(ref)), (j, lp[j], ref)
+    log(f"fp64 d={D}: log pi at the start matches FP64 on chains {J}")
+    L = host(s.get_f64(diam.F_L, (D, D))).T
+    xr = host(s.get_f64(diam.F_XREF, (D,)))
+    Z = host(s.get_f64(diam.F_Z, (P, D)))
+    zq = host(s.get_f64(diam.F_ZQ, (P,)))
+    S_before = s.get_f64(diam.F_S, (D, D))[It][:, It].clone()
+    m_before = s.get_f64(diam.F_M, (D,)).clone()
+    xsum = torch.zeros(D, dtype=torch.float64, device="cuda")
+    sblk = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    ties = 0
+    for k in range(NL):
+        s.step_batch(1)
+        if k == 0:
+            W = host(s.get_f64(diam.F_W, (P, D)))
+            Xi = host(s.get_f64(diam.F_XI, (P, D)))
+            U = host(s.get_f64(diam.F_U, (P,)))
+            la = host(s.get_f64(diam.F_LA, (P,)))
+            acc = host(s.get(diam.F_ACC)).astype(bool)
+            for j in J:
+                xi_ref = BETA * (L @ W[j])
+                e = np.linalg.norm(Xi[j] - xi_ref) / np.linalg.norm(xi_ref)
+                assert e < 1e-13, (j, e)
+                xp = xr + RHO * (x0[:, j] - xr) + Xi[j]
+                zp = RHO * Z[j] + BETA * W[j]
+                la_ref = (logpi(t, xp) - lp[j]) + 0.5 * (float(zp @ zp) - zq[j])
+                tol = 1e-11 * (1 + abs(lp[j]))
+                assert abs(la[j] - la_ref) <= tol, (j, la[j], la_ref)
+                if abs(la_ref - np.log(U[j])) > tol:
+                    assert acc[j] == (np.log(U[j]) < la_ref), j
+                else:
+                    ties += 1
+            log(f"fp64 step 1: Xi columns, log alpha and decisions match FP64 on chains {J} ({ties} near-ties)")
+        X = s.get_f64(diam.F_X, (P, D))
+        xsum += X.sum(0)
+        XI = X[:, It]
+        sblk += XI.T @ XI
+    n = P * NL
+    s.merge_moments()
+    S_after = s.get_f64(diam.F_S, (D, D))[It][:, It]
+    m_after = s.get_f64(diam.F_M, (D,))
+    Sw = host(((N0 + n) * S_after - N0 * S_before) / n)
+    mw = host(((N0 + n) * m_after - N0 * m_before) / n)
+    eS = np.linalg.norm(Sw - host(sblk / n)) / np.linalg.norm(host(sblk / n))
+    em = np.linalg.norm(mw - host(xsum / n)) / np.linalg.norm(host(xsum / n))
+    log(f"fp64 window contribution to the merge: S block rel {eS:.2e}, mean rel {em:.2e}")
+    # recovering the window's share from (N0 + n) S_after - N0 S_before
+    # multiplies the FP64 rounding of S by N0 / n = 196
+    assert eS < 1e-11 and em < 1e-11
+    st, jit = s.update_proposal()
+    assert st == diam.OK and jit == -1
+    Sg = host(s.get_f64(diam.F_S, (D, D))).T
+    mg = host(s.get_f64(diam.F_M, (D,)))
+    Lg = host(s.get_f64(diam.F_L, (D, D))).T
+    L_ref = np.linalg.cholesky(Sg - np.outer(mg, mg))
+    eL = np.linalg.norm(Lg - L_ref) / np.linalg.norm(L_ref)
+    # two FP64 Cholesky factorisations of C agree to about kappa(C) u, kappa(C) ~ d^2
+    tolL = 100.0 * D * D * u
+    log(f"fp64 factor vs numpy Cholesky of the GPU's moments: rel {eL:.2e} (bound {tolL:.1e})")
+    assert eL < tolL
+    assert np.array_equal(host(s.get_f64(diam.F_XREF, (D,))), mg)
+    Xg = host(s.get_f64(diam.F_X, (P, D)))
+    Zg = host(s.get_f64(diam.F_Z, (P, D)))
+    import scipy.linalg as sla
+    for j in J:
+        z_ref = sla.solve_triangular(Lg, Xg[j] - mg, lower=True)
+        ez = np.linalg.norm(Zg[j] - z_ref) / np.linalg.norm(z_ref)
+        assert ez < 100.0 * D * u, (j, ez)
+    nacc = int(s.get(diam.F_NACC).view(torch.int32).sum())
+    log(f"fp64 window: acceptance {nacc / n:.3f}, z of chains {J} match the triangular solve")
+    assert nacc > 0.5 * n
+    s.close()
 
 
 def test_full_size_window_in_one_call(setup):

@@ -26,6 +26,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle import diam as od
+from oracle import ess as oe
 from oracle import mlp as om
 from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
@@ -384,3 +385,105 @@ def test_learned_form_state_errors():
     with pytest.raises(diam.DiamError) as e:            # more pairs than reserved
         pr2.s.surrogate_train(dev(X.T), dev(lp), steps=1)
     assert e.value.status == diam.E_ARG
+
+
+def _run_logistic(data, mode, C, P, n_lag, beta, windows, use_da, n_pairs=4096, train_steps=1500):
+    """Warm-started sampler on the logistic posterior; `windows` traced
+    windows after a collection phase of n_pairs states (which, with use_da,
+    train the surrogate before delayed acceptance is switched on).  Returns
+    the traces (steps x 3 x P: log pi, v_max^T x, v_min^T x), the seconds of
+    the traced windows, the accepted count and the stage-1 survivors."""
+    import time
+    d = data.A.shape[1]
+    rng = np.random.default_rng(17)
+    x0 = mode[:, None] + np.linalg.cholesky(C) @ rng.standard_normal((d, P))
+    cfg = diam.make_config(d, P, n_lag, "fp32", beta=beta, seed=91, surrogate=2 if use_da else 0,
+                           train_max=n_pairs)
+    s = diam.Sampler(cfg, None, None, dev(x0.T), A=dev(data.A, torch.float32), y=dev(data.y, torch.float32),
+                     prior_var=data.prior_var)
+    assert s.seed_moments(dev(C + np.outer(mode, mode)), dev(mode), 10 * P * n_lag)[0] == diam.OK
+    collect = -(-n_pairs // P)
+    Xtr = torch.empty((collect * P, d), dtype=torch.float64, device="cuda")
+    ltr = torch.empty(collect * P, dtype=torch.float64, device="cuda")
+    for k in range(collect):                                  # identical in both runs
+        s.step_batch(1)
+        Xtr[k * P:(k + 1) * P] = s.get_f64(diam.F_X, (P, d))
+        ltr[k * P:(k + 1) * P] = s.get_f64(diam.F_LOGP, (P,))
+        if s.stats()["steps_in_window"] == n_lag:
+            s.merge_moments()
+            assert s.update_proposal()[0] == diam.OK
+    rest = n_lag - s.stats()["steps_in_window"]
+    if rest < n_lag:
+        s.step_batch(rest)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+    loss = None
+    if use_da:
+        loss = s.surrogate_train(Xtr[:n_pairs], ltr[:n_pairs], steps=train_steps, batch=256, lr=1e-3, seed=5)
+        s.set_delayed_acceptance(True)
+    ev, V = np.linalg.eigh(C)
+    proj = dev(np.stack([V[:, -1], V[:, 0]]))
+    trace = torch.empty((windows * n_lag, 3, P), dtype=torch.float64, device="cuda")
+    s.set_trace(proj, trace)
+    nacc0 = int(s.get(diam.F_NACC).view(torch.int32).sum())
+    npass0 = int(s.get(diam.F_NPASS).view(torch.int32).sum()) if use_da else 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(windows):
+        s.step_batch(n_lag)
+        s.merge_moments()
+        assert s.update_proposal()[0] == diam.OK
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    nacc = int(s.get(diam.F_NACC).view(torch.int32).sum()) - nacc0
+    npass = (int(s.get(diam.F_NPASS).view(torch.int32).sum()) - npass0) if use_da else windows * n_lag * P
+    tr = host(trace)
+    s.close()
+    return tr, T, nacc, npass, loss
+
+
+def test_delayed_acceptance_matches_plain_posterior_and_reports_gain():
+    """Delayed acceptance with the trained surrogate against the plain
+    sampler on the same logistic-regression posterior (n = 20000, d = 64,
+    P = 128, beta = 1, Laplace warm start): the posterior mean of log pi, the
+    means and variances of v_max^T x and v_min^T x agree within 4 combined
+    Monte Carlo standard errors (the plain FP32 sampler is the judge).  The
+    test also measures what the network gains: the share of exact target
+    evaluations stage 1 saves, the ESS per exact evaluation and the ESS per
+    second of delayed acceptance relative to the plain sampler."""
+    n, d, P, n_lag, windows = 20000, 64, 128, 100, 30
+    data = synth.logreg_data(n=n, d=d, seed=4)
+    mode, C = synth.logreg_laplace(data)
+    res = {}
+    for use_da in (False, True):
+        res[use_da] = _run_logistic(data, mode, C, P, n_lag, 1.0, windows, use_da)
+    worst = 0.0
+    report = []
+    ess = {}
+    for use_da in (False, True):
+        tr = res[use_da][0]
+        ess[use_da] = min(oe.ess_chains(tr[:, f, :]) for f in range(3))
+    for f, name in enumerate(("log pi", "v_max^T x", "v_min^T x")):
+        stats = []
+        for use_da in (False, True):
+            x = res[use_da][0][:, f, :]
+            sq = (x - x.mean()) ** 2
+            stats.append(((x.mean(), x.std() / math.sqrt(oe.ess_chains(x))),
+                          (sq.mean(), sq.std() / math.sqrt(oe.ess_chains(sq)))))
+        for k in ((0,) if f == 0 else (0, 1)):
+            (a, sa), (b, sb) = stats[0][k], stats[1][k]
+            z = (b - a) / math.sqrt(sa * sa + sb * sb)
+            worst = max(worst, abs(z))
+            report.append(f"{name} {'mean' if k == 0 else 'variance'} z {z:+.2f}")
+    steps = windows * n_lag * P
+    plain, da = res[False], res[True]
+    saved = 1.0 - da[3] / steps
+    per_eval = (ess[True] / da[3]) / (ess[False] / plain[3])
+    per_s = (ess[True] / da[1]) / (ess[False] / plain[1])
+    log(f"delayed acceptance vs plain (logistic n={n}, d={d}, P={P}, beta=1): " + ", ".join(report)
+        + f"; acceptance plain {plain[2] / steps:.3f}, DA {da[2] / steps:.3f}, stage-1 pass {da[3] / steps:.3f}; "
+          f"surrogate loss {da[4]:.4f}; the network saves {100 * saved:.1f} % of exact evaluations, "
+          f"ESS per exact evaluation x{per_eval:.2f}, ESS/s x{per_s:.2f} of the plain sampler")
+    assert worst < 4.0
+    assert 0.0 < saved < 1.0                                  # stage 1 screens some proposals, not all
+    assert da[2] > 0.2 * steps
