@@ -388,6 +388,20 @@ int diam_batch_set_tiles(diam_batch* b, int32_t choice);
 int diam_batch_autotune(diam_batch* b, int32_t reps, int32_t* choice, double* us);
 /* Graph capture of the window on (default) or off (eager launches). */
 int diam_batch_set_graph(diam_batch* b, int32_t on);
+/* The n_lag-step loop of every window as one persistent launch (on != 0)
+ * instead of three grouped launches per step (default off).  A fixed grid of
+ * co-resident workgroups takes (problem, phase, tile) items of the loop from
+ * a device queue in order; each problem advances through its own phases
+ * (target tiles, decisions, update chunks) as soon as their inputs are
+ * ready, without a device-wide barrier between steps.  Same kernels bodies
+ * as the grouped launches with the default tile shape, so results are
+ * bitwise those of the graph or eager windows (and of separate samplers).
+ * Needs every d <= 4096 (else DIAM_E_ARG); sets the default target tile
+ * shape, after which diam_batch_set_tiles and diam_batch_autotune return
+ * DIAM_E_STATE.  Every wait inside the loop is bounded: a wait that gives up
+ * makes the loop stop and diam_batch_window return DIAM_E_HIP (the window's
+ * results are then invalid).  Works with and without graph capture. */
+int diam_batch_set_persistent(diam_batch* b, int32_t on);
 /* Per-problem fields at a window boundary: DIAM_F_X, Z, LOGP, ZQ, XREF, L, S,
  * M, LA, ACC (last window, n_lag x P), NACC, W (last window's normals, ld x
  * P n_lag f32 with ld = d rounded up to a multiple of 4; rows >= d unused),

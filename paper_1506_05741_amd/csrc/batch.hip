@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -56,7 +57,7 @@ struct PLay {
 struct BLay {
   std::vector<PLay> p;
   std::vector<size_t> Woff;  // offset of each problem's normals inside W_all (floats)
-  size_t W_all, U_all, info, win_ctr, N, err, probs, tiles, total;
+  size_t W_all, U_all, info, win_ctr, N, err, probs, tiles, pitems, pstep, pctl, total;
   long nW, nU;
   long ntiles;
 };
@@ -66,6 +67,8 @@ struct Tiles {
   std::vector<BTile> all;
   Seg tgt[dk::G_TGT_CONFIGS], decide, step, trigemm, syrk, rowsum, dd, d1, dp, colnorm, triinv;
   std::vector<Seg> cdiag, cpanel, cupd, tdiag, tupd;
+  std::vector<dk::PItem> pitems;  // one step of the persistent loop
+  std::vector<int> pstep;         // items of problem g per step
   int max_nb = 0;
   Seg add(const std::vector<BTile>& v) {
     Seg s;
@@ -154,10 +157,28 @@ Tiles build_tiles(const std::vector<int>& dims, int P, int n) {
     T.tdiag.push_back(T.add(td));
     T.tupd.push_back(T.add(tu));
   }
+  // persistent loop: per step the target tiles of every problem (largest
+  // problems first: the longest chains of dependent items start earliest),
+  // then every problem's decisions, then the update chunks
+  std::vector<int> order(G);
+  for (int g = 0; g < G; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dims[x] > dims[y]; });
+  const int pbm = dk::g_tgt_bm(dk::PERSIST_TGT_CFG);
+  std::vector<int> ntg(G);
+  T.pstep.assign(G, 0);
+  for (int g : order) {
+    ntg[g] = cdivh(dims[g], pbm) * cdivh(P, 32);
+    for (int bx = 0; bx < cdivh(dims[g], pbm); ++bx)
+      for (int by = 0; by < cdivh(P, 32); ++by) T.pitems.push_back({0, g, bx, by, 0});
+  }
+  for (int g : order) T.pitems.push_back({1, g, 0, 0, ntg[g]});
+  for (int g : order)
+    for (int ch = 0; ch < dk::step_chunks(dims[g]); ++ch) T.pitems.push_back({2, g, ch, 0, ntg[g] + 1});
+  for (int g = 0; g < G; ++g) T.pstep[g] = ntg[g] + 1 + dk::step_chunks(dims[g]);
   return T;
 }
 
-BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles) {
+BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles, long npitems) {
   BLay L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -182,6 +203,9 @@ BLay make_blay(const std::vector<int>& dims, int P, int n, long ntiles) {
   L.probs = take(sizeof(BProb) * G);
   L.tiles = take(sizeof(BTile) * ntiles);
   L.ntiles = ntiles;
+  L.pitems = take(sizeof(dk::PItem) * npitems);
+  L.pstep = take(sizeof(int) * G);
+  L.pctl = take(sizeof(int) * (G + 1));  // queue position, then the G counters
   for (int g = 0; g < G; ++g) {
     const size_t d = dims[g], dP = d * P, dd = d * d, win = dP * n;
     const int nch = dk::step_chunks(dims[g]);
@@ -280,6 +304,11 @@ struct diam_batch {
   double N;
   int64_t windows, steps;
   int use_graph;
+  int persistent;       // the n_lag step loop as one persistent launch
+  int pgrid;            // its workgroups (co-resident capacity, at most the items of one window)
+  dk::PItem* pitems;
+  int* pstep;
+  int* pctl;
   hipGraph_t graph;
   hipGraphExec_t gexec;
   bool graph_valid;
@@ -302,7 +331,7 @@ extern "C" int diam_batch_workspace_bytes(const diam_batch_config* cfg, const in
   if (!bytes) return bfail(DIAM_E_ARG, "null bytes");
   std::vector<int> dv(dims, dims + cfg->G);
   Tiles T = build_tiles(dv, cfg->P, cfg->n_lag);
-  *bytes = make_blay(dv, cfg->P, cfg->n_lag, (long)T.all.size()).total;
+  *bytes = make_blay(dv, cfg->P, cfg->n_lag, (long)T.all.size(), (long)T.pitems.size()).total;
   return DIAM_OK;
 }
 
@@ -321,7 +350,7 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
   if (!workspace || ((uintptr_t)workspace & 255)) return bfail(DIAM_E_ARG, "workspace null or not 256-byte aligned");
   std::vector<int> dv(dims, dims + cfg->G);
   Tiles T = build_tiles(dv, cfg->P, cfg->n_lag);
-  BLay L = make_blay(dv, cfg->P, cfg->n_lag, (long)T.all.size());
+  BLay L = make_blay(dv, cfg->P, cfg->n_lag, (long)T.all.size(), (long)T.pitems.size());
   if (ws_bytes < L.total) return bfail(DIAM_E_ARG, "workspace too small: %zu < %zu", ws_bytes, L.total);
 
   diam_batch* b = new (std::nothrow) diam_batch();
@@ -365,6 +394,19 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
   b->err = (int*)(w + L.err);
   b->dp = (BProb*)(w + L.probs);
   b->dt = (BTile*)(w + L.tiles);
+  b->pitems = (dk::PItem*)(w + L.pitems);
+  b->pstep = (int*)(w + L.pstep);
+  b->pctl = (int*)(w + L.pctl);
+  b->persistent = 0;
+  {
+    int ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || ncu < 1)
+      ncu = 1;
+    const long cap = (long)dk::g_persist_blocks_per_cu() * ncu;
+    const long items = (long)T.pitems.size() * cfg->n_lag;
+    b->pgrid = (int)std::max(1L, std::min(cap, items));
+  }
   b->hp.resize(b->G);
   for (int g = 0; g < b->G; ++g) {
     const PLay& q = L.p[g];
@@ -410,6 +452,8 @@ extern "C" int diam_batch_init(diam_batch** out, const diam_batch_config* cfg, c
     if (_e != hipSuccess) return fail_init(_e, #expr); \
   } while (0)
   BCHK_INIT(hipMemcpyAsync(b->dt, T.all.data(), sizeof(BTile) * T.all.size(), hipMemcpyHostToDevice, s));
+  BCHK_INIT(hipMemcpyAsync(b->pitems, T.pitems.data(), sizeof(dk::PItem) * T.pitems.size(), hipMemcpyHostToDevice, s));
+  BCHK_INIT(hipMemcpyAsync(b->pstep, T.pstep.data(), sizeof(int) * T.pstep.size(), hipMemcpyHostToDevice, s));
   BCHK_INIT(hipMemcpyAsync(b->dp, b->hp.data(), sizeof(BProb) * b->G, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_bzero, dim3(1), dim3(256), 0, s, (char*)b->win_ctr, 8L);
   hipLaunchKernelGGL(k_bzero, dim3(1), dim3(256), 0, s, (char*)b->Nd, 8L);
@@ -500,6 +544,10 @@ static int retry_failed(diam_batch* b, int32_t* jitter, int* any_fail) {
   return DIAM_OK;
 }
 
+// Polls of a wait in the persistent loop before it gives up (a few seconds;
+// a legitimate wait lasts well under a millisecond).
+constexpr int PERSIST_SPIN_MAX = 4000000;
+
 // One window of every problem on stream s (eager, or while capturing).
 static int enqueue_window(diam_batch* b, hipStream_t s) {
   const int P = b->P, n = b->n;
@@ -519,11 +567,25 @@ static int enqueue_window(diam_batch* b, hipStream_t s) {
   st.err = b->err;
   st.t = -1;
   BCHK(dk::g_step(b->dp, tl(T.decide), T.decide.n, tl(T.step), T.step.n, st, s));
-  const Seg& tg = T.tgt[b->tgt_cfg];
-  for (int t = 0; t < n; ++t) {
-    BCHK(dk::g_tgt(b->tgt_cfg, b->dp, tl(tg), tg.n, P, s));
-    st.t = t;
-    BCHK(dk::g_step(b->dp, tl(T.decide), T.decide.n, tl(T.step), T.step.n, st, s));
+  if (b->persistent) {
+    // the n_lag steps of every problem: one launch over the item queue
+    hipLaunchKernelGGL(k_bzero, dim3(cdivh((long)(b->G + 1) * 4, 256)), dim3(256), 0, s, (char*)b->pctl,
+                       (long)(b->G + 1) * 4);
+    BCHK(hipGetLastError());
+    dk::PCtl ctl;
+    ctl.qctr = b->pctl;
+    ctl.done = b->pctl + 1;
+    ctl.per_step = b->pstep;
+    ctl.err = b->err;
+    ctl.spin_max = PERSIST_SPIN_MAX;
+    BCHK(dk::g_persist(b->dp, b->pitems, (int)T.pitems.size(), st, ctl, b->pgrid, s));
+  } else {
+    const Seg& tg = T.tgt[b->tgt_cfg];
+    for (int t = 0; t < n; ++t) {
+      BCHK(dk::g_tgt(b->tgt_cfg, b->dp, tl(tg), tg.n, P, s));
+      st.t = t;
+      BCHK(dk::g_step(b->dp, tl(T.decide), T.decide.n, tl(T.step), T.step.n, st, s));
+    }
   }
   BCHK(dk::g_scatter(b->dp, tl(T.syrk), T.syrk.n, tl(T.rowsum), T.rowsum.n, (int)K, s));
   BCHK(dk::g_fold(b->dp, tl(T.dd), T.dd.n, tl(T.d1), T.d1.n, b->Nd, (double)K, s));
@@ -597,6 +659,8 @@ extern "C" int diam_batch_window(diam_batch* b, int32_t* jitter) {
   b->steps += b->n;
   if (err) {
     hipLaunchKernelGGL(k_bzero, dim3(1), dim3(256), 0, b->cs, (char*)b->err, 8L);
+    BCHK(hipStreamSynchronize(b->cs));
+    if (err & 2) return bfail(DIAM_E_HIP, "the persistent step loop gave up waiting for an item (window lost)");
     return bfail(DIAM_E_TARGET, "a target log density returned +inf");
   }
   if (any) return bfail(DIAM_E_NOT_PD, "a covariance was not positive definite at any jitter level");
@@ -645,12 +709,32 @@ extern "C" int diam_batch_set_tiles(diam_batch* b, int32_t choice) {
   if (!b) return bfail(DIAM_E_ARG, "null batch");
   if (choice < 0 || choice >= dk::G_TGT_CONFIGS) return bfail(DIAM_E_ARG, "tile choice %d out of range", choice);
   if (choice == b->tgt_cfg) return DIAM_OK;
+  if (b->persistent) return bfail(DIAM_E_STATE, "the persistent loop runs its own tile shape");
   BCHK(hipStreamSynchronize(b->cs));
   b->tgt_cfg = choice;
   set_nrb(b);
   int r = upload_probs(b, b->cs);
   if (r) return r;
   drop_graph(b);
+  return DIAM_OK;
+}
+
+extern "C" int diam_batch_set_persistent(diam_batch* b, int32_t on) {
+  if (!b) return bfail(DIAM_E_ARG, "null batch");
+  if (on) {
+    for (int g = 0; g < b->G; ++g)
+      if (b->dims[g] > 4096)
+        return bfail(DIAM_E_ARG, "the persistent loop takes d <= 4096 (problem %d has d = %d)", g, b->dims[g]);
+    if (b->tgt_cfg != dk::PERSIST_TGT_CFG) {
+      BCHK(hipStreamSynchronize(b->cs));
+      b->tgt_cfg = dk::PERSIST_TGT_CFG;
+      set_nrb(b);
+      int r = upload_probs(b, b->cs);
+      if (r) return r;
+    }
+  }
+  if ((on ? 1 : 0) != b->persistent) drop_graph(b);
+  b->persistent = on ? 1 : 0;
   return DIAM_OK;
 }
 
@@ -667,6 +751,7 @@ extern "C" int diam_batch_set_graph(diam_batch* b, int32_t on) {
 extern "C" int diam_batch_autotune(diam_batch* b, int32_t reps, int32_t* choice, double* us) {
   if (!b) return bfail(DIAM_E_ARG, "null batch");
   if (reps < 1 || reps > 10000) return bfail(DIAM_E_ARG, "reps must lie in [1, 10000]");
+  if (b->persistent) return bfail(DIAM_E_STATE, "the persistent loop runs its own tile shape");
   hipStream_t s = b->cs;
   BCHK(hipEventRecord(b->ev_in, b->user));
   BCHK(hipStreamWaitEvent(s, b->ev_in, 0));

@@ -160,7 +160,11 @@ hipError_t psrf_accumulate(Prec prec, const void* win, int d, int P, int nw, con
                            double* m2, hipStream_t s);
 hipError_t psrf_finalize(const double* mean, const double* m2, int d, int P, double n, double* out, hipStream_t s);
 // Stopping errors (Section 3.3): scratch[0] = |S - m m^T - Sigma|_F / |Sigma|_F,
-// scratch[1] = |m - mu|_2 (0 when mu is null); scratch of moment_err_scratch_bytes().
+// scratch[1] = |m - mu|_2 (0 when mu is null); scratch of moment_err_scratch_bytes():
+// the two results, then 3 partial sums per workgroup of at most MERR_BLOCKS.
+// Every partial is written before it is read: nothing must start at zero.
+constexpr int MERR_BLOCKS = 1024;
+constexpr size_t MERR_SCRATCH_DOUBLES = 2 + 3 * (size_t)MERR_BLOCKS;
 size_t moment_err_scratch_bytes();
 hipError_t moment_error(const double* S, const double* m, const double* Sigma, const double* mu, int d, double* scratch,
                         hipStream_t s);
@@ -199,6 +203,30 @@ struct BStep {
   const double* U;                  // (g n + t) P + p
   int* err;
 };
+// The n_lag step loop of a window as one persistent launch: a fixed grid of
+// workgroups takes items from a device queue in order; an item is one
+// (problem, phase, tile) of one step.  Phases of a step of problem g, each
+// needing all of the previous one: kind 0 target tiles (64-row tile a,
+// 32-chain tile b), kind 1 the decisions of all P chains, kind 2 the update
+// of 128-row chunk a for all P chains.  items[] lists one step (every step
+// runs the same list); problem g's counter done[g] counts its finished items,
+// and an item of step t waits until done[g] >= t * per_step[g] + need.
+struct PItem { int kind, g, a, b, need; };
+struct PCtl {
+  int* qctr;            // next queue position (zero before the launch)
+  int* done;            // G counters (zero before the launch)
+  const int* per_step;  // G: items of problem g per step
+  int* err;             // bit 1 (2) set when a wait gives up after spin_max polls
+  int spin_max;
+};
+constexpr int PERSIST_THREADS = 512;
+// Target tile rows the persistent loop uses (the default tile shape: 64 rows,
+// two k-groups), so the decisions' partial sums fit one wavefront.
+constexpr int PERSIST_TGT_CFG = 2;
+hipError_t g_persist(const BProb* pr, const PItem* items, int nitems, const BStep& st, const PCtl& ctl, int grid,
+                     hipStream_t s);
+// Workgroups of the persistent loop that fit one CU at once.
+int g_persist_blocks_per_cu();
 constexpr int G_TGT_CONFIGS = 5;    // target tile shapes the autotuner chooses from
 int g_tgt_bm(int cfg);
 hipError_t g_tgt(int cfg, const BProb* pr, const BTile* tl, int ntiles, int P, hipStream_t s);

@@ -763,73 +763,166 @@ DEV double readlane_f64(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Lane r holds row r of the block.  Step c: the pivot comes from lane c by
-// readlane, column c of L goes through a double-buffered LDS vector, and
-// every lane applies the rank-1 update to its whole row without per-element
-// masks: entries right of the diagonal collect values that are never read
-// (the broadcast and the stores mask them).  One wavefront does the work and
-// the others of a larger workgroup return at once (the core ends every kernel
-// that calls it), so the LDS exchanges need no workgroup barrier: within the
-// wavefront they run in program order, fenced at wavefront scope (10 % off
-// the factorisation's time against a barrier per step).
-// LDS: two column buffers, the factored block, the reciprocal diagonal.
-constexpr int CHOL_DIAG_LDS = 2 * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB;  // doubles
+// The diagonal block on a workgroup of four wavefronts.  Lane r of every
+// wavefront holds row r; wavefront w holds columns 16 w .. 16 w + 15 of it.
+// Column c is published through a double-buffered LDS vector; after one
+// workgroup barrier every wavefront that owns columns right of c applies the
+// rank-1 update to its part of each row, without per-element masks (entries
+// right of the diagonal collect values that are never read).  Look-ahead: the
+// wavefront owning column c + 1 updates that column first, takes its pivot
+// (from lane c + 1 by readlane) and publishes it before its other updates, so
+// one barrier per column separates consecutive pivots.  The pivot step forms
+// y ~ 1/sqrt(pivot) by the hardware reciprocal square root refined with two
+// Newton-Raphson steps, then L(c, c) = pivot y and L(r, c) = a(r, c) y; a
+// pivot that is not > 0 (or NaN) gives a diagonal that is not > 0.  Each
+// entry of the lower triangle sees the updates in the same order as a
+// right-looking factorisation.  The block inverse is formed as
+// [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1, C^-1]] with 32 x 32 blocks:
+// one wavefront forms A^-1 and C^-1 by substitution (lane c of each half a
+// column), then all four form the two products.
+// LDS: two column buffers, the factored block (whose zero upper-right
+// quarter then holds B A^-1), the reciprocal diagonal, A^-1 and C^-1.
+constexpr int CHOL_DIAG_THREADS = 256;
+constexpr int CHOL_DIAG_LDS = 2 * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB + 2 * 32 * 33;  // doubles
 
-// orders this wavefront's LDS stores before its following LDS loads
-DEV void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// 1/sqrt(x): hardware estimate, then two Newton-Raphson steps
+// y <- y + y (1 - x y^2) / 2 (NaN for x < 0 or NaN, +inf for x = 0)
+DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = __fma_rn(-x * y, y, 1.0);
+    y = __fma_rn(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Column c (0 .. 31) of the inverse of the lower-triangular 32 x 32 block of
+// Ls starting at (o, o), by forward substitution (four partial sums).
+DEV void tri_inverse_col32(const double (*Ls)[CHOL_NB + 1], const double* rdiag, int o, double* x, int c) {
+#pragma unroll
+  for (int rr = 0; rr < 32; ++rr) {
+    double s[4] = {(rr == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < rr; ++q) s[q & 3] = __fma_rn(-Ls[o + rr][o + q], x[q], s[q & 3]);
+    x[rr] = ((s[0] + s[1]) + (s[2] + s[3])) * rdiag[o + rr];
+  }
 }
 
 DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
                         int* __restrict__ info, double* sh) {
+  constexpr int H = CHOL_NB / 4;  // columns per wavefront
   double (*colv)[CHOL_NB] = (double (*)[CHOL_NB])sh;
   double (*Ls)[CHOL_NB + 1] = (double (*)[CHOL_NB + 1])(sh + 2 * CHOL_NB);
   double* rdiag = sh + 2 * CHOL_NB + CHOL_NB * (CHOL_NB + 1);
-  const int r = threadIdx.x;
-  if (r >= CHOL_NB) return;
-  double a[CHOL_NB];
+  double (*Ai)[33] = (double (*)[33])(rdiag + CHOL_NB);
+  double (*Ci)[33] = Ai + 32;
+  const int t = threadIdx.x, r = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  double a[H];
 #pragma unroll
-  for (int c = 0; c < CHOL_NB; ++c) {
+  for (int k = 0; k < H; ++k) {
+    const int c = w * H + k;
     double v = 0.0;
     if (r < jn && c < jn) {
       if (c <= r) v = A[(j0 + r) + (long)(j0 + c) * d];
     } else if (c == r) {
       v = 1.0;  // identity padding beyond the matrix edge
     }
-    a[c] = v;
+    a[k] = v;
   }
+  // pivot step of column c by the wavefront holding it (its local column kc)
+  auto pivot = [&](int c, int kc) {
+    const double piv = readlane_f64(a[kc], c);
+    const double y = rsqrt_nr(piv);
+    const double l = (r == c) ? piv * y : a[kc] * y;
+    a[kc] = l;
+    colv[c & 1][r] = (r >= c) ? l : 0.0;
+  };
+  if (w == 0) pivot(0, 0);
 #pragma unroll
   for (int c = 0; c < CHOL_NB; ++c) {
-    const double piv = readlane_f64(a[c], c);
-    const double sq = sqrt(piv);
-    const double l = (r == c) ? sq : a[c] * (1.0 / sq);
-    a[c] = l;
-    colv[c & 1][r] = (r >= c) ? l : 0.0;
-    wave_lds_sync();
+    const int wc = c / H, c1 = c + 1, w1 = c1 / H, k1 = c1 % H;
+    __syncthreads();
+    if (c1 < CHOL_NB && w == w1) {
+      // owner of column c + 1: that column, its pivot, then the rest right of c
+      const double lr = colv[c & 1][r];
+      a[k1] = __fma_rn(-lr, colv[c & 1][w1 * H + k1], a[k1]);
+      pivot(c1, k1);
 #pragma unroll
-    for (int q = c + 1; q < CHOL_NB; ++q) a[q] = __fma_rn(-l, colv[c & 1][q], a[q]);
+      for (int k = (w1 == wc) ? k1 + 1 : 1; k < H; ++k) a[k] = __fma_rn(-lr, colv[c & 1][w1 * H + k], a[k]);
+    } else if (w > wc) {
+      const double lr = colv[c & 1][r];
+#pragma unroll
+      for (int k = 0; k < H; ++k) a[k] = __fma_rn(-lr, colv[c & 1][w * H + k], a[k]);
+    }
   }
-  if (r < jn) {
 #pragma unroll
-    for (int c = 0; c < CHOL_NB; ++c)
-      if (c < jn) A[(j0 + r) + (long)(j0 + c) * d] = (c <= r) ? a[c] : 0.0;
+  for (int k = 0; k < H; ++k) {
+    const int c = w * H + k;
+    if (r < jn && c < jn) A[(j0 + r) + (long)(j0 + c) * d] = (c <= r) ? a[k] : 0.0;
+    Ls[r][c] = (c <= r) ? a[k] : 0.0;
   }
+  __syncthreads();
+  if (w == 0) {
+    // a pivot that is not > 0 (or NaN) leaves a diagonal root that is not > 0,
+    // and every later pivot inherits the failure: the first bad column is the
+    // lowest such lane
+    const double diag = Ls[r][r];
+    const unsigned long long bad = __ballot(r < jn && !(diag > 0.0));
+    if (r == 0 && bad && *info == 0) *info = j0 + __ffsll((long long)bad);
+    rdiag[r] = 1.0 / diag;
+  }
+  __syncthreads();
+  if (w == 0) {
+    // lanes 0 .. 31: column r of A^-1; lanes 32 .. 63: column r - 32 of C^-1
+    const int o = (r < 32) ? 0 : 32, c = r - o;
+    double x[32];
+    tri_inverse_col32(Ls, rdiag, o, x, c);
+    double (*D)[33] = (r < 32) ? Ai : Ci;
 #pragma unroll
-  for (int c = 0; c < CHOL_NB; ++c) Ls[r][c] = (c <= r) ? a[c] : 0.0;
-  wave_lds_sync();
-  // a pivot that is not > 0 (or NaN) leaves a diagonal root that is not > 0,
-  // and every later pivot inherits the failure: the first bad column is the
-  // lowest such lane
-  const double diag = Ls[r][r];
-  const unsigned long long bad = __ballot(r < jn && !(diag > 0.0));
-  if (r == 0 && bad && *info == 0) *info = j0 + __ffsll((long long)bad);
-  rdiag[r] = 1.0 / diag;
-  wave_lds_sync();
-  tri_inverse_col(Ls, rdiag, a, r);
+    for (int q = 0; q < 32; ++q) D[q][c] = x[q];
+  }
+  __syncthreads();
+  // T = B A^-1 (B = rows 32 .. 63, columns 0 .. 31 of L; A^-1 lower) into
+  // Ls[i][32 + j] (rows 0 .. 31 of the factor's zero columns 32 .. 63):
+  // thread t forms row t / 8, columns 4 (t % 8) .. 4 (t % 8) + 3
+  const int ti = t >> 3, tj = (t & 7) * 4;
+  {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < CHOL_NB; ++q) Linv[q + r * CHOL_NB] = a[q];
+    for (int q = 0; q < 32; ++q) {
+      const double bq = Ls[32 + ti][q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = __fma_rn(bq, Ai[q][tj + e], acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ls[ti][32 + tj + e] = acc[e];
+  }
+  __syncthreads();
+  // lower-left block of the inverse: -C^-1 T (C^-1 lower)
+  double xl[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    const double cq = Ci[ti][q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xl[e] = __fma_rn(-cq, Ls[q][32 + tj + e], xl[e]);
+  }
+  // inverse out, column-major: Linv[q + c 64] = (L^-1)(q, c).  Thread t
+  // writes its lower-left entries from registers, then the other three blocks
+  // (A^-1, the zero block, C^-1) from LDS in coalesced column runs
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Linv[(32 + ti) + (tj + e) * CHOL_NB] = xl[e];
+#pragma unroll
+  for (int k = 0; k < CHOL_NB * CHOL_NB / CHOL_DIAG_THREADS; ++k) {
+    const int e = t + k * CHOL_DIAG_THREADS;
+    const int q = e & (CHOL_NB - 1), c = e >> 6;
+    if (c < 32) {
+      if (q < 32) Linv[e] = Ai[q][c];
+    } else {
+      Linv[e] = (q < 32) ? 0.0 : Ci[q - 32][c - 32];
+    }
+  }
 }
 
 DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
@@ -838,8 +931,8 @@ DEV void chol_diag_block(double* __restrict__ A, int d, int j0, int jn, double* 
   chol_diag_core(A, d, j0, jn, Linv, info, sh);
 }
 
-__global__ __launch_bounds__(64) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
-                                                  double* __restrict__ Linv, int* __restrict__ info) {
+__global__ __launch_bounds__(CHOL_DIAG_THREADS) void k_chol_diag(double* __restrict__ A, int d, int j0, int jn,
+                                                                 double* __restrict__ Linv, int* __restrict__ info) {
   chol_diag_block(A, d, j0, jn, Linv, info);
 }
 
@@ -948,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_chol_update_diag(double* __restrict__ A
 
 hipError_t potrf(double* A, int d, int* info, double* Linv, hipStream_t s) {
   const int nb = cdiv(d, CHOL_NB);
-  hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, s, A, d, 0, min(CHOL_NB, d), Linv, info);
+  hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(CHOL_DIAG_THREADS), 0, s, A, d, 0, min(CHOL_NB, d), Linv, info);
   for (int jb = 0; jb + 1 < nb; ++jb) {
     const int j0 = jb * CHOL_NB, jn = CHOL_NB;
     const double* Li = Linv + (long)jb * CHOL_NB * CHOL_NB;
@@ -1242,7 +1335,7 @@ hipError_t trsm_whiten(const double* L, const double* X, const double* xr, doubl
 // problem's arithmetic is bitwise that of a separate call.  Problem z owns A
 // + z sA, Linv + z sL, info[z]; the whitening works on column z of X and Z.
 // skip (whitening): problem z is left untouched when skip[z] != 0.
-__global__ __launch_bounds__(64) void kb_chol_diag(double* __restrict__ A, long sA, int d, int j0, int jn,
+__global__ __launch_bounds__(CHOL_DIAG_THREADS) void kb_chol_diag(double* __restrict__ A, long sA, int d, int j0, int jn,
                                                    double* __restrict__ Linv, long sL, int* __restrict__ info) {
   const int z = blockIdx.z;
   chol_diag_block(A + z * sA, d, j0, jn, Linv + z * sL, info + z);
@@ -1272,7 +1365,8 @@ __global__ __launch_bounds__(256) void kb_chol_update_diag(double* __restrict__ 
 hipError_t potrf_batched(double* A, long sA, int d, int* info, double* Linv, long sL, int nprob, hipStream_t s) {
   if (nprob < 1 || nprob > 65535) return hipErrorInvalidValue;
   const int nb = cdiv(d, CHOL_NB);
-  hipLaunchKernelGGL(kb_chol_diag, dim3(1, 1, nprob), dim3(64), 0, s, A, sA, d, 0, min(CHOL_NB, d), Linv, sL, info);
+  hipLaunchKernelGGL(kb_chol_diag, dim3(1, 1, nprob), dim3(CHOL_DIAG_THREADS), 0, s, A, sA, d, 0, min(CHOL_NB, d),
+                     Linv, sL, info);
   for (int jb = 0; jb + 1 < nb; ++jb) {
     const int j0 = jb * CHOL_NB, jn = CHOL_NB;
     const int m = nb - jb - 1;
@@ -1620,8 +1714,7 @@ DEV double block_sum_f64(double v, double* red) {
 
 // Stopping errors of the experiments (Section 3.3): |S - m m^T - Sigma|_F^2,
 // |Sigma|_F^2 and |m - mu|^2, as per-block FP64 partial sums (fixed order)
-// reduced by one more block: deterministic.
-constexpr int MERR_BLOCKS = 1024;
+// reduced by one more block: deterministic (MERR_BLOCKS in kernels.h).
 
 __global__ __launch_bounds__(256) void k_moment_err(const double* __restrict__ S, const double* __restrict__ m,
                                                     const double* __restrict__ Sigma, const double* __restrict__ mu,
@@ -1669,7 +1762,7 @@ __global__ __launch_bounds__(256) void k_moment_err_final(const double* __restri
   }
 }
 
-size_t moment_err_scratch_bytes() { return (size_t)(2 + 3 * MERR_BLOCKS) * sizeof(double); }
+size_t moment_err_scratch_bytes() { return MERR_SCRATCH_DOUBLES * sizeof(double); }
 
 hipError_t moment_error(const double* S, const double* m, const double* Sigma, const double* mu, int d, double* scratch,
                         hipStream_t s) {
@@ -2061,10 +2154,9 @@ int g_tgt_bm(int cfg) {
   return bm[cfg];
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, const BTile* __restrict__ tl, BStep st) {
-  const BTile t = tl[blockIdx.x];
-  const BProb& b = pr[t.g];
+// Step arguments of problem b for step st.t (accept step t, propose step
+// t + 1; t = -1: the first proposal only).
+DEV StepArgs g_step_args(const BProb& b, const BStep& st, int g) {
   const int P = st.P, d = b.d, cu = st.t & 1, nx = cu ^ 1;
   const long dP = (long)b.ld * P;  // one step's slice of W and Xi (padded rows)
   StepArgs a{};
@@ -2096,7 +2188,7 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
     a.zq_cur = b.zq + (long)cu * P;
     a.lp_nxt = b.lp + (long)nx * P;
     a.zq_nxt = b.zq + (long)nx * P;
-    a.u = st.U + ((long)t.g * st.n + st.t) * P;
+    a.u = st.U + ((long)g * st.n + st.t) * P;
     a.la_out = b.la + (long)st.t * P;
     a.acc_out = b.acc + (long)st.t * P;
     a.win_col0 = (long)st.t * P;
@@ -2110,8 +2202,16 @@ __global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, con
     a.wlo_nxt = nullptr;
     a.zq_part_nxt = b.zq_part + (long)(tn & 1) * b.nch * P;
   }
+  return a;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void gk_step(const BProb* __restrict__ pr, const BTile* __restrict__ tl, BStep st) {
+  const BTile t = tl[blockIdx.x];
+  const BProb& b = pr[t.g];
+  const StepArgs a = g_step_args(b, st, t.g);
   if (MODE == 1) decide_block(a, b.nch, t.b);
-  else if ((d & 1) == 0) step_update2<P32>(a, t.a, b.nch, t.b);
+  else if ((b.d & 1) == 0) step_update2<P32>(a, t.a, b.nch, t.b);
   else step_body<P32, 2>(a, t.a, b.nch, t.b);
 }
 
@@ -2123,6 +2223,91 @@ hipError_t g_step(const BProb* pr, const BTile* dec_tl, int ndec, const BTile* t
   if (st.t >= 0) hipLaunchKernelGGL((gk_step<1>), dim3(ndec), dim3(256), 0, s, pr, dec_tl, st);
   hipLaunchKernelGGL((gk_step<2>), dim3(ntiles), dim3(256), 0, s, pr, tl, st);
   return hipGetLastError();
+}
+
+// The n_lag steps of a window for every problem in one launch (see PItem).
+// Items are taken in queue order, so every item an item waits for was taken
+// earlier by a running workgroup: the earliest unfinished item can always
+// proceed, whatever the grid size.  A wait is bounded: after spin_max polls it
+// sets bit 1 of the error word, and every workgroup then stops taking items.
+// Thread 0 publishes a finished item (agent-scope release, after the
+// workgroup barrier that ends the item) when it takes the next one; a waiter
+// polls relaxed and then fences with an agent-scope acquire.  Every loop exit
+// tests a value read back as wavefront-uniform, so all wavefronts leave (and
+// pass every barrier) together.  The bodies are those of gk_tgt (64 x 2
+// tiles), decide_wave (bitwise decide_block at these sizes: at most 64 row
+// blocks and 64 chunks) and the update half of gk_step, so results are
+// bitwise those of the per-phase launches with the default tile shape.
+__global__ __launch_bounds__(PERSIST_THREADS) void gk_persist(const BProb* __restrict__ pr,
+                                                              const PItem* __restrict__ items, int nitems, BStep st,
+                                                              PCtl c) {
+  __shared__ int s_q, s_ok;
+  const int total = nitems * st.n;
+  int prev_g = -1;  // problem of the item finished in the previous pass (thread 0 publishes it)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (prev_g >= 0) __hip_atomic_fetch_add(c.done + prev_g, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int q = -1;
+      if ((__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) == 0)
+        q = __hip_atomic_fetch_add(c.qctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_q = q;
+    }
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(s_q);
+    if (q < 0 || q >= total) break;
+    const int t = q / nitems;
+    const PItem it = items[q - t * nitems];
+    if (threadIdx.x == 0) {
+      const int need = t * c.per_step[it.g] + it.need;
+      int ok = 1, spins = 0;
+      while (__hip_atomic_load(c.done + it.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++spins > c.spin_max || (__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!ok) __hip_atomic_fetch_or(c.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
+    const int kind = __builtin_amdgcn_readfirstlane(it.kind), g = __builtin_amdgcn_readfirstlane(it.g);
+    const BProb& b = pr[g];
+    if (kind == 0) {
+      tgt_gauss_tile<float, 32, 64, 32, 2>(b.Rp, b.Vp, b.ld, st.P, it.a, it.b, b.lpp_part, b.nrb);
+    } else {
+      BStep sp = st;
+      sp.t = t;
+      const StepArgs a = g_step_args(b, sp, g);
+      const int w = threadIdx.x >> 6;
+      if (kind == 1) {
+        for (int p = w; p < st.P; p += PERSIST_THREADS / 64) decide_wave(a, b.nch, p, true);
+      } else {
+        // eight waves: chains 8k .. 8k + 7 per pass (the bodies take chain 4 pq + wave)
+        for (int pq = 0; pq * 4 < st.P; pq += PERSIST_THREADS / 256) {
+          if ((b.d & 1) == 0) step_update2<P32>(a, it.a, b.nch, pq);
+          else step_body<P32, 2>(a, it.a, b.nch, pq);
+        }
+      }
+    }
+    __syncthreads();  // the item's stores, in every wavefront, before thread 0 publishes it
+    prev_g = g;
+  }
+}
+
+hipError_t g_persist(const BProb* pr, const PItem* items, int nitems, const BStep& st, const PCtl& ctl, int grid,
+                     hipStream_t s) {
+  if (nitems <= 0 || st.n <= 0 || grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gk_persist, dim3(grid), dim3(PERSIST_THREADS), 0, s, pr, items, nitems, st, ctl);
+  return hipGetLastError();
+}
+
+int g_persist_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gk_persist, PERSIST_THREADS, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 __global__ __launch_bounds__(256) void gk_trigemm(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int ncols,
@@ -2196,7 +2381,7 @@ hipError_t g_cov(const BProb* pr, const BTile* dd_tl, int ndd, hipStream_t s) {
 }
 
 // blocked Cholesky, block column jb of every problem with more than jb blocks
-__global__ __launch_bounds__(64) void gk_chol_diag(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb) {
+__global__ __launch_bounds__(CHOL_DIAG_THREADS) void gk_chol_diag(const BProb* __restrict__ pr, const BTile* __restrict__ tl, int jb) {
   const BTile t = tl[blockIdx.x];
   const BProb& b = pr[t.g];
   const int j0 = jb * CHOL_NB, jn = min(CHOL_NB, b.d - j0);
@@ -2218,7 +2403,7 @@ __global__ __launch_bounds__(256) void gk_chol_update(const BProb* __restrict__ 
 
 hipError_t g_chol_step(const BProb* pr, const BTile* diag, int ndiag, const BTile* panel, int npanel,
                        const BTile* upd, int nupd, int jb, hipStream_t s) {
-  if (ndiag) hipLaunchKernelGGL(gk_chol_diag, dim3(ndiag), dim3(64), 0, s, pr, diag, jb);
+  if (ndiag) hipLaunchKernelGGL(gk_chol_diag, dim3(ndiag), dim3(CHOL_DIAG_THREADS), 0, s, pr, diag, jb);
   if (npanel) hipLaunchKernelGGL(gk_chol_panel, dim3(npanel), dim3(256), 0, s, pr, panel, jb);
   if (nupd) hipLaunchKernelGGL(gk_chol_update, dim3(nupd), dim3(256), 0, s, pr, upd, jb);
   return hipGetLastError();

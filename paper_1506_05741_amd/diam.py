@@ -32,7 +32,8 @@ EXPORTED = (
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
     "diam_set_beta_adaptation", "diam_psrf_enable", "diam_psrf", "diam_moment_error",
     "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
-    "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_field_bytes",
+    "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_set_persistent",
+    "diam_batch_field_bytes",
     "diam_batch_get", "diam_batch_get_stats", "diam_batch_destroy",
 )
 BATCH_TILES = ("32x2", "64x1", "64x2", "128x2", "32x4")   # target tile rows x k-groups
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
         "diam_batch_set_tiles": ([vp, i32], ctypes.c_int),
         "diam_batch_autotune": ([vp, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
         "diam_batch_set_graph": ([vp, i32], ctypes.c_int),
+        "diam_batch_set_persistent": ([vp, i32], ctypes.c_int),
         "diam_batch_field_bytes": ([vp, i32, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "diam_batch_get": ([vp, i32, i32, vp, sz], ctypes.c_int),
         "diam_batch_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
@@ -414,6 +416,9 @@ class Batch:
 
     def set_graph(self, on=True):
         _check(self.lib.diam_batch_set_graph(self.ctx, 1 if on else 0))
+
+    def set_persistent(self, on=True):
+        _check(self.lib.diam_batch_set_persistent(self.ctx, 1 if on else 0))
 
     def autotune(self, reps=20):
         c = ctypes.c_int32()

@@ -8,8 +8,15 @@
   70, 128, 200): partial tiles, several Cholesky blocks and a degenerate d = 1.
 * Graph replays against eager launches, with unrelated eager work between
   the replays, bitwise on every window.
+* The n_lag loop as one persistent launch (a device work queue of
+  (problem, phase, tile) items) against the per-phase grouped launches,
+  bitwise, with and without graph capture and at the batched size.
 * With the autotuned tile shape the chains of every problem reproduce its
   posterior moments within 4 Monte Carlo standard errors.
+* Against the FP64 oracle: the 48 problems of the benchmark's batched
+  configuration over two windows; the smallest, the median and the largest
+  problem are followed by the oracle through the normals and uniforms the
+  batch drew (decisions, log alpha, states, merged moments and factor).
 """
 import math
 import sys
@@ -20,8 +27,11 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+from oracle import diam as od
 from oracle import ess as oe
+from oracle import targets as ot
 from paper_1506_05741_amd import diam, synth
+from tests.gpu_parity import assert_few_forced, oracle_follow
 
 
 def log(msg):
@@ -110,6 +120,63 @@ def test_graph_replays_match_eager_windows():
     log("graph replays equal eager windows bitwise over 4 windows")
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_persistent_loop_matches_grouped_launches(graph):
+    """The n_lag loop as one persistent launch against the per-phase grouped
+    launches: every field bitwise equal over three windows, with ragged
+    dimensions (a degenerate d = 1, odd d), with and without graph capture."""
+    dims, P, n_lag = [40, 128, 1, 201, 70, 333], 32, 8
+    ts, x0 = problems(dims, P, 61)
+    ref, _ = make_batch(ts, x0, P, n_lag, 4, 10 * P * n_lag)
+    per, _ = make_batch(ts, x0, P, n_lag, 4, 10 * P * n_lag)
+    per.set_persistent(True)
+    per.set_graph(graph)
+    with pytest.raises(diam.DiamError) as e:
+        per.set_tiles(0)
+    assert e.value.status == diam.E_STATE
+    for w in range(3):
+        assert ref.window()[0] == diam.OK
+        assert per.window()[0] == diam.OK
+        for g in range(len(dims)):
+            for f in FIELDS + [diam.F_W, diam.F_U, diam.F_ACC, diam.F_LA]:
+                assert torch.equal(ref.get(g, f), per.get(g, f)), (w, g, f)
+    acc = sum(int(per.get(g, diam.F_NACC).view(torch.int32).sum()) for g in range(len(dims)))
+    log(f"persistent loop ({'graph' if graph else 'eager'}): 3 windows bitwise equal to the grouped launches, "
+        f"{acc} accepted")
+    assert acc > 0
+    ref.close()
+    per.close()
+
+
+def test_persistent_loop_at_the_batched_size():
+    """The 48 targets of the batched configuration (d log-uniform in
+    [128, 3072], 32 chains, n_lag = 128): two windows of the persistent loop
+    bitwise equal to the grouped launches, and both timed."""
+    import time
+    P, nl = 32, 128
+    dims = [int(x) for x in synth.batch_dims(48)]
+    ts = [synth.gaussian_target(d, 1000 + g) for g, d in enumerate(dims)]
+    x0 = [synth.gaussian_exact_draws(t, P, 2000 + g) for g, t in enumerate(ts)]
+    ref, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
+    per, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
+    per.set_persistent(True)
+    times = {}
+    for name, b in (("grouped", ref), ("persistent", per)):
+        assert b.window()[0] == diam.OK
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        assert b.window()[0] == diam.OK
+        torch.cuda.synchronize()
+        times[name] = 1e3 * (time.perf_counter() - t0)
+    for g in range(48):
+        for f in FIELDS + [diam.F_ACC, diam.F_LA]:
+            assert torch.equal(ref.get(g, f), per.get(g, f)), (g, f)
+    log(f"48 targets: persistent loop bitwise equal to the grouped launches over 2 windows; ms per window "
+        f"{times}")
+    ref.close()
+    per.close()
+
+
 def _worst_z(t, X):
     n, d, P = X.shape
     V = np.concatenate([np.eye(d)[:, : min(d, 8)], t.Q[:, [0, -1]], synth.unit_vectors(d, 8, 5)], axis=1)
@@ -141,3 +208,100 @@ def test_autotuned_batch_reproduces_posterior_moments():
         acc = host(b.get(g, diam.F_NACC).view(torch.int32)).sum() / (P * n_lag * windows)
         log(f"problem {g} (d={t.d}): worst |z| {worst:.2f}, acceptance {acc:.3f}")
         assert worst < 4.0 and acc > 0.5
+
+
+U32 = 2.0 ** -24
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_batch_problems_against_the_oracle():
+    """The batched configuration (48 targets, d log-uniform in [128, 3072],
+    32 chains each, n_lag = 128, warm start) over two windows, with the
+    smallest, the median and the largest problem judged by the FP64 oracle.
+
+    The oracle runs the problem's own target as the batch receives it (R in
+    FP32, evaluated in FP64) and the proposal the batch applies: the factor
+    rounded to FP32 (diam_batch_get of the factor, adopted after every
+    update) and the FP32 normals and uniforms the batch drew.  What differs
+    is the FP32 arithmetic of the proposal and target contractions.  FP32
+    accumulation over d terms has a relative error that grows like sqrt(d) u
+    (the probabilistic model of Higham and Mary, SIAM J. Sci. Comput. 2019);
+    measured, log pi is within about 0.3 to 1.2 sqrt(d) u32 |log pi| of FP64
+    (single-problem FP32 form at d = 256 to 1024, this batch at d = 753).
+    The near-tie band and the log alpha tolerance are
+    8 sqrt(d) u32 (1 + 3 |log pi(x)|), and the model is checked at the start
+    on every judged problem: the batch's log pi of its states lies within
+    3 sqrt(d) u32 (1 + |log pi|) of FP64.  Away from
+    the band the decisions must be the oracle's; inside it the oracle follows
+    the batch.  States must agree to 1e-5 relative, merged moments to 1e-6,
+    and the factor must reproduce the oracle's covariance to 1e-5."""
+    P, nl, windows = 32, 128, 2
+    dims = [int(x) for x in synth.batch_dims(48)]
+    ts = [synth.gaussian_target(d, 1000 + g) for g, d in enumerate(dims)]
+    x0 = [synth.gaussian_exact_draws(t, P, 2000 + g) for g, t in enumerate(ts)]
+    N0 = float(P) * 12800
+    b, _ = make_batch(ts, x0, P, nl, 77, N0)
+    order = np.argsort(dims)
+    G = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    oracles = {}
+    for g in G:
+        t, d = ts[g], dims[g]
+        R32 = t.R.astype(np.float32).astype(np.float64)
+        o = od.DiamOracle(lambda X, R=R32, mu=t.mu: ot.gaussian_logpdf(R, mu, X), d, P, nl, 0.3, X=x0[g])
+        S0, m0 = synth.gaussian_warm_moments(t)
+        assert o.seed_moments(S0, m0, N0) == od.OK
+        lp_b = host(b.get_f64(g, diam.F_LOGP, (P,)))
+        e = np.max(np.abs(lp_b - o.lp) / (1 + np.abs(o.lp)))
+        log(f"problem {g} (d={d}): log pi of the start states within {e / (np.sqrt(d) * U32):.3f} sqrt(d) u32")
+        assert e <= 3.0 * np.sqrt(d) * U32
+        oracles[g] = o
+
+    def adopt(g):
+        d, o = dims[g], oracles[g]
+        o.A = host(b.get_f64(g, diam.F_L, (d, d))).T.copy()        # the factor the batch applies (FP32 values)
+        o.Z = od.whiten(o.A, o.x_ref, o.X)
+
+    for g in G:
+        adopt(g)
+    forced = {g: 0 for g in G}
+    ratio = {g: {} for g in G}
+    for w in range(windows):
+        assert b.window()[0] == diam.OK
+        for g in G:
+            d, o = dims[g], oracles[g]
+            ld = (d + 3) // 4 * 4
+            W = host(b.get(g, diam.F_W).view(torch.float32).reshape(nl, P, ld)[:, :, :d]).astype(np.float64)
+            U = host(b.get_f64(g, diam.F_U, (nl, P)))
+            acc_g = host(b.get(g, diam.F_ACC)).reshape(nl, P).astype(bool)
+            la_g = host(b.get_f64(g, diam.F_LA, (nl, P)))
+            band = lambda o, d=d: 8.0 * np.sqrt(d) * U32 * (1.0 + 3.0 * np.abs(o.lp))
+            _, f = oracle_follow(o, W, U, acc_g, la_g, band, where=f"batch problem {g} d={d} window {w}",
+                                 stats=ratio[g])
+            forced[g] += f
+            Xg = host(b.get_f64(g, diam.F_X, (P, d))).T
+            ex = max(rel(Xg[:, p], o.X[:, p]) for p in range(P))
+            assert ex <= 1e-5, (g, w, ex)
+            o.merge_moments()
+            S = host(b.get_f64(g, diam.F_S, (d, d))).T
+            m = host(b.get_f64(g, diam.F_M, (d,)))
+            eS, em = rel(S, o.S_glob), rel(m, o.m_glob)
+            assert eS <= 1e-6 and em <= 1e-6, (g, w, eS, em)
+            assert o.update_proposal() == od.OK
+            L = host(b.get_f64(g, diam.F_L, (d, d))).T
+            C = od.sample_covariance(o.S_glob, o.m_glob)
+            eC = rel(L @ L.T, C)
+            assert eC <= 1e-5, (g, w, eC)
+            assert rel(host(b.get_f64(g, diam.F_XREF, (d,))), o.x_ref) <= 1e-6
+            adopt(g)
+            acc = int(acc_g.sum())
+            log(f"window {w}, problem {g} (d={d}): {acc} of {nl * P} accepted, {forced[g]} forced so far, largest "
+                f"log alpha difference {ratio[g].get('max_ratio', 0.0):.3f} of the band; states {ex:.1e}, "
+                f"S {eS:.1e}, m {em:.1e}, L L^T vs C {eC:.1e}")
+    for g in G:
+        # FP32 arithmetic at d ~ 3000 makes a band of ~0.1 in log alpha: a few
+        # per cent of the decisions fall inside it and are forced
+        assert_few_forced(forced[g], windows * nl * P, where=f"problem {g}", frac=0.15)
+    b.close()
