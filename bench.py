@@ -62,7 +62,38 @@ def ess_per_chain(traces):
     return tot
 
 
-def run_sampler(prec, tgt, args, torch, diam, profile):
+def posterior_z_scores(tr, tgt, d, n_lag):
+    """z-scores of traced functionals against the target's exact moments:
+    log pi = -1/2 chi^2_d (mean -d/2, variance d/2), and v^T x for the
+    largest- and smallest-variance eigenvectors (mean v^T mu, variance the
+    eigenvalue); tr is steps x 3 x P (log pi, v_max^T x, v_min^T x).  The
+    chains share the adapted factor and pivot, so their fluctuations are not
+    independent: the standard error comes from batch means, the per-window
+    averages over all chains and steps, with the Geyer ESS of that series
+    (se).  The figure that treats the chains as independent (the sum of the
+    per-chain Geyer ESS) is kept as se_chains / z_chains."""
+    out = {}
+    truths = (("logpi", -0.5 * d, 0.5 * d), ("v_max", tgt["v_max"] @ tgt["mu"], tgt["lam"][0]),
+              ("v_min", tgt["v_min"] @ tgt["mu"], tgt["lam"][-1]))
+    worst = worst_chains = 0.0
+    nw = tr.shape[0] // n_lag
+    for k, (name, mean, var) in enumerate(truths):
+        x = tr[:nw * n_lag, k, :]
+        for kind, f, truth in (("mean", x, mean), ("variance", (x - mean) ** 2, var)):
+            wm = f.reshape(nw, n_lag, -1).mean(axis=(1, 2))
+            se = wm.std() / math.sqrt(ess_per_chain(wm[:, None]))
+            se_c = f.std() / math.sqrt(ess_per_chain(f))
+            z, z_c = (f.mean() - truth) / se, (f.mean() - truth) / se_c
+            out[f"{name}_{kind}"] = {"estimate": float(f.mean()), "exact": float(truth), "se": float(se),
+                                     "z": float(z), "se_chains": float(se_c), "z_chains": float(z_c)}
+            worst = max(worst, abs(z))
+            worst_chains = max(worst_chains, abs(z_c))
+    out["worst_abs_z"] = worst
+    out["worst_abs_z_chains"] = worst_chains
+    return out
+
+
+def run_sampler(prec, tgt, args, torch, diam, profile, stats=False):
     d, P, nl = args.d, args.P, args.n_lag
     dev = torch.device("cuda:0")
     cfg = diam.make_config(d, P, nl, prec, beta=args.beta, seed=args.seed)
@@ -77,7 +108,8 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
     assert st == diam.OK
     proj = torch.as_tensor(np.stack([tgt["v_max"], tgt["v_min"]]), device=dev).contiguous()
     n_timed = args.steps * nl
-    trace = torch.empty((n_timed, 3, P), dtype=torch.float64, device=dev)
+    stat_windows = max(args.steps, getattr(args, "stat_windows", 0) if stats else 0)
+    trace = torch.empty((stat_windows * nl, 3, P), dtype=torch.float64, device=dev)
 
     def window():
         s.step_batch(nl)
@@ -97,6 +129,14 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     nacc = s.get(diam.F_NACC).view(torch.int32).sum().item()
+    # statistics run: the traced windows continue (untimed) to the configured
+    # samples per chain, for the posterior-moment z-scores
+    t_stat = time.perf_counter()
+    for _ in range(stat_windows - args.steps):
+        window()
+    torch.cuda.synchronize()
+    t_stat = time.perf_counter() - t_stat
+    s.set_trace(None, None)
     # stopping errors of Section 3.3 (after the timed windows, outside the timing)
     Sig = torch.as_tensor(tgt["S0"] - np.outer(tgt["m0"], tgt["m0"]), device=dev)
     cov_err, mean_err = s.moment_error(Sig, torch.as_tensor(tgt["mu"], device=dev))
@@ -116,8 +156,14 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         s.psrf_enable(False)
         s.profile(False)
     tr = trace.cpu().numpy()
+    del trace
     half = n_timed // 2
-    ess = {name: ess_per_chain(tr[half:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
+    ess = {name: ess_per_chain(tr[half:n_timed, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
+    moments = None
+    if stat_windows > args.steps and "lam" in tgt:
+        moments = posterior_z_scores(tr, tgt, d, nl)
+        moments.update(windows=stat_windows, samples_per_chain=stat_windows * nl, seconds=T + t_stat)
+    del tr
     s.close()
     chain_steps = P * n_timed
     return {
@@ -131,6 +177,7 @@ def run_sampler(prec, tgt, args, torch, diam, profile):
         "acceptance": nacc / (P * (n_timed + args.warmup * nl)),
         "profile": prof,
         "psrf_worst": psrf_worst if profile else None,
+        "moments": moments,
         "stopping": {"cov_rel_fro": cov_err, "mean_abs": mean_err, "tol": {"cov_rel_fro": 1e-3, "mean_abs": 1e-2}},
     }
 
@@ -160,12 +207,14 @@ def learned_experiment(args, torch, diam):
     proj = torch.as_tensor(np.stack([V[:, -1], V[:, 0]]), device=dev).contiguous()
     n_pairs = 50000
     collect = -(-n_pairs // P)                            # steps whose states train the surrogate
-    betas = [float(b) for b in args.learned_betas.split(",")]
+    # (beta, alpha) settings: the step size and the inflation of eq. diamnl
+    settings = [tuple(float(v) for v in pair.split(":")) if ":" in pair else (float(pair), 1.0)
+                for pair in args.learned_settings.split(",")]
     out = {"workload": f"Bayesian logistic regression n=200000 d={d} (A ~ N(0, 1/d), prior N(0, 10 I)), "
                        f"P={P}, n_lag={nl}, Laplace warm start; surrogate form {args.surrogate_form}",
            "precision": args.learned_precision, "runs": []}
-    for beta, use_da in [(b, u) for b in betas for u in (False, True)]:
-        cfg = diam.make_config(d, P, nl, args.learned_precision, beta=beta, seed=91,
+    for (beta, alpha), use_da in [(st, u) for st in settings for u in (False, True)]:
+        cfg = diam.make_config(d, P, nl, args.learned_precision, beta=beta, alpha=alpha, seed=91,
                                surrogate=args.surrogate_form if use_da else 0, train_max=n_pairs)
         s = diam.Sampler(cfg, None, None, torch.as_tensor(np.ascontiguousarray(x0.T), device=dev), A=A, y=y,
                          prior_var=data.prior_var)
@@ -224,7 +273,7 @@ def learned_experiment(args, torch, diam):
         prof = s.profile_read(reset=True)
         s.profile(False)
         ess = {name: ess_per_chain(tr[:, k, :]) for k, name in enumerate(("logpi", "v_max", "v_min"))}
-        r = {"beta": beta, "delayed_acceptance": use_da,
+        r = {"beta": beta, "alpha": alpha, "delayed_acceptance": use_da,
              "seconds": T, "chain_steps_per_s": P * n_timed / T, "ess": ess, "ess_per_s": min(ess.values()) / T,
              "acceptance": nacc / (P * n_timed),
              "stage_ms_per_window": {k: v[0] for k, v in prof.items() if v[1]}}
@@ -234,14 +283,20 @@ def learned_experiment(args, torch, diam):
             r["ess_per_s_incl_training"] = min(ess.values()) / (T + train_s)
             r["surrogate"] = surr
         out["runs"].append(r)
-        log(f"logistic beta={beta} {'DA' if use_da else 'plain'}: {r['chain_steps_per_s']:.4g} chain-steps/s, "
+        log(f"logistic beta={beta} alpha={alpha} {'DA' if use_da else 'plain'}: "
+            f"{r['chain_steps_per_s']:.4g} chain-steps/s, "
             f"ESS/s {r['ess_per_s']:.4g}, acceptance {r['acceptance']:.3f}"
             + (f", stage-1 pass {r['stage1_pass_rate']:.3f}" if use_da else ""))
         s.close()
         del Xtr, ltr, trace
-    plain = {r["beta"]: r for r in out["runs"] if not r["delayed_acceptance"]}
-    da = {r["beta"]: r for r in out["runs"] if r["delayed_acceptance"]}
-    out["ess_per_s_gain_at_beta"] = {str(b): da[b]["ess_per_s"] / plain[b]["ess_per_s"] for b in betas}
+    plain = {(r["beta"], r["alpha"]): r for r in out["runs"] if not r["delayed_acceptance"]}
+    da = {(r["beta"], r["alpha"]): r for r in out["runs"] if r["delayed_acceptance"]}
+    out["ess_per_s_gain_at_setting"] = {f"beta={b},alpha={a}": da[(b, a)]["ess_per_s"] / plain[(b, a)]["ess_per_s"]
+                                        for b, a in settings}
+    # what the network does per exact evaluation: ESS per exact target evaluation, DA / plain
+    out["ess_per_exact_eval_gain_at_setting"] = {
+        f"beta={b},alpha={a}": (min(da[(b, a)]["ess"].values()) / (da[(b, a)]["stage1_pass_rate"]))
+        / min(plain[(b, a)]["ess"].values()) for b, a in settings}
     best_plain = max(r["ess_per_s"] for r in plain.values())
     best_da = max(r["ess_per_s"] for r in da.values())
     out["best_plain_ess_per_s"] = best_plain
@@ -299,15 +354,19 @@ def batch_experiment(args, torch, diam):
         assert b.window()[0] == diam.OK
         for g, t in enumerate(ts):
             series[g].append(b.get_f64(g, diam.F_X, (P, t.d)).cpu().numpy() @ proj[g].T)
-    ess_win, worst = 0.0, 0.0
+    ess_win, worst, worst_at = 0.0, 0.0, None
     for g, t in enumerate(ts):
         Y = np.stack(series[g])                               # windows x P x 2
         es = []
         for f, lam in ((0, t.lam[0]), (1, t.lam[-1])):
             y, m = Y[:, :, f], proj[g][f] @ t.mu
             es.append(ess_per_chain(y))
-            for h, truth in ((y, m), ((y - m) ** 2, lam)):
-                worst = max(worst, abs(h.mean() - truth) / (h.std() / math.sqrt(ess_per_chain(h))))
+            for kind, h, truth in (("mean", y, m), ("variance", (y - m) ** 2, lam)):
+                z = (h.mean() - truth) / (h.std() / math.sqrt(ess_per_chain(h)))
+                if abs(z) > worst:
+                    worst = abs(z)
+                    worst_at = {"target": g, "d": t.d, "functional": ("v_max" if f == 0 else "v_min") + "^T x",
+                                "moment": kind, "z": float(z)}
         ess_win += min(es) / Y.shape[0]
     b.close()
     chain_steps = 48 * P * nl * args.batch_windows
@@ -318,7 +377,7 @@ def batch_experiment(args, torch, diam):
            "chain_steps_per_s": chain_steps / T, "acceptance": acc,
            "ess_per_s_summed": ess_win * args.batch_windows / T,
            "ess": {"windows": args.batch_ess_windows, "per_window_summed": ess_win,
-                   "worst_z_moments": worst,
+                   "worst_z_moments": worst, "worst": worst_at,
                    "note": "window-end states of the 48 targets, v_max^T x and v_min^T x; worst |z| of their "
                            "means and variances against the exact values over all targets"},
            "autotune_us_per_target_launch": us, "tile_choice": diam.BATCH_TILES[choice],
@@ -326,6 +385,24 @@ def batch_experiment(args, torch, diam):
                                "achieved": flops / (us[diam.BATCH_TILES[choice]] * 1e-6) / 1e12,
                                "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
                                "frac": flops / (us[diam.BATCH_TILES[choice]] * 1e-6) / PEAK["fp32"]}}
+    # the same windows with the n_lag loop as one persistent launch (a device
+    # queue of (problem, phase, tile) items; default 64 x 2 target tiles)
+    bp = diam.Batch(cfg, mus, Rs, xs)
+    assert bp.seed_moments(S0, m0, N0)[0] == diam.OK
+    bp.set_persistent(True)
+    assert bp.window()[0] == diam.OK
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.batch_windows):
+        st, _ = bp.window()
+        assert st == diam.OK
+    torch.cuda.synchronize()
+    Tp = time.perf_counter() - t1
+    bp.close()
+    out["persistent"] = {"windows": args.batch_windows, "ms_per_window": 1e3 * Tp / args.batch_windows,
+                         "chain_steps_per_s": chain_steps / Tp, "vs_graph": T / Tp,
+                         "note": "the n_lag loop of every window as one persistent launch over a device work "
+                                 "queue, graph-captured window, default 64x2 target tiles"}
     # the same windows problem by problem through the single-problem API
     singles = []
     for g, t in enumerate(ts):
@@ -354,8 +431,9 @@ def batch_experiment(args, torch, diam):
                          "chain_steps_per_s": 48 * P * nl * nseq / Ts}
     out["speedup_vs_sequential"] = out["chain_steps_per_s"] / out["sequential"]["chain_steps_per_s"]
     log(f"batch: {out['chain_steps_per_s']:.4g} chain-steps/s ({out['ms_per_window']:.2f} ms/window, tiles "
-        f"{out['tile_choice']}), sequential {out['sequential']['chain_steps_per_s']:.4g}, ESS/s summed "
-        f"{out['ess_per_s_summed']:.4g}, worst |z| {worst:.2f}")
+        f"{out['tile_choice']}), persistent loop {out['persistent']['ms_per_window']:.2f} ms/window, sequential "
+        f"{out['sequential']['chain_steps_per_s']:.4g}, ESS/s summed {out['ess_per_s_summed']:.4g}, "
+        f"worst |z| {worst:.2f} ({out['ess']['worst']})")
     return out
 
 
@@ -510,18 +588,64 @@ def local_global_experiment(args, torch, diam):
     return out
 
 
+def host_info():
+    """The host the oracle runs on: core count, CPU model, NumPy's BLAS
+    backend and the threads its pool uses."""
+    info = {"cpu_count": os.cpu_count(), "cpu_model": None, "blas": None, "blas_threads": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        info["blas"] = f"{blas.get('name')} {blas.get('version', '')}".strip()
+    except Exception:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if pools:
+            info["blas_threads"] = max(int(p.get("num_threads", 1)) for p in pools)
+            info["blas"] = info["blas"] or pools[0].get("internal_api")
+    except Exception:
+        pass
+    return info
+
+
+def _oracle_windows(o, d, P, nl, windows, seed):
+    """Time `windows` whole windows of the oracle (steps, merge, update) on
+    seeded normals and uniforms drawn outside the timing."""
+    from paper_1506_05741_amd import synth
+    T = 0.0
+    for w in range(windows):
+        W = synth.draw_normals(d, P, nl, seed + 2 * w)
+        U = synth.draw_uniforms(P, nl, seed + 2 * w + 1)
+        t0 = time.perf_counter()
+        for t in range(nl):
+            o.step(W[t].T, U[t])
+        o.merge_moments()
+        o.update_proposal()
+        T += time.perf_counter() - t0
+    return T
+
+
 def cpu_baseline(tgt, args):
-    """The FP64 oracle on the host cores over a bounded sample of the same
-    workload: a few steps of all P chains, one merge of those steps and one
-    refactorisation, extrapolated to whole windows."""
+    """The FP64 oracle on the host cores.  The d = 4096 workload (the line's
+    unit): a bounded sample of a few steps of all P chains, one merge of those
+    steps (scaled to a window's length) and one refactorisation, extrapolated
+    to whole windows; two full windows would take about half an hour.  The
+    d = 32 configuration as a full run (400 windows, literal cold start) and
+    the d = 1024 configuration over two whole windows (warm start), both
+    timed directly."""
     from oracle import diam as od
     from oracle import targets as ot
     from paper_1506_05741_amd import synth
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
-    except Exception:
-        cores = os.cpu_count()
+    info = host_info()
+    cores = info["blas_threads"] or info["cpu_count"]
     d, P, nl = args.d, args.P, args.n_lag
     R, mu = tgt["R"], tgt["mu"]
     o = od.DiamOracle(lambda X: ot.gaussian_logpdf(R, mu, X), d, P, nl, args.beta, X=tgt["x0"])
@@ -540,10 +664,30 @@ def cpu_baseline(tgt, args):
     o.update_proposal()
     t_update = time.perf_counter() - t0
     t_window = nl * t_step + t_merge + t_update
+    del o
+    configs = {}
+    # d = 32, P = 4, n_lag = 50, 2e4 samples per chain: the whole run
+    t32 = synth.gaussian_target(32, 0)
+    o32 = od.DiamOracle(lambda X: ot.gaussian_logpdf(t32.R, t32.mu, X), 32, 4, 50, 0.3, X=np.zeros((32, 4)))
+    T32 = _oracle_windows(o32, 32, 4, 50, 400, 1000)
+    configs["d32"] = {"chain_steps_per_s": 4 * 50 * 400 / T32, "seconds": T32,
+                      "run": "full: 400 windows of 50 steps, P = 4, literal cold start"}
+    # d = 1024, P = 64, n_lag = 200: two whole windows from the warm start
+    t1k = synth.gaussian_target(1024, 1)
+    S1, m1 = synth.gaussian_warm_moments(t1k)
+    o1k = od.DiamOracle(lambda X: ot.gaussian_logpdf(t1k.R, t1k.mu, X), 1024, 64, 200, 0.3,
+                        X=synth.gaussian_exact_draws(t1k, 64, 2))
+    o1k.seed_moments(S1, m1, 64 * 1e5)
+    T1k = _oracle_windows(o1k, 1024, 64, 200, 2, 2000)
+    configs["d1024"] = {"chain_steps_per_s": 64 * 200 * 2 / T1k, "seconds": T1k,
+                        "run": "2 whole windows of 200 steps, P = 64, warm start"}
     return {
         "value": P * nl / t_window, "unit": "chain-steps/s", "cores": cores, "kind": "oracle",
         "sample": f"{ns} steps of all {P} chains at d={d}, one merge of those steps scaled to n_lag={nl}, "
-                  f"one FP64 refactorisation; per window {t_window:.1f} s",
+                  f"one FP64 refactorisation; per window {t_window:.1f} s (extrapolated)",
+        "host": info, "configs": configs,
+        "note": "NumPy FP64 oracle with the plain triangular solve for z (d^2 P more flops per step than "
+                "the GPU's recurrence); ESS/s(oracle) = its steps/s x the GPU run's ESS per step",
     }
 
 
@@ -552,6 +696,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12, help="timed windows")
     ap.add_argument("--warmup", type=int, default=2, help="untimed windows")
+    ap.add_argument("--stat-windows", dest="stat_windows", type=int, default=196,
+                    help="traced windows (timed ones included) for the posterior-moment z-scores: 196 windows = "
+                         "5e4 samples per chain at n_lag = 256")
     ap.add_argument("--d", type=int, default=4096)
     ap.add_argument("--P", type=int, default=256)
     ap.add_argument("--n-lag", dest="n_lag", type=int, default=256)
@@ -568,7 +715,8 @@ def main():
                     help="first run 3 device copies of this many bytes (counter calibration)")
     ap.add_argument("--learned-only", action="store_true", help="run only the learned-part experiment")
     ap.add_argument("--learned-P", dest="learned_P", type=int, default=128)
-    ap.add_argument("--learned-betas", dest="learned_betas", default="0.5,1.0")
+    ap.add_argument("--learned-settings", dest="learned_settings", default="0.5,1.0,1.0:1.2,1.0:1.5",
+                    help="comma-separated beta or beta:alpha settings of the learned-form comparison")
     ap.add_argument("--surrogate-form", dest="surrogate_form", type=int, default=2, choices=[1, 2])
     ap.add_argument("--learned-windows", dest="learned_windows", type=int, default=4)
     ap.add_argument("--learned-precision", dest="learned_precision", default="fp32", choices=["mixed", "fp32", "fp64"])
@@ -628,15 +776,15 @@ def main():
     x0 = synth.gaussian_exact_draws(t, args.P, 3)
     S0, m0 = synth.gaussian_warm_moments(t)
     tgt = dict(mu=t.mu, R=t.R, x0=x0, S0=S0, m0=m0, N0=float(args.P) * 50176,
-               v_max=t.v_max, v_min=t.v_min)
+               v_max=t.v_max, v_min=t.v_min, lam=t.lam)
     log(f"target built in {time.perf_counter() - t0:.1f} s")
 
-    res = run_sampler(args.precision, tgt, args, torch, diam, profile=True)
+    res = run_sampler(args.precision, tgt, args, torch, diam, profile=True, stats=True)
     log(f"{args.precision}: {res['chain_steps_per_s']:.4g} chain-steps/s, ESS/s {res['ess_per_s']:.4g}, "
         f"{res['ms_per_window']:.2f} ms/window, acceptance {res['acceptance']:.3f}")
     ref = None
     if not args.no_fp64 and args.precision != "fp64":
-        ref = run_sampler("fp64", tgt, args, torch, diam, profile=True)
+        ref = run_sampler("fp64", tgt, args, torch, diam, profile=True, stats=True)
         log(f"fp64: {ref['chain_steps_per_s']:.4g} chain-steps/s, ESS/s {ref['ess_per_s']:.4g}, "
             f"{ref['ms_per_window']:.2f} ms/window")
 
@@ -646,29 +794,41 @@ def main():
     useful = 2.0 * args.d * args.d * args.P          # algorithmic flops of Y = R (x - mu) per step
     dt = (ms_t / n_t) * 1e-3
     split = args.precision == "mixed" and args.d % 128 == 0 and args.P % 64 == 0
+    method_bytes = 4.0 * args.d * args.d + 4.0 * args.d * args.P    # R (FP32) and x - mu read once
     if split:
-        # three bf16 parts per operand, six bf16 products per FP32-equivalent product
+        # three bf16 parts per operand, six bf16 products per FP32-equivalent
+        # product: frac counts the method's 2 d^2 P flops, executed_frac the
+        # six products the matrix cores run
+        traffic = TRAFFIC.get("k_tgt_s3") if (args.d, args.P) == (4096, 256) else None
         roofline = {"kernel": "k_tgt_s3 + k_tgt_s3_reduce (split-bf16 MFMA, FP32-equivalent; Y = R (x - mu), "
                               "column sums of Y^2)",
-                    "bound": "mfma", "achieved": 6 * useful / dt / 1e12, "peak": PEAK["bf16"] / 1e12,
-                    "unit": "TFLOP/s", "frac": 6 * useful / dt / PEAK["bf16"],
-                    "traffic": TRAFFIC.get("k_tgt_s3") if (args.d, args.P) == (4096, 256) else None,
+                    "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK["bf16"] / 1e12,
+                    "unit": "TFLOP/s", "frac": useful / dt / PEAK["bf16"],
+                    "traffic": traffic,
+                    "traffic_ratio": (traffic / method_bytes) if traffic else None,
+                    "method_bytes": method_bytes,
+                    "executed_tflops": 6 * useful / dt / 1e12, "executed_frac": 6 * useful / dt / PEAK["bf16"],
+                    "fp32_equivalent_frac": useful / dt / PEAK["fp32"],
                     "avg_us": dt * 1e6, "launches": n_t,
-                    "useful_tflops": useful / dt / 1e12}
+                    "work": "2 d^2 P flops per step (useful); 6 x that in bf16 products executed"}
     else:
         tdt = "fp64" if args.precision == "fp64" else "fp32"
         roofline = {"kernel": f"k_tgt_gauss ({tdt} MFMA, Y = R (x - mu), column sums of Y^2)",
                     "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK[tdt] / 1e12, "unit": "TFLOP/s",
                     "frac": useful / dt / PEAK[tdt], "traffic": TRAFFIC.get(f"k_tgt_gauss_{tdt}"),
                     "avg_us": dt * 1e6, "launches": n_t}
-    # the proposal contraction of the window (aim: >= 60 % of the bf16 peak)
+    # the proposal contraction of the window (spec: >= 60 % of the bf16
+    # peak): frac on the triangular d (d + 1) P n_lag flops of the method,
+    # executed_frac on the four bf16 hi/lo products the matrix cores run
     ms_p, n_p = prof["proposal"]
     if args.precision == "mixed" and n_p:
-        pf = 4.0 * args.d * (args.d + 1) * args.P * args.n_lag   # four bf16 hi/lo products, triangular
+        pf = float(args.d) * (args.d + 1) * args.P * args.n_lag
         dtp = ms_p / n_p * 1e-3
         roofline["proposal"] = {"kernel": "k_trigemm_hl (bf16 hi/lo, direct-to-LDS)", "achieved": pf / dtp / 1e12,
                                 "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s", "frac": pf / dtp / PEAK["bf16"],
-                                "avg_us": dtp * 1e6}
+                                "executed_tflops": 4 * pf / dtp / 1e12, "executed_frac": 4 * pf / dtp / PEAK["bf16"],
+                                "avg_us": dtp * 1e6,
+                                "work": "d (d + 1) P n_lag flops per window (useful, triangular); 4 x that executed"}
     stages = {k: {"ms_per_window": v[0] / args.profile_windows, "regions": v[1]} for k, v in prof.items() if v[1]}
     # the PSRF fold of a merged window (profiled windows only): store read + accumulators read and written
     psrf = None
@@ -705,10 +865,12 @@ def main():
         "roofline": roofline,
         "psrf": psrf,
         "stopping": res["stopping"],
+        "moments": res["moments"],
     }
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],
                        "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"],
+                       "moments": ref["moments"],
                        "stage_ms_per_window": {k: v[0] / args.profile_windows for k, v in ref["profile"].items()
                                                if v[1]}}
         out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],
