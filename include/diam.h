@@ -333,6 +333,22 @@ int diam_psrf(diam_ctx* ctx, double* out, double* worst);
  * (symmetric, so either layout), mu: device d f64.  FP64 sums in a fixed
  * order; synchronises the stream. */
 int diam_moment_error(diam_ctx* ctx, const double* Sigma, const double* mu, double* cov_rel, double* mean_abs);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * stopping errors for moments the caller holds, without a context or a
+ * workspace.  S: d x d f64 raw second moment, m: d f64 mean (device; e.g.
+ * read with diam_get or diam_batch_get), Sigma and mu as in
+ * diam_moment_error; cov_rel and mean_abs (host) as there.  hip_stream: a
+ * hipStream_t of the current device (NULL = default stream); synchronises
+ * it.  The reduction partials live in a static device array of the library
+ * (1024 partial triples and the two results, 24.6 KB per GPU, held until the
+ * process ends): the grid is capped at 1024 workgroups, so every d >= 1 fits
+ * (d < 1 is DIAM_E_ARG).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  Nothing in the array must start at zero: each
+ * call writes every partial it reads.  Calls no allocating routine. */
+int diam_moment_error_noalloc(const double* S, const double* m, int32_t d, const double* Sigma, const double* mu,
+                              double* cov_rel, double* mean_abs, void* hip_stream);
 
 /* ---- batched form ---------------------------------------------------------
  * G independent Gaussian problems of dimensions dims[g] (each target as in

@@ -31,6 +31,7 @@ EXPORTED = (
     "diam_last_error", "diam_destroy", "diam_profile_enable", "diam_profile_read",
     "diam_surrogate_train", "diam_surrogate_eval", "diam_set_delayed_acceptance",
     "diam_set_beta_adaptation", "diam_psrf_enable", "diam_psrf", "diam_moment_error",
+    "diam_moment_error_noalloc",
     "diam_batch_workspace_bytes", "diam_batch_init", "diam_batch_seed_moments", "diam_batch_window",
     "diam_batch_set_tiles", "diam_batch_autotune", "diam_batch_set_graph", "diam_batch_set_persistent",
     "diam_batch_field_bytes",
@@ -111,6 +112,8 @@ def load(path: str = LIB_PATH):
         "diam_psrf_enable": ([vp, i32], ctypes.c_int),
         "diam_psrf": ([vp, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "diam_moment_error": ([vp, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
+        "diam_moment_error_noalloc": ([vp, vp, i32, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp],
+                                      ctypes.c_int),
         "diam_batch_workspace_bytes": ([ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(sz)], ctypes.c_int),
         "diam_batch_init": ([ctypes.POINTER(vp), ctypes.POINTER(BatchConfig), vp, vp, vp, vp, sz, vp, vp],
                             ctypes.c_int),
@@ -353,6 +356,23 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+
+def moment_error_noalloc(S, m, Sigma, mu=None, stream=None):
+    """Stopping errors of caller-held moments (S (d, d) f64, m (d,) f64 CUDA)
+    through diam_moment_error_noalloc: (|S - m m^T - Sigma|_F / |Sigma|_F,
+    |m - mu|_2 or NaN).  Runs on the current device's current stream."""
+    import torch
+    lib = load()
+    d = int(m.numel())
+    for t in (S, m, Sigma) + ((mu,) if mu is not None else ()):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    assert S.numel() == d * d and Sigma.numel() == d * d and (mu is None or mu.numel() == d)
+    st = stream if stream is not None else torch.cuda.current_stream(m.device)
+    cov, mean = ctypes.c_double(), ctypes.c_double()
+    _check(lib.diam_moment_error_noalloc(_ptr(S), _ptr(m), d, _ptr(Sigma), _ptr(mu) if mu is not None else None,
+                                         ctypes.byref(cov), ctypes.byref(mean), ctypes.c_void_p(st.cuda_stream)))
+    return cov.value, mean.value
 
 
 def _ptr_array(ts, ctype=ctypes.c_void_p):
