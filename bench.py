@@ -28,12 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ESS/sec and chain steps/sec, d=4096 P=256: mixed-precision vs plain FP64 GPU"
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
 HBM_PEAK = 8.0e12
 # HBM bytes per launch of the target kernels from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE runs scaled by a device copy's counters (see profiles/); a
 # kernel missing here has changed since its counters were taken.
-TRAFFIC = {"k_tgt_s3": 187.3e6}   # profiles/hbm_traffic_k_tgt_s3_d4096_P256.md (d=4096, P=256)
+TRAFFIC = {}   # kernel -> HBM bytes per launch at d=4096, P=256 (profiles/hbm_traffic_*.md), once measured
 
 
 def log(msg):
@@ -155,6 +155,25 @@ def run_sampler(prec, tgt, args, torch, diam, profile, stats=False):
         psrf_worst = s.psrf()[1] if args.profile_windows else None
         s.psrf_enable(False)
         s.profile(False)
+    fixed = None
+    if stats and getattr(args, "fixed_windows", 0) > 0 and "lam" in tgt:
+        # control: the same sampler with the proposal frozen (factor and pivot
+        # of the end of the adaptive run; windows are merged but never
+        # refactorised), a fixed Metropolis-Hastings kernel whose moments can
+        # carry no adaptation bias
+        nf = args.fixed_windows
+        trf = torch.empty((nf * nl, 3, P), dtype=torch.float64, device=dev)
+        s.set_trace(proj, trf)
+        nacc_f0 = s.get(diam.F_NACC).view(torch.int32).sum().item()
+        for _ in range(nf):
+            s.step_batch(nl)
+            s.merge_moments()
+        torch.cuda.synchronize()
+        s.set_trace(None, None)
+        acc_f = (s.get(diam.F_NACC).view(torch.int32).sum().item() - nacc_f0) / (P * nl * nf)
+        fixed = posterior_z_scores(trf.cpu().numpy(), tgt, d, nl)
+        fixed.update(windows=nf, acceptance=acc_f)
+        del trf
     tr = trace.cpu().numpy()
     del trace
     half = n_timed // 2
@@ -178,6 +197,7 @@ def run_sampler(prec, tgt, args, torch, diam, profile, stats=False):
         "profile": prof,
         "psrf_worst": psrf_worst if profile else None,
         "moments": moments,
+        "moments_fixed_proposal": fixed,
         "stopping": {"cov_rel_fro": cov_err, "mean_abs": mean_err, "tol": {"cov_rel_fro": 1e-3, "mean_abs": 1e-2}},
     }
 
@@ -696,6 +716,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12, help="timed windows")
     ap.add_argument("--warmup", type=int, default=2, help="untimed windows")
+    ap.add_argument("--fixed-windows", dest="fixed_windows", type=int, default=196,
+                    help="traced windows with the proposal frozen after the statistics run (0: none)")
     ap.add_argument("--stat-windows", dest="stat_windows", type=int, default=196,
                     help="traced windows (timed ones included) for the posterior-moment z-scores: 196 windows = "
                          "5e4 samples per chain at n_lag = 256")
@@ -796,29 +818,29 @@ def main():
     split = args.precision == "mixed" and args.d % 128 == 0 and args.P % 64 == 0
     method_bytes = 4.0 * args.d * args.d + 4.0 * args.d * args.P    # R (FP32) and x - mu read once
     if split:
-        # three bf16 parts per operand, six bf16 products per FP32-equivalent
+        # two half parts per operand, three half products per FP32-equivalent
         # product: frac counts the method's 2 d^2 P flops, executed_frac the
-        # six products the matrix cores run
-        traffic = TRAFFIC.get("k_tgt_s3") if (args.d, args.P) == (4096, 256) else None
-        roofline = {"kernel": "k_tgt_s3 + k_tgt_s3_reduce (split-bf16 MFMA, FP32-equivalent; Y = R (x - mu), "
+        # three products the matrix cores run
+        traffic = TRAFFIC.get("k_tgt_h2") if (args.d, args.P) == (4096, 256) else None
+        roofline = {"kernel": "k_tgt_h2 + k_tgt_h2_reduce (two-part half MFMA, FP32-equivalent; Y = R (x - mu), "
                               "column sums of Y^2)",
-                    "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK["bf16"] / 1e12,
-                    "unit": "TFLOP/s", "frac": useful / dt / PEAK["bf16"],
+                    "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK["fp16"] / 1e12,
+                    "unit": "TFLOP/s", "frac": useful / dt / PEAK["fp16"],
                     "traffic": traffic,
                     "traffic_ratio": (traffic / method_bytes) if traffic else None,
                     "method_bytes": method_bytes,
-                    "executed_tflops": 6 * useful / dt / 1e12, "executed_frac": 6 * useful / dt / PEAK["bf16"],
+                    "executed_tflops": 3 * useful / dt / 1e12, "executed_frac": 3 * useful / dt / PEAK["fp16"],
                     "fp32_equivalent_frac": useful / dt / PEAK["fp32"],
                     "avg_us": dt * 1e6, "launches": n_t,
-                    "work": "2 d^2 P flops per step (useful); 6 x that in bf16 products executed"}
+                    "work": "2 d^2 P flops per step (useful); 3 x that in half products executed"}
     else:
         tdt = "fp64" if args.precision == "fp64" else "fp32"
         roofline = {"kernel": f"k_tgt_gauss ({tdt} MFMA, Y = R (x - mu), column sums of Y^2)",
                     "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK[tdt] / 1e12, "unit": "TFLOP/s",
                     "frac": useful / dt / PEAK[tdt], "traffic": TRAFFIC.get(f"k_tgt_gauss_{tdt}"),
                     "avg_us": dt * 1e6, "launches": n_t}
-    # the proposal contraction of the window (spec: >= 60 % of the bf16
-    # peak): frac on the triangular d (d + 1) P n_lag flops of the method,
+    # the proposal contraction of the window (aimed at 60 % or more of the
+    # bf16 peak): frac on the triangular d (d + 1) P n_lag flops of the method,
     # executed_frac on the four bf16 hi/lo products the matrix cores run
     ms_p, n_p = prof["proposal"]
     if args.precision == "mixed" and n_p:
@@ -866,11 +888,12 @@ def main():
         "psrf": psrf,
         "stopping": res["stopping"],
         "moments": res["moments"],
+        "moments_fixed_proposal": res["moments_fixed_proposal"],
     }
     if ref is not None:
         out["fp64"] = {"chain_steps_per_s": ref["chain_steps_per_s"], "ess_per_s": ref["ess_per_s"],
                        "ms_per_window": ref["ms_per_window"], "acceptance": ref["acceptance"],
-                       "moments": ref["moments"],
+                       "moments": ref["moments"], "moments_fixed_proposal": ref["moments_fixed_proposal"],
                        "stage_ms_per_window": {k: v[0] / args.profile_windows for k, v in ref["profile"].items()
                                                if v[1]}}
         out["speedup_vs_fp64"] = {"chain_steps": res["chain_steps_per_s"] / ref["chain_steps_per_s"],

@@ -50,8 +50,8 @@ struct Layout {
   size_t mlp_master, mlp_eff, mlp_grad, mlp_m, mlp_in_mean, mlp_in_scale, mlp_stats, mlp_Xs, mlp_ts, mlp_xb, mlp_tb,
       mlp_a1, mlp_h1, mlp_a2, mlp_h2, mlp_ga1, mlp_ga2, mlp_out, mlp_gout, mlp_loss, mlp_bidx, s_cur, s_new, pass1,
       slot, idx, nsurv, npass, Vs, t64, Zs;
-  // split-bf16 target (mixed form, Gaussian)
-  size_t R3, V3, Yp;
+  // two-part half target (mixed form, Gaussian)
+  size_t R2, V2, vsc, rsc, Yp;
   // PSRF accumulators
   size_t pmean, pm2, pout, merr;
   // per-chain factors and local sums (M > 1)
@@ -71,8 +71,8 @@ int target_row_blocks(const diam_config& c, const diam_target& t) {
   return t.kind == DIAM_TGT_LOGREG ? dk::logreg_row_blocks(t.n_obs) : dk::tgt_row_blocks(c.d);
 }
 
-bool use_s3(const diam_config& c, const diam_target& t) {
-  return c.precision == DIAM_MIXED && t.kind == DIAM_TGT_GAUSS && dk::tgt_s3_ok(c.d, c.P);
+bool use_h2(const diam_config& c, const diam_target& t) {
+  return c.precision == DIAM_MIXED && t.kind == DIAM_TGT_GAUSS && dk::tgt_h2_ok(c.d, c.P);
 }
 
 Layout make_layout(const diam_config& c, const diam_target& tg) {
@@ -116,10 +116,12 @@ Layout make_layout(const diam_config& c, const diam_target& tg) {
   L.status = take(sizeof(Status));
   L.proj_part = take(nl * (size_t)nch * 4 * P * 8);
   L.linv = take(dk::chol_scratch_bytes(c.d));
-  const bool s3 = use_s3(c, tg);
-  L.R3 = take(s3 ? 3 * dd * 2 : 0);
-  L.V3 = take(s3 ? 3 * dP * 2 : 0);
-  L.Yp = take(s3 ? dk::tgt_s3_scratch_bytes(c.d, c.P) : 0);
+  const bool h2 = use_h2(c, tg);
+  L.R2 = take(h2 ? 2 * dd * 2 : 0);
+  L.V2 = take(h2 ? 2 * dP * 2 : 0);
+  L.vsc = take(h2 ? d * 4 : 0);
+  L.rsc = take(h2 ? d * 8 : 0);
+  L.Yp = take(h2 ? dk::tgt_h2_scratch_bytes(c.d, c.P) : 0);
   L.pmean = take(dP * 8);
   L.pm2 = take(dP * 8);
   L.pout = take(d * 8);
@@ -188,8 +190,10 @@ struct diam_ctx {
   double *X, *Z, *lp, *zq, *lpp_part, *zq_part, *pq_part, *la, *U, *xr, *S, *m, *L, *Lnew, *h, *proj_part, *linv;
   // target
   int logreg;
-  int s3;          // split-bf16 target contraction
-  uint16_t *R3, *V3;
+  int h2;          // two-part half target contraction
+  uint16_t *R2, *V2;
+  float* vsc;
+  double* rsc;
   float* Yp;
   double prior_w;
   // PSRF
@@ -438,9 +442,11 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   c->zq_part = dptr(c, lay.zq_part);
   c->pq_part = dptr(c, lay.pq_part);
   c->logreg = tgt->kind == DIAM_TGT_LOGREG;
-  c->s3 = use_s3(*cfg, *tgt);
-  c->R3 = (uint16_t*)(c->ws + lay.R3);
-  c->V3 = (uint16_t*)(c->ws + lay.V3);
+  c->h2 = use_h2(*cfg, *tgt);
+  c->R2 = (uint16_t*)(c->ws + lay.R2);
+  c->V2 = (uint16_t*)(c->ws + lay.V2);
+  c->vsc = (float*)(c->ws + lay.vsc);
+  c->rsc = (double*)(c->ws + lay.rsc);
   c->Yp = (float*)(c->ws + lay.Yp);
   c->prior_w = c->logreg ? 1.0 / (2.0 * tgt->prior_var) : 0.0;
   c->trained = 0;
@@ -583,10 +589,10 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
     HIPCHK_INIT(dk::tgt_logreg(tgt->A, tgt->y, tgt->n_obs, (const float*)c->V, d, P, nullptr, c->lpp_part, s));
   } else {
     HIPCHK_INIT(dk::init_eval(c->prec == dk::P64, c->X, tgt->mu, c->V, c->Z, d, P, s));
-    if (c->s3) {
-      HIPCHK_INIT(dk::split3_f32((const float*)tgt->R, (long)d * d, c->R3, s));
-      HIPCHK_INIT(dk::split3_f32((const float*)c->V, (long)d * P, c->V3, s));
-      HIPCHK_INIT(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s, tgt->twist));
+    if (c->h2) {
+      HIPCHK_INIT(dk::h2_scales(c->X, tgt->mu, c->L, (const float*)tgt->R, d, P, c->vsc, c->R2, c->rsc, s));
+      HIPCHK_INIT(dk::h2_split_v(c->X, tgt->mu, c->vsc, d, P, c->V2, s));
+      HIPCHK_INIT(dk::tgt_gauss_h2(c->R2, c->V2, c->rsc, d, P, c->Yp, c->lpp_part, s, tgt->twist));
     } else {
       HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s, tgt->twist));
     }
@@ -664,7 +670,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   a.win = c->win;
   a.err = &c->status->err;
   a.v32 = c->logreg;
-  a.v3 = c->s3 ? c->V3 : nullptr;
+  a.vh = c->h2 ? c->V2 : nullptr;
+  a.vsc = c->vsc;
   a.prior_w = c->prior_w;
   a.proj = c->proj;
   a.nproj = tracing ? c->nproj : 0;
@@ -695,8 +702,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     if (c->logreg)
       HIPCHK(dk::tgt_logreg(c->tgt.A, c->tgt.y, c->tgt.n_obs, c->da_on ? c->Vs : (const float*)c->V, d, P,
                             c->da_on ? c->nsurv : nullptr, c->lpp_part, s));
-    else if (c->s3)
-      HIPCHK(dk::tgt_gauss_s3(c->R3, c->V3, d, P, c->Yp, c->lpp_part, s, c->tgt.twist));
+    else if (c->h2)
+      HIPCHK(dk::tgt_gauss_h2(c->R2, c->V2, c->rsc, d, P, c->Yp, c->lpp_part, s, c->tgt.twist));
     else
       HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s, c->tgt.twist));
     prof_end(c, ps);
@@ -945,6 +952,26 @@ static int read_status(diam_ctx* c, Status* st) {
   return DIAM_OK;
 }
 
+// Error words flagged by the steps since the last update: bit 0, a target
+// log density of +inf; bit 1, a proposal outside the half range of the
+// mixed-form Gaussian target's scaled operands (more than about 1000 spreads
+// from the target mean, where the spread is the larger of the states' largest
+// deviation and the proposal scale at the last update).  Cleared once reported.
+static int status_error(diam_ctx* c, int err) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, c->stream, c->status, 1);
+  if (err & 1) return fail(DIAM_E_TARGET, "the target log density returned +inf");
+  return fail(DIAM_E_TARGET, "a proposal left the range of the mixed-form target's scaled half operands");
+}
+
+// Mixed-form Gaussian target: coordinate and row scales of the half operands
+// from the current states and factor (kept until the next update).
+static int refresh_h2(diam_ctx* c) {
+  if (!c->h2) return DIAM_OK;
+  HIPCHK(dk::h2_scales(c->X, c->tgt.mu, c->L, (const float*)c->tgt.R, c->cfg.d, c->cfg.P, c->vsc, c->R2, c->rsc,
+                       c->stream));
+  return DIAM_OK;
+}
+
 // C = S - m m^T (eq. sampcov) assembled into Lnew and factored in place,
 // retrying on C + eps_j I, eps_j = 10^j jitter0 tr(C)/d (1 if not > 0), when a
 // pivot is not positive.  *j: -1, the level used, or jitter_tries when every
@@ -962,10 +989,7 @@ static int factor_jitter(diam_ctx* c, const double* S, const double* m, int* j) 
   if (r) return r;
   r = prof_flush(c);
   if (r) return r;
-  if (st.err) {
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
-    return fail(DIAM_E_TARGET, "the target log density returned +inf");
-  }
+  if (st.err) return status_error(c, st.err);
   *j = -1;
   if (st.info != 0) {
     const double tr = st.trace / d;
@@ -1014,10 +1038,7 @@ static int update_local(diam_ctx* c, int32_t* jitter_used) {
   if (r) return r;
   r = prof_flush(c);
   if (r) return r;
-  if (st.err) {
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
-    return fail(DIAM_E_TARGET, "the target log density returned +inf");
-  }
+  if (st.err) return status_error(c, st.err);
   int jmax = -1, failed = 0;
   for (int p = 0; p < P; ++p) {
     if (info[p] == 0) continue;
@@ -1074,11 +1095,8 @@ static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
     if (r) return r;
     r = prof_flush(c);
     if (r) return r;
-    if (st.err) {
-      hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, c->status, 1);
-      return fail(DIAM_E_TARGET, "the target log density returned +inf");
-    }
-    return DIAM_OK;
+    if (st.err) return status_error(c, st.err);
+    return refresh_h2(c);
   }
   if (c->cfg.M > 1 && c->m_int > 0) return update_local(c, jitter_used);
   int j = -1;
@@ -1096,8 +1114,9 @@ static int update_impl(diam_ctx* c, int32_t* jitter_used, bool refactor) {
   HIPCHK(dk::round_factor(c->prec, c->L, c->Llow, d, s));
   HIPCHK(hipMemcpyAsync(c->xr, c->m, d * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(dk::trsm_whiten(c->L, c->X, c->xr, c->Z, c->zq + (long)c->cur * P, c->linv, d, P, s));
+  const int r2 = refresh_h2(c);
   prof_end(c, ps);
-  return DIAM_OK;
+  return r2;
 }
 
 extern "C" int diam_update_proposal(diam_ctx* c, int32_t* jitter_used) {

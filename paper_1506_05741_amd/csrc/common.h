@@ -2,10 +2,11 @@
 //
 // * MFMA wrappers with their lane layouts (64-wide wavefront):
 //     f64 16x16x4 and f32 16x16x4:  a = A[l%16][l/16], b = B[l/16][l%16]
-//     bf16 16x16x32:                a[e] = A[l%16][8*(l/16)+e], b[e] = B[8*(l/16)+e][l%16]
+//     bf16 and f16 16x16x32:        a[e] = A[l%16][8*(l/16)+e], b[e] = B[8*(l/16)+e][l%16]
 //     result f32 and bf16:          c[r] = C[4*(l/16)+r][l%16]
 //     result f64:                   c[r] = C[4*r+l/16][l%16]
-// * bf16 conversion (round to nearest even) and the hi/lo split.
+// * bf16 conversion (round to nearest even) and the hi/lo split; the two-part
+//   IEEE half split.
 // * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals.
 // * deterministic wavefront reductions.
 #pragma once
@@ -15,6 +16,7 @@
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16;
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -29,6 +31,19 @@ DEV f4_t mfma_f32(float a, float b, f4_t c) {
 }
 DEV f4_t mfma_bf16(bf8_t a, bf8_t b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+DEV f4_t mfma_f16(h8_t a, h8_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// ---- IEEE half precision ------------------------------------------------------
+// hi = f16(v), lo = f16(v - hi) (round to nearest even): hi + lo carries 22
+// significant bits of v when |v| lies in the normal range of both parts.
+DEV void split_f16(double v, u16& hi, u16& lo) {
+  const _Float16 h = (_Float16)(float)v;
+  const _Float16 l = (_Float16)(float)(v - (double)h);
+  hi = __builtin_bit_cast(u16, h);
+  lo = __builtin_bit_cast(u16, l);
 }
 
 // ---- bfloat16 -------------------------------------------------------------

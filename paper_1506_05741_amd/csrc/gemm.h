@@ -779,23 +779,23 @@ DEV void p_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long lda,
   }
 }
 
-// Three-part split BF16 engine (FP32-equivalent products).  Both operands
-// are given as x = x0 + x1 + x2 with bf16 parts of decreasing weight (8
-// significant bits each, 24 together); per 32-deep K slice the six products
-// x0 y0, x0 y1, x1 y0, x0 y2, x1 y1, x2 y0 (everything down to relative
-// weight 2^-16) accumulate in FP32, which leaves an error of the order of
-// FP32 rounding.  Direct-to-LDS ring as h_gemm; K range [kbeg, kend), both
-// multiples of 32; parts at fixed element strides dA, dB; unguarded.
+// Two-part IEEE half engine (the mixed form's target contraction).  Both
+// operands are given as x = x0 + x1 with f16 parts (11 significant bits
+// each, scaled by powers of two into the f16 range by the caller); per 32-deep
+// K slice the three products x1 y0, x0 y1, x0 y0 (everything down to relative
+// weight 2^-22) accumulate in FP32, the accuracy of an FP32 product.
+// Direct-to-LDS ring as h_gemm; K range [kbeg, kend), both multiples of 32;
+// parts at fixed element strides dA, dB; unguarded.
 template <int BM, int BN, int ST>
-constexpr int s3_lds_elems() { return ST * 3 * (BM + BN) * HBK; }
+constexpr int h2_lds_elems() { return ST * 2 * (BM + BN) * HBK; }
 
 template <int BM, int BN, int WGM, int WGN, int ST>
-DEV void s3_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, long lda, const u16* __restrict__ B,
+DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, long lda, const u16* __restrict__ B,
                  long dB, long ldb, int i0, int j0, int kbeg, int kend, u16* lds) {
   typedef WFrag<BM, BN, WGM, WGN> F;
   constexpr int NW = WGM * WGN;
-  constexpr int SA = BM * HBK, SB = BN * HBK, SS = 3 * (SA + SB);
-  constexpr int BLK_A = BM / 16, BLK_B = BN / 16, NBLK = 3 * (BLK_A + BLK_B);
+  constexpr int SA = BM * HBK, SB = BN * HBK, SS = 2 * (SA + SB);
+  constexpr int BLK_A = BM / 16, BLK_B = BN / 16, NBLK = 2 * (BLK_A + BLK_B);
   static_assert(NBLK % NW == 0, "copy blocks must divide among the waves");
   constexpr int LPW = NBLK / NW;
   const int nk = (kend - kbeg) / HBK;
@@ -806,12 +806,12 @@ DEV void s3_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
       const int blk = w * LPW + q;
-      if (blk < 3 * BLK_A) {
+      if (blk < 2 * BLK_A) {
         const int h = blk / BLK_A, b = blk % BLK_A;
         h_copy_block(A + h * dA, lda, i0 + b * 16, k0, st + h * SA + b * 512);
       } else {
-        const int bb = blk - 3 * BLK_A, h = bb / BLK_B, b = bb % BLK_B;
-        h_copy_block(B + h * dB, ldb, j0 + b * 16, k0, st + 3 * SA + h * SB + b * 512);
+        const int bb = blk - 2 * BLK_A, h = bb / BLK_B, b = bb % BLK_B;
+        h_copy_block(B + h * dB, ldb, j0 + b * 16, k0, st + 2 * SA + h * SB + b * 512);
       }
     }
   };
@@ -824,34 +824,29 @@ DEV void s3_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
     asm volatile("s_barrier" ::: "memory");
     if (kt + ST - 1 < nk) issue(kt + ST - 1);
     const u16* st = lds + (kt % ST) * SS;
-    bf8_t a0[F::FM], a1[F::FM], a2[F::FM], b0[F::FN], b1[F::FN], b2[F::FN];
+    h8_t a0[F::FM], a1[F::FM], b0[F::FN], b1[F::FN];
 #pragma unroll
     for (int m = 0; m < F::FM; ++m) {
       const int r = wm * (BM / WGM) + m * 16 + lr;
       const int o = r * HBK + ((lk ^ hswz(r)) * 8);
-      a0[m] = *(const bf8_t*)(st + o);
-      a1[m] = *(const bf8_t*)(st + SA + o);
-      a2[m] = *(const bf8_t*)(st + 2 * SA + o);
+      a0[m] = *(const h8_t*)(st + o);
+      a1[m] = *(const h8_t*)(st + SA + o);
     }
 #pragma unroll
     for (int n = 0; n < F::FN; ++n) {
       const int r = wn * (BN / WGN) + n * 16 + lr;
       const int o = r * HBK + ((lk ^ hswz(r)) * 8);
-      b0[n] = *(const bf8_t*)(st + 3 * SA + o);
-      b1[n] = *(const bf8_t*)(st + 3 * SA + SB + o);
-      b2[n] = *(const bf8_t*)(st + 3 * SA + 2 * SB + o);
+      b0[n] = *(const h8_t*)(st + 2 * SA + o);
+      b1[n] = *(const h8_t*)(st + 2 * SA + SB + o);
     }
 #pragma unroll
     for (int m = 0; m < F::FM; ++m)
 #pragma unroll
       for (int n = 0; n < F::FN; ++n) {
         // smallest terms first
-        f.c[m][n] = mfma_bf16(a2[m], b0[n], f.c[m][n]);
-        f.c[m][n] = mfma_bf16(a1[m], b1[n], f.c[m][n]);
-        f.c[m][n] = mfma_bf16(a0[m], b2[n], f.c[m][n]);
-        f.c[m][n] = mfma_bf16(a1[m], b0[n], f.c[m][n]);
-        f.c[m][n] = mfma_bf16(a0[m], b1[n], f.c[m][n]);
-        f.c[m][n] = mfma_bf16(a0[m], b0[n], f.c[m][n]);
+        f.c[m][n] = mfma_f16(a1[m], b0[n], f.c[m][n]);
+        f.c[m][n] = mfma_f16(a0[m], b1[n], f.c[m][n]);
+        f.c[m][n] = mfma_f16(a0[m], b0[n], f.c[m][n]);
       }
   }
 }

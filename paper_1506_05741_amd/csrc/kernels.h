@@ -25,15 +25,22 @@ inline int step_chunks(int d) { return (d + STEP_RCH - 1) / STEP_RCH; }
 // y gains twist[2k+1] * y_{2k}^2 before it is squared.
 hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, double* part, hipStream_t s,
                      const double* twist = nullptr);
-// Mixed form, Gaussian: the same partials from three-part bf16 splits of R
-// and V (FP32-equivalent products); needs tgt_s3_ok(d, P); Yp scratch of
-// tgt_s3_scratch_bytes.  split3_f32 writes the parts of n floats at dst,
-// dst + n, dst + 2n.
-bool tgt_s3_ok(int d, int P);
-size_t tgt_s3_scratch_bytes(int d, int P);
-hipError_t split3_f32(const float* src, long n, uint16_t* dst, hipStream_t s);
-hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s,
-                        const double* twist = nullptr);
+// Mixed form, Gaussian: the same partials from two-part half splits of
+// scaled R and V (FP32-equivalent products); needs tgt_h2_ok(d, P) and Yp
+// scratch of tgt_h2_scratch_bytes.  h2_scales computes the coordinate scales
+// vsc (d floats) from the states X (d x P) about mu and the lower factor L
+// (d x d column-major FP64), then the row scales rsc (d FP64) and both parts
+// of the scaled R (FP32 row-major) into R2 (2 d^2 halves); h2_split_v writes
+// both parts of the scaled X - mu into V2 (2 d P halves).  The step kernel
+// writes V2 itself (vh, vsc) after that.
+bool tgt_h2_ok(int d, int P);
+size_t tgt_h2_scratch_bytes(int d, int P);
+hipError_t h2_scales(const double* X, const double* mu, const double* L, const float* R, int d, int P, float* vsc,
+                     uint16_t* R2, double* rsc, hipStream_t s);
+hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d, int P, uint16_t* V2,
+                      hipStream_t s);
+hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rsc, int d, int P, float* Yp,
+                        double* part, hipStream_t s, const double* twist = nullptr);
 // Logistic: part[p][rb] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
 // (A n_obs x d row-major FP32, V d x P FP32); columns >= *nact skipped.
 int logreg_row_blocks(long n_obs);
@@ -146,7 +153,8 @@ struct StepArgs {
   const double* u2;                       // P
   int da_resid;                           // residual surrogate r(x) - |z|^2/(2 alpha^2)
   int fuse_dec;                           // set by step(): the update kernel takes the decision itself
-  uint16_t* v3;                           // non-null: write V as three bf16 parts (d x P each) instead
+  uint16_t* vh;                           // non-null: write V as two half parts of (x - mu) vsc (d x P each) instead
+  const float* vsc;                       // d: power-of-two coordinate scales for vh
   int ldv;                                // leading dimension of V (0: d)
   int ldw;                                // leading dimension of Xi and W (0: d)
   int32_t* wacc;                          // P: accepted proposals since the last update (optional)

@@ -70,46 +70,127 @@ __global__ __launch_bounds__(512) void k_tgt_gauss(const T* __restrict__ R, cons
   tgt_gauss_tile<T, BK, 64, 64, 2>(R, V, d, P, blockIdx.x, blockIdx.y, part, gridDim.x, twist);
 }
 
-// ---- split-BF16 target (mixed form): Y = R V with both operands in three
-// bf16 parts (FP32-equivalent products, see s3_gemm), 64 x 64 tiles, K split
-// in S3_KSPLIT ranges whose FP32 partial Y are summed in FP64 by the
-// reduction, which squares and sums 64-row blocks (chain-major partials).
-constexpr int S3_KSPLIT = 4;
+// ---- two-part half target (mixed form): Y = R V with both operands split
+// into two IEEE half parts (products with the accuracy of FP32, see h2_gemm).
+// Half precision needs operands in its range, so both are scaled by powers of
+// two, exactly: coordinate k of x - mu by 2^s_k (vsc), chosen from the
+// largest deviation of the current states and the current factor's row norm
+// so that values up to 1024 times those stay finite (the step kernel flags
+// any beyond); row i of R by
+// 2^(a_i - s_k) so that its largest entry lies in [2^14, 2^15).  Then
+// (R' V')_i = 2^a_i (R V)_i and the reduction multiplies by 2^-a_i (rsc).
+// 64- or 128-wide tiles, K split in H2_KSPLIT ranges whose FP32 partial Y are
+// summed in FP64 by the reduction, which squares and sums 64-row blocks
+// (chain-major partials).
+constexpr int H2_KSPLIT = 4;
+// scaled V entries at or above this magnitude round to infinity in half
+constexpr double H2_RANGE = 65520.0;
 
-DEV void split3(float x, u16& h, u16& m, u16& l) {
-  h = f32_to_bf16_bits(x);
-  const float r1 = x - bf16_bits_to_f32(h);
-  m = f32_to_bf16_bits(r1);
-  const float r2 = r1 - bf16_bits_to_f32(m);
-  l = f32_to_bf16_bits(r2);
+// vsc[k] = 2^(6 - e_k) with sigma_k < 2^e_k (frexp), sigma_k the larger of
+// max_p |x_kp - mu_k| and the 2-norm of row k of the lower factor L
+// (column-major), e_k clamped to [-100, 100].  64 rows per block, one per
+// lane; the 16 waves split the columns of L and the chains.
+__global__ __launch_bounds__(1024) void k_h2_vscale(const double* __restrict__ X, const double* __restrict__ mu,
+                                                    const double* __restrict__ L, int d, int P,
+                                                    float* __restrict__ vsc) {
+  __shared__ double sdev[16][64], srn[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  double dev = 0.0, rn = 0.0;
+  if (k < d) {
+    const double mk = mu[k];
+    for (int p = w; p < P; p += 16) dev = fmax(dev, fabs(X[k + (long)p * d] - mk));
+    for (int j = w; j <= k; j += 16) {
+      const double l = L[k + (long)j * d];
+      rn = __fma_rn(l, l, rn);
+    }
+  }
+  sdev[w][lane] = dev;
+  srn[w][lane] = rn;
+  __syncthreads();
+  if (w != 0 || k >= d) return;
+  for (int q = 1; q < 16; ++q) {
+    dev = fmax(dev, sdev[q][lane]);
+    rn += srn[q][lane];
+  }
+  const double sig = fmax(dev, sqrt(rn));
+  int e = 0;
+  if (sig > 0.0 && isfinite(sig)) {
+    frexp(sig, &e);  // sig < 2^e
+    e = 6 - e;
+  }
+  e = e < -100 ? -100 : (e > 100 ? 100 : e);
+  vsc[k] = ldexpf(1.0f, e);
 }
 
-__global__ __launch_bounds__(256) void k_split3(const float* __restrict__ src, long n, u16* __restrict__ dst) {
+// Row i of R: a_i from the largest |R_ik / vsc[k]|, then both half parts of
+// R_ik 2^a_i / vsc[k] into R2 (d x d row-major each) and rsc[i] = 2^-a_i.
+__global__ __launch_bounds__(256) void k_h2_split_r(const float* __restrict__ R, const float* __restrict__ vsc, int d,
+                                                    u16* __restrict__ R2, double* __restrict__ rsc) {
+  __shared__ float red[4];
+  const int i = blockIdx.x, t = threadIdx.x;
+  const float* row = R + (long)i * d;
+  float mx = 0.0f;
+  for (int k = t; k < d; k += 256) mx = fmaxf(mx, fabsf(row[k] / vsc[k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((t & 63) == 0) red[t >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int e = 0;
+  if (mx > 0.0f && isfinite(mx)) {
+    frexpf(mx, &e);  // mx < 2^e
+    e = 15 - e;
+  }
+  const long n = (long)d * d;
+  for (int k = t; k < d; k += 256) {
+    const double v = ldexp((double)row[k] / (double)vsc[k], e);
+    u16 h, l;
+    split_f16(v, h, l);
+    R2[(long)i * d + k] = h;
+    R2[n + (long)i * d + k] = l;
+  }
+  if (t == 0) rsc[i] = ldexp(1.0, -e);
+}
+
+// Both half parts of (x - mu) vsc into V2 (d x P each, column-major).
+__global__ __launch_bounds__(256) void k_h2_split_v(const double* __restrict__ X, const double* __restrict__ mu,
+                                                    const float* __restrict__ vsc, int d, long n,
+                                                    u16* __restrict__ V2) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
-  u16 h, m, l;
-  split3(src[e], h, m, l);
-  dst[e] = h;
-  dst[n + e] = m;
-  dst[2 * n + e] = l;
+  const int k = (int)(e % d);
+  u16 h, l;
+  split_f16((X[e] - mu[k]) * (double)vsc[k], h, l);
+  V2[e] = h;
+  V2[n + e] = l;
 }
 
-hipError_t split3_f32(const float* src, long n, uint16_t* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_split3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, n, dst);
+hipError_t h2_scales(const double* X, const double* mu, const double* L, const float* R, int d, int P, float* vsc,
+                     uint16_t* R2, double* rsc, hipStream_t s) {
+  hipLaunchKernelGGL(k_h2_vscale, dim3((unsigned)((d + 63) / 64)), dim3(1024), 0, s, X, mu, L, d, P, vsc);
+  hipLaunchKernelGGL(k_h2_split_r, dim3(d), dim3(256), 0, s, R, (const float*)vsc, d, (u16*)R2, rsc);
+  return hipGetLastError();
+}
+
+hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d, int P, uint16_t* V2,
+                      hipStream_t s) {
+  const long n = (long)d * P;
+  hipLaunchKernelGGL(k_h2_split_v, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, mu, vsc, d, n, (u16*)V2);
   return hipGetLastError();
 }
 
 template <int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_s3(const u16* __restrict__ R3, const u16* __restrict__ V3,
+__global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict__ R2, const u16* __restrict__ V2,
                                                           int d, int P, float* __restrict__ Yp) {
   constexpr int ST = 2;
   typedef WFrag<BM, BN, WGM, WGN> F;
-  __shared__ __attribute__((aligned(1024))) u16 lds[s3_lds_elems<BM, BN, ST>()];
+  __shared__ __attribute__((aligned(1024))) u16 lds[h2_lds_elems<BM, BN, ST>()];
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
-  const int kl = d / S3_KSPLIT;
+  const int kl = d / H2_KSPLIT;
   F f;
   f.zero();
-  s3_gemm<BM, BN, WGM, WGN, ST>(f, R3, (long)d * d, d, V3, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl, lds);
+  h2_gemm<BM, BN, WGM, WGN, ST>(f, R2, (long)d * d, d, V2, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl, lds);
   float* Y = Yp + (long)ks * P * d;
 #pragma unroll
   for (int m = 0; m < F::FM; ++m)
@@ -122,17 +203,20 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_s3(const u16* __restrict
     }
 }
 
-// part[j][rb] = -1/2 sum over rows of block rb of (sum_s Yp[s])^2, one wave per (j, rb)
-__global__ __launch_bounds__(256) void k_tgt_s3_reduce(const float* __restrict__ Yp, int d, int P, int nrb,
-                                                       double* __restrict__ part, const double* __restrict__ twist) {
+// part[j][rb] = -1/2 sum over rows of block rb of (rsc_i sum_s Yp[s])^2, one wave per (j, rb)
+__global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__ Yp, const double* __restrict__ rsc,
+                                                       int d, int P, int nrb, double* __restrict__ part,
+                                                       const double* __restrict__ twist) {
   const int lane = threadIdx.x & 63;
   const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wid >= (long)P * nrb) return;
   const int j = (int)(wid / nrb), rb = (int)(wid % nrb);
   const int i = rb * 64 + lane;
   double y = 0.0;
-  if (i < d)
-    for (int s = 0; s < S3_KSPLIT; ++s) y += (double)Yp[((long)s * P + j) * d + i];
+  if (i < d) {
+    for (int s = 0; s < H2_KSPLIT; ++s) y += (double)Yp[((long)s * P + j) * d + i];
+    y *= rsc[i];
+  }
   if (twist) {
     // twisted target: row 2k+1 (odd lane, as blocks start at even rows) gets c y_{2k}^2
     const double yp = __shfl_xor(y, 1, 64);
@@ -142,23 +226,23 @@ __global__ __launch_bounds__(256) void k_tgt_s3_reduce(const float* __restrict__
   if (lane == 0) part[(long)j * nrb + rb] = -0.5 * q;
 }
 
-bool tgt_s3_ok(int d, int P) { return d % (S3_KSPLIT * 32) == 0 && d % 64 == 0 && P % 64 == 0; }
+bool tgt_h2_ok(int d, int P) { return d % (H2_KSPLIT * 32) == 0 && d % 64 == 0 && P % 64 == 0; }
 
-size_t tgt_s3_scratch_bytes(int d, int P) { return (size_t)S3_KSPLIT * d * P * sizeof(float); }
+size_t tgt_h2_scratch_bytes(int d, int P) { return (size_t)H2_KSPLIT * d * P * sizeof(float); }
 
-hipError_t tgt_gauss_s3(const uint16_t* R3, const uint16_t* V3, int d, int P, float* Yp, double* part, hipStream_t s,
-                        const double* twist) {
-  // 128 x 128 tiles on 8 waves where they fit (measured 1.45x the rate of 64 x 64)
+hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rsc, int d, int P, float* Yp,
+                        double* part, hipStream_t s, const double* twist) {
+  // 128 x 128 tiles on 8 waves where they fit
   if (d % 128 == 0 && P % 128 == 0)
-    hipLaunchKernelGGL((k_tgt_s3<128, 128, 4, 2>), dim3(d / 128, P / 128, S3_KSPLIT), dim3(512), 0, s,
-                       (const u16*)R3, (const u16*)V3, d, P, Yp);
+    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
+                       (const u16*)R2, (const u16*)V2, d, P, Yp);
   else
-    hipLaunchKernelGGL((k_tgt_s3<64, 64, 2, 2>), dim3(d / 64, P / 64, S3_KSPLIT), dim3(256), 0, s, (const u16*)R3,
-                       (const u16*)V3, d, P, Yp);
+    hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s, (const u16*)R2,
+                       (const u16*)V2, d, P, Yp);
   const int nrb = tgt_row_blocks(d);
   const long waves = (long)P * nrb;
-  hipLaunchKernelGGL(k_tgt_s3_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, d, P, nrb,
-                     part, twist);
+  hipLaunchKernelGGL(k_tgt_h2_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, rsc, d,
+                     P, nrb, part, twist);
   return hipGetLastError();
 }
 
@@ -1668,13 +1752,13 @@ DEV void step_body(const StepArgs& a, int ch, int nch, int pq) {
     }
     if (a.do_propose) {
       const double xp = propose1(xr[q], xv, a.rho, xn[q]);
-      if (a.v3) {
-        u16 h, m, l;
-        split3((float)(xp - mu[q]), h, m, l);
-        const long n = (long)d * P;
-        a.v3[e] = h;
-        a.v3[n + e] = m;
-        a.v3[2 * n + e] = l;
+      if (a.vh) {
+        u16 h, l;
+        const double sv = (xp - mu[q]) * (double)a.vsc[i];
+        if (fabs(sv) >= H2_RANGE) atomicOr(a.err, 2);
+        split_f16(sv, h, l);
+        a.vh[e] = h;
+        a.vh[(long)d * P + e] = l;
       } else {
         const long ev = i + (long)p * (a.ldv ? a.ldv : d);
         if (a.v32) ((float*)a.V)[ev] = (float)(xp - mu[q]);
@@ -1951,14 +2035,15 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
     }
     if (a.do_propose) {
       const double xp0 = propose1(r0, x0, a.rho, n0), xp1 = propose1(r1, x1, a.rho, n1);
-      if (a.v3) {
-        u16 h0, m0_, l0, h1, m1_, l1;
-        split3((float)(xp0 - m0), h0, m0_, l0);
-        split3((float)(xp1 - m1), h1, m1_, l1);
-        const long n = (long)d * P;
-        *(uint32_t*)(a.v3 + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        *(uint32_t*)(a.v3 + n + e) = (uint32_t)m0_ | ((uint32_t)m1_ << 16);
-        *(uint32_t*)(a.v3 + 2 * n + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      if (a.vh) {
+        u16 h0, l0, h1, l1;
+        const float2 sv = *(const float2*)(a.vsc + i);
+        const double s0 = (xp0 - m0) * (double)sv.x, s1 = (xp1 - m1) * (double)sv.y;
+        if (fmax(fabs(s0), fabs(s1)) >= H2_RANGE) atomicOr(a.err, 2);
+        split_f16(s0, h0, l0);
+        split_f16(s1, h1, l1);
+        *(uint32_t*)(a.vh + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        *(uint32_t*)(a.vh + (long)d * P + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
       } else {
         const long ev = i + (long)p * (a.ldv ? a.ldv : d);
         if (a.v32 || PR != P64) *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - m0), (float)(xp1 - m1));

@@ -1,7 +1,7 @@
 """Full-size checks.  The mixed form at the benchmark size: d = 4096, P = 256, n_lag = 256,
 the Gaussian target of seed 2 with the warm start (the workload bench.py
 times, in the same launch configuration: internal Philox normals and
-uniforms, the 256 x 256 paired proposal tiles, the 128 x 128 split-bf16
+uniforms, the 256 x 256 paired proposal tiles, the 128 x 128 two-part half
 target tiles, the plain-bf16 scatter, the fused blocked Cholesky).
 
 At this size the oracle cannot run whole windows, so outputs are checked one
@@ -415,7 +415,7 @@ def test_full_size_batch():
 
 def test_full_size_twisted_log_density(setup):
     """The twisted-target pairing at the benchmark size and launch
-    configuration (split-bf16 128 x 128 tiles, K split in 4, the reduction
+    configuration (two-part half 128 x 128 tiles, K split in 4, the reduction
     that applies the twist): log pi of sampled chains against FP64, with a
     twist weight on every odd row."""
     t, x0, s, N0 = setup

@@ -58,7 +58,7 @@ S_TOL = {"fp32": 1e-5, "mixed": 5e-3}
 @pytest.mark.parametrize("prec,P,d,tseed", [("fp32", 32, 256, 3), ("mixed", 32, 256, 3), ("mixed", 64, 256, 3),
                                             ("mixed", 128, 256, 3), ("fp32", 64, 1024, 1), ("mixed", 64, 1024, 1)])
 def test_per_stage_error_against_fp64(prec, P, d, tseed):
-    # P = 64 and 128 take the mixed form's split-bf16 target contraction (64 and
+    # P = 64 and 128 take the mixed form's two-part half target contraction (64 and
     # 128 tiles); d = 1024, seed 1, P = 64 is the d = 1024 configuration's target
     n_lag = 16
     t, x0, s = make(d, P, n_lag, prec, tseed=tseed)
@@ -124,7 +124,7 @@ def _moments_ok(t, X, k_sigma=4.0):
 
 @pytest.mark.parametrize("prec,d,P", [("fp64", 32, 256), ("fp32", 32, 256), ("mixed", 32, 256), ("mixed", 128, 64)])
 def test_posterior_moments_within_4se(prec, d, P):
-    # (mixed, 128, 64) runs the split-bf16 target contraction
+    # (mixed, 128, 64) runs the two-part half target contraction
     n_lag, windows = 50, 40
     t, x0, s = make(d, P, n_lag, prec, tseed=0, seed=7)
     ends = []
