@@ -61,7 +61,10 @@ typedef enum {
   DIAM_E_STATE = -2,  /* call out of order (see each call) */
   DIAM_E_HIP = -3,    /* a HIP runtime call or kernel launch failed */
   DIAM_E_NOT_PD = -4, /* Cholesky failed at every jitter level; previous factor kept */
-  DIAM_E_TARGET = -5  /* the target log density returned +inf */
+  DIAM_E_TARGET = -5  /* the target log density returned +inf, or (mixed form, Gaussian
+                         target) a proposal left the half range of the scaled
+                         operands: more than about 1000 spreads from the mean,
+                         the spread taken at the last update */
 } diam_status;
 
 typedef enum { DIAM_FP64 = 0, DIAM_FP32 = 1, DIAM_MIXED = 2 } diam_precision;
@@ -244,7 +247,14 @@ int diam_merge_moments(diam_ctx* ctx);
  * m^{p,glob} and z_p = A_p^-1 (x_p - x_ref_p); a chain failing every level
  * keeps its pair (DIAM_E_NOT_PD is returned, the others are updated);
  * jitter_used gets the largest level used.  After a global merge the update
- * above runs and, on success, all chains share the new factor again. */
+ * above runs and, on success, all chains share the new factor again.
+ * Errors flagged by the steps since the last update come first, as
+ * DIAM_E_TARGET (the update is then not made, the flag is cleared).  Mixed
+ * form with a Gaussian target: the update also chooses the power-of-two
+ * scales that bring x - mu and R into the half range of the target
+ * contraction (coordinate k by 2^(6 - e_k), sigma_k < 2^e_k the larger of the
+ * states' largest |x_k - mu_k| and the factor's row norm; each row of R to a
+ * largest entry in [2^14, 2^15)). */
 int diam_update_proposal(diam_ctx* ctx, int32_t* jitter_used);
 
 /* Warm start: replace the global moments by (S0, m0) with pseudo-count N0

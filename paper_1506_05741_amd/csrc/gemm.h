@@ -673,7 +673,8 @@ DEV void h_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, 
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's copies of slice kt are done when at most the later
     // slices' copies are outstanding; the barrier then covers all waves
-    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+    // stage kt has landed once at most the later stages' copies are pending
+    if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     asm volatile("s_barrier" ::: "memory");
     // the ring slot refilled here was last read before this barrier
@@ -752,7 +753,8 @@ DEV void p_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long lda,
   asm volatile("s_barrier" ::: "memory");
   for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+    // stage kt has landed once at most the later stages' copies are pending
+    if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     asm volatile("s_barrier" ::: "memory");
     if (kt + ST - 1 < nk) issue(kt + ST - 1);
@@ -784,13 +786,29 @@ DEV void p_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long lda,
 // each, scaled by powers of two into the f16 range by the caller); per 32-deep
 // K slice the three products x1 y0, x0 y1, x0 y0 (everything down to relative
 // weight 2^-22) accumulate in FP32, the accuracy of an FP32 product.
-// Direct-to-LDS ring as h_gemm; K range [kbeg, kend), both multiples of 32;
-// parts at fixed element strides dA, dB; unguarded.
+// A (rows x K) comes pre-tiled: each part (at element stride dA) is a
+// sequence of 1 KB blocks of 16 rows x 32 columns, block (row block rb,
+// column block kb) at ((kb * arb) + rb) * 512 with arb = rows / 16, and inside
+// a block element (r, k) at r * 32 + ((k / 8) ^ hswz(r)) * 8 + k % 8: the
+// order in which h_copy_block leaves a block in LDS, so one tile slice is a
+// run of contiguous 1 KB blocks copied without address arithmetic.  B is
+// row-major (rows = chains, K contiguous) at leading dimension ldb as in
+// h_gemm.  Direct-to-LDS ring of ST stages; K range [kbeg, kend), both
+// multiples of 32; unguarded.
 template <int BM, int BN, int ST>
 constexpr int h2_lds_elems() { return ST * 2 * (BM + BN) * HBK; }
 
+DEV long h2_tile_index(int r, int k, int arb) {
+  return ((long)(k >> 5) * arb + (r >> 4)) * 512 + (r & 15) * 32 + ((((k & 31) >> 3) ^ hswz(r)) << 3) + (k & 7);
+}
+
+DEV void h_copy_flat(const u16* __restrict__ src, u16* lds_block) {
+  const int lane = threadIdx.x & 63;
+  __builtin_amdgcn_global_load_lds((const void*)(src + lane * 8), (lds_ptr_t)lds_block, 16, 0, 0);
+}
+
 template <int BM, int BN, int WGM, int WGN, int ST>
-DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, long lda, const u16* __restrict__ B,
+DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, int arb, const u16* __restrict__ B,
                  long dB, long ldb, int i0, int j0, int kbeg, int kend, u16* lds) {
   typedef WFrag<BM, BN, WGM, WGN> F;
   constexpr int NW = WGM * WGN;
@@ -808,7 +826,7 @@ DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
       const int blk = w * LPW + q;
       if (blk < 2 * BLK_A) {
         const int h = blk / BLK_A, b = blk % BLK_A;
-        h_copy_block(A + h * dA, lda, i0 + b * 16, k0, st + h * SA + b * 512);
+        h_copy_flat(A + h * dA + ((long)(k0 >> 5) * arb + (i0 >> 4) + b) * 512, st + h * SA + b * 512);
       } else {
         const int bb = blk - 2 * BLK_A, h = bb / BLK_B, b = bb % BLK_B;
         h_copy_block(B + h * dB, ldb, j0 + b * 16, k0, st + 2 * SA + h * SB + b * 512);
@@ -819,7 +837,8 @@ DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
   const int lr = lane & 15, lk = lane >> 4;
   for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+    // stage kt has landed once at most the later stages' copies are pending
+    if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     asm volatile("s_barrier" ::: "memory");
     if (kt + ST - 1 < nk) issue(kt + ST - 1);

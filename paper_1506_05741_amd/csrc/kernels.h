@@ -30,7 +30,8 @@ hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, doub
 // scratch of tgt_h2_scratch_bytes.  h2_scales computes the coordinate scales
 // vsc (d floats) from the states X (d x P) about mu and the lower factor L
 // (d x d column-major FP64), then the row scales rsc (d FP64) and both parts
-// of the scaled R (FP32 row-major) into R2 (2 d^2 halves); h2_split_v writes
+// of the scaled R (FP32 row-major) into R2 (2 d^2 halves, each part in
+// 16 x 32 blocks ordered by column block, then row block); h2_split_v writes
 // both parts of the scaled X - mu into V2 (2 d P halves).  The step kernel
 // writes V2 itself (vh, vsc) after that.
 bool tgt_h2_ok(int d, int P);

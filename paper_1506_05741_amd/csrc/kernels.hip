@@ -124,7 +124,8 @@ __global__ __launch_bounds__(1024) void k_h2_vscale(const double* __restrict__ X
 }
 
 // Row i of R: a_i from the largest |R_ik / vsc[k]|, then both half parts of
-// R_ik 2^a_i / vsc[k] into R2 (d x d row-major each) and rsc[i] = 2^-a_i.
+// R_ik 2^a_i / vsc[k] into R2 (d x d each, in the tiled order h2_gemm reads,
+// h2_tile_index) and rsc[i] = 2^-a_i.
 __global__ __launch_bounds__(256) void k_h2_split_r(const float* __restrict__ R, const float* __restrict__ vsc, int d,
                                                     u16* __restrict__ R2, double* __restrict__ rsc) {
   __shared__ float red[4];
@@ -143,12 +144,14 @@ __global__ __launch_bounds__(256) void k_h2_split_r(const float* __restrict__ R,
     e = 15 - e;
   }
   const long n = (long)d * d;
+  const int arb = d / 16;
   for (int k = t; k < d; k += 256) {
     const double v = ldexp((double)row[k] / (double)vsc[k], e);
     u16 h, l;
     split_f16(v, h, l);
-    R2[(long)i * d + k] = h;
-    R2[n + (long)i * d + k] = l;
+    const long q = h2_tile_index(i, k, arb);
+    R2[q] = h;
+    R2[n + q] = l;
   }
   if (t == 0) rsc[i] = ldexp(1.0, -e);
 }
@@ -180,17 +183,17 @@ hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d
   return hipGetLastError();
 }
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, int ST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict__ R2, const u16* __restrict__ V2,
                                                           int d, int P, float* __restrict__ Yp) {
-  constexpr int ST = 2;
   typedef WFrag<BM, BN, WGM, WGN> F;
   __shared__ __attribute__((aligned(1024))) u16 lds[h2_lds_elems<BM, BN, ST>()];
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
   const int kl = d / H2_KSPLIT;
   F f;
   f.zero();
-  h2_gemm<BM, BN, WGM, WGN, ST>(f, R2, (long)d * d, d, V2, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl, lds);
+  h2_gemm<BM, BN, WGM, WGN, ST>(f, R2, (long)d * d, d / 16, V2, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl,
+                                lds);
   float* Y = Yp + (long)ks * P * d;
 #pragma unroll
   for (int m = 0; m < F::FM; ++m)
@@ -234,11 +237,11 @@ hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rs
                         double* part, hipStream_t s, const double* twist) {
   // 128 x 128 tiles on 8 waves where they fit
   if (d % 128 == 0 && P % 128 == 0)
-    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
+    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2, 3>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
   else
-    hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s, (const u16*)R2,
-                       (const u16*)V2, d, P, Yp);
+    hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2, 3>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s,
+                       (const u16*)R2, (const u16*)V2, d, P, Yp);
   const int nrb = tgt_row_blocks(d);
   const long waves = (long)P * nrb;
   hipLaunchKernelGGL(k_tgt_h2_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, rsc, d,

@@ -139,3 +139,27 @@ def test_posterior_moments_within_4se(prec, d, P):
     print(f"\n[{prec}] worst |z| over means and variances: {worst:.2f}, acceptance {acc:.3f}", flush=True)
     assert worst < 4.0
     assert acc > 0.5
+
+
+def test_mixed_target_reports_a_proposal_outside_the_half_range():
+    """The mixed form's Gaussian target takes x - mu in half precision after
+    a power-of-two scale per coordinate, chosen at each update from the
+    states' spread and the proposal scale with a factor of 1024 of headroom.
+    A proposal far beyond that (chains exactly at the mean, a seeded pivot
+    100 away with a proposal scale of 1e-4: the contraction toward the pivot
+    moves every coordinate by about 4.6) must be reported by the next update
+    as an error instead of being rejected silently."""
+    d, P, n_lag = 128, 64, 4
+    t = synth.gaussian_target(d, 3)
+    x0 = np.repeat(t.mu[:, None], P, axis=1)     # d x P, every chain at the mean
+    cfg = diam.make_config(d, P, n_lag, "mixed", seed=5)
+    s = diam.Sampler(cfg, dev(t.mu), dev(t.R, torch.float32), dev(x0.T))
+    m0 = t.mu + 100.0
+    S0 = 1e-8 * np.eye(d) + np.outer(m0, m0)
+    st, _ = s.seed_moments(dev(S0), dev(m0), 1000.0)
+    assert st == diam.OK
+    s.step_batch(n_lag)
+    s.merge_moments()
+    with pytest.raises(diam.DiamError, match="range of the mixed-form target"):
+        s.update_proposal()
+    s.close()
