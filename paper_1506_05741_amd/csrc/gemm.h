@@ -807,10 +807,42 @@ DEV void h_copy_flat(const u16* __restrict__ src, u16* lds_block) {
   __builtin_amdgcn_global_load_lds((const void*)(src + lane * 8), (lds_ptr_t)lds_block, 16, 0, 0);
 }
 
+// Accumulators of a 32 x 32-fragment wave tile: the workgroup tile BM x BN
+// is split over WGM x WGN waves, each holding FM x FN fragments of 32 x 32.
+template <int BM, int BN, int WGM, int WGN>
+struct W32Frag {
+  static constexpr int FM = BM / (32 * WGM), FN = BN / (32 * WGN);
+  static_assert(FM >= 1 && FN >= 1, "wave tile smaller than one 32 x 32 fragment");
+  f16v_t c[FM][FN];
+  DEVM void zero() {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) c[a][b] = (f16v_t)0.0f;
+  }
+};
+
+// Tile coordinates of register group g (entries 4g .. 4g + 3, four
+// consecutive rows) of fragment (m, n).
+template <int BM, int BN, int WGM, int WGN>
+DEV void w32_coords(int m, int n, int g, int& ti, int& tj) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w % WGM, wn = w / WGM;
+  ti = wm * (BM / WGM) + m * 32 + 8 * g + 4 * (lane >> 5);
+  tj = wn * (BN / WGN) + n * 32 + (lane & 31);
+}
+
 template <int BM, int BN, int WGM, int WGN, int ST>
-DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, int arb, const u16* __restrict__ B,
+DEV void h2_gemm(W32Frag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA, int arb, const u16* __restrict__ B,
                  long dB, long ldb, int i0, int j0, int kbeg, int kend, u16* lds) {
-  typedef WFrag<BM, BN, WGM, WGN> F;
+  // Software-pipelined: the fragments of slice kt + 1 are read from LDS while
+  // the products of slice kt run, and copies run ST - 2 slices ahead of the
+  // reads.  At the barrier of step kt every wave has completed its reads of
+  // slice kt - 1 and stage kt + 1 has landed; the copy of slice kt + ST - 1
+  // then refills the stage of slice kt - 1.  Products on the 32 x 32 x 16
+  // instruction, two per 32-deep slice and part pair.
+  static_assert(ST >= 3, "the pipelined ring needs three stages or more");
+  typedef W32Frag<BM, BN, WGM, WGN> F;
   constexpr int NW = WGM * WGN;
   constexpr int SA = BM * HBK, SB = BN * HBK, SS = 2 * (SA + SB);
   constexpr int BLK_A = BM / 16, BLK_B = BN / 16, NBLK = 2 * (BLK_A + BLK_B);
@@ -834,39 +866,81 @@ DEV void h2_gemm(WFrag<BM, BN, WGM, WGN>& f, const u16* __restrict__ A, long dA,
     }
   };
   const int wm = w % WGM, wn = w / WGM;
-  const int lr = lane & 15, lk = lane >> 4;
-  for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
-  for (int kt = 0; kt < nk; ++kt) {
-    // stage kt has landed once at most the later stages' copies are pending
-    if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    asm volatile("s_barrier" ::: "memory");
-    if (kt + ST - 1 < nk) issue(kt + ST - 1);
+  const int lr = lane & 31, lh = lane >> 5;
+  // [k half][part][fragment]
+  struct Frags {
+    h8_t a[2][2][F::FM], b[2][2][F::FN];
+  };
+  auto read = [&](int kt, Frags& g) {
     const u16* st = lds + (kt % ST) * SS;
-    h8_t a0[F::FM], a1[F::FM], b0[F::FN], b1[F::FN];
 #pragma unroll
-    for (int m = 0; m < F::FM; ++m) {
-      const int r = wm * (BM / WGM) + m * 16 + lr;
-      const int o = r * HBK + ((lk ^ hswz(r)) * 8);
-      a0[m] = *(const h8_t*)(st + o);
-      a1[m] = *(const h8_t*)(st + SA + o);
-    }
+    for (int kh = 0; kh < 2; ++kh) {
+      const int ch = 2 * kh + lh;  // 8-column chunk of the 32-deep slice
 #pragma unroll
-    for (int n = 0; n < F::FN; ++n) {
-      const int r = wn * (BN / WGN) + n * 16 + lr;
-      const int o = r * HBK + ((lk ^ hswz(r)) * 8);
-      b0[n] = *(const h8_t*)(st + 2 * SA + o);
-      b1[n] = *(const h8_t*)(st + 2 * SA + SB + o);
-    }
-#pragma unroll
-    for (int m = 0; m < F::FM; ++m)
+      for (int m = 0; m < F::FM; ++m) {
+        const int r = wm * (BM / WGM) + m * 32 + lr;
+        const int o = r * HBK + ((ch ^ hswz(r)) * 8);
+        g.a[kh][0][m] = *(const h8_t*)(st + o);
+        g.a[kh][1][m] = *(const h8_t*)(st + SA + o);
+      }
 #pragma unroll
       for (int n = 0; n < F::FN; ++n) {
-        // smallest terms first
-        f.c[m][n] = mfma_f16(a1[m], b0[n], f.c[m][n]);
-        f.c[m][n] = mfma_f16(a0[m], b1[n], f.c[m][n]);
-        f.c[m][n] = mfma_f16(a0[m], b0[n], f.c[m][n]);
+        const int r = wn * (BN / WGN) + n * 32 + lr;
+        const int o = r * HBK + ((ch ^ hswz(r)) * 8);
+        g.b[kh][0][n] = *(const h8_t*)(st + 2 * SA + o);
+        g.b[kh][1][n] = *(const h8_t*)(st + 2 * SA + SB + o);
       }
+    }
+  };
+  auto mma = [&](const Frags& g) {
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+      for (int m = 0; m < F::FM; ++m)
+#pragma unroll
+        for (int n = 0; n < F::FN; ++n) {
+          // smallest terms first
+          f.c[m][n] = mfma32_f16(g.a[kh][1][m], g.b[kh][0][n], f.c[m][n]);
+          f.c[m][n] = mfma32_f16(g.a[kh][0][m], g.b[kh][1][n], f.c[m][n]);
+          f.c[m][n] = mfma32_f16(g.a[kh][0][m], g.b[kh][0][n], f.c[m][n]);
+        }
+  };
+  auto step = [&](int kt, const Frags& cur, Frags& nxt) {
+    if (kt + 1 < nk) {
+      // slices issued after kt + 1: min(ST - 3, nk - 2 - kt)
+      if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 3)) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + ST - 1 < nk) issue(kt + ST - 1);
+    // unconditional, so that the products below wait only for the reads of
+    // the step before (the last step re-reads a landed stage, unused)
+    read(kt + 1 < nk ? kt + 1 : kt, nxt);
+    // keep the reads ahead of the products (neither sunk below them nor
+    // interleaved by the scheduler); the products use registers whose reads
+    // completed at the end of the step before, so they start at once
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur);
+    // every LDS read of this step done (s_waitcnt lgkmcnt(0), visible to the
+    // compiler's wait tracking unlike an asm wait), after the products
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int p = 0; p < ST - 1 && p < nk; ++p) issue(p);
+  if (nk >= ST - 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW * (ST - 2)) : "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  asm volatile("s_barrier" ::: "memory");
+  Frags fa, fb;
+  read(0, fa);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int kt = 0; kt < nk; kt += 2) {
+    step(kt, fa, fb);
+    if (kt + 1 < nk) step(kt + 1, fb, fa);
   }
 }
 

@@ -186,24 +186,30 @@ hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d
 template <int BM, int BN, int WGM, int WGN, int ST>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict__ R2, const u16* __restrict__ V2,
                                                           int d, int P, float* __restrict__ Yp) {
-  typedef WFrag<BM, BN, WGM, WGN> F;
+  typedef W32Frag<BM, BN, WGM, WGN> F;
   __shared__ __attribute__((aligned(1024))) u16 lds[h2_lds_elems<BM, BN, ST>()];
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
   const int kl = d / H2_KSPLIT;
+  // the output pointer is loaded before the loop: a scalar load left in
+  // flight there would make every LDS wait of the pipelined loop a full one
+  float* Y = Yp + (long)ks * P * d;
+  asm volatile("" ::"s"(Y));
   F f;
   f.zero();
   h2_gemm<BM, BN, WGM, WGN, ST>(f, R2, (long)d * d, d / 16, V2, (long)d * P, d, i0, j0, ks * kl, (ks + 1) * kl,
                                 lds);
-  float* Y = Yp + (long)ks * P * d;
 #pragma unroll
   for (int m = 0; m < F::FM; ++m)
 #pragma unroll
-    for (int n = 0; n < F::FN; ++n) {
-      int ti, tj;
-      w_coords<BM, BN, WGM, WGN>(m, n, 0, ti, tj);
-      // four consecutive rows of one chain: one 16-byte store
-      *(f4_t*)(Y + (long)(j0 + tj) * d + i0 + ti) = f.c[m][n];
-    }
+    for (int n = 0; n < F::FN; ++n)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        int ti, tj;
+        w32_coords<BM, BN, WGM, WGN>(m, n, g, ti, tj);
+        // four consecutive rows of one chain: one 16-byte store
+        const f4_t v = {f.c[m][n][4 * g], f.c[m][n][4 * g + 1], f.c[m][n][4 * g + 2], f.c[m][n][4 * g + 3]};
+        *(f4_t*)(Y + (long)(j0 + tj) * d + i0 + ti) = v;
+      }
 }
 
 // part[j][rb] = -1/2 sum over rows of block rb of (rsc_i sum_s Yp[s])^2, one wave per (j, rb)
@@ -237,10 +243,10 @@ hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rs
                         double* part, hipStream_t s, const double* twist) {
   // 128 x 128 tiles on 8 waves where they fit
   if (d % 128 == 0 && P % 128 == 0)
-    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2, 3>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
+    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2, 4>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
   else
-    hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2, 3>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2, 4>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
   const int nrb = tgt_row_blocks(d);
   const long waves = (long)P * nrb;
