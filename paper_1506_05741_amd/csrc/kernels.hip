@@ -2079,8 +2079,10 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
   }
 }
 
+// eight waves per SIMD: the P * d / 128 waves of a step at P = 256, d = 4096
+// fit the chip in one round (the argument block alone would hold it to seven)
 template <int PR, int MODE>
-__global__ __launch_bounds__(256) void k_step(StepArgs a, int nch) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step(StepArgs a, int nch) {
   if (MODE == 2 && (a.d & 1) == 0) step_update2<PR>(a, blockIdx.x, nch, blockIdx.y);
   else step_body<PR, MODE>(a, blockIdx.x, nch, blockIdx.y);
 }
