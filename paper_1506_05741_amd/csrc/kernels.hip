@@ -212,27 +212,44 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict
       }
 }
 
-// part[j][rb] = -1/2 sum over rows of block rb of (rsc_i sum_s Yp[s])^2, one wave per (j, rb)
+// part[j][rb] = -1/2 sum over rows of block rb of (rsc_i sum_s Yp[s])^2.  One
+// wave per chain and four 64-row blocks: lane l takes rows 4l .. 4l + 3 of the
+// wave's 256 (16-byte loads), sixteen lanes make one block (d is a multiple
+// of 64, so a block is wholly inside or outside).
 __global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__ Yp, const double* __restrict__ rsc,
                                                        int d, int P, int nrb, double* __restrict__ part,
                                                        const double* __restrict__ twist) {
   const int lane = threadIdx.x & 63;
+  const int nq = (nrb + 3) / 4;
   const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wid >= (long)P * nrb) return;
-  const int j = (int)(wid / nrb), rb = (int)(wid % nrb);
-  const int i = rb * 64 + lane;
-  double y = 0.0;
+  if (wid >= (long)P * nq) return;
+  const int j = (int)(wid / nq), q4 = (int)(wid % nq);
+  const int i = q4 * 256 + 4 * lane;
+  double q = 0.0;
   if (i < d) {
-    for (int s = 0; s < H2_KSPLIT; ++s) y += (double)Yp[((long)s * P + j) * d + i];
-    y *= rsc[i];
+    double y[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < H2_KSPLIT; ++s) {
+      const f4_t v = *(const f4_t*)(Yp + ((long)s * P + j) * d + i);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[r] += (double)v[r];
+    }
+    const double2 r01 = *(const double2*)(rsc + i), r23 = *(const double2*)(rsc + i + 2);
+    y[0] *= r01.x;
+    y[1] *= r01.y;
+    y[2] *= r23.x;
+    y[3] *= r23.y;
+    if (twist) {
+      // twisted target: row 2k+1 gets c y_{2k}^2 (pairs lie within a lane)
+      y[1] = __fma_rn(twist[i + 1], y[0] * y[0], y[1]);
+      y[3] = __fma_rn(twist[i + 3], y[2] * y[2], y[3]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q = __fma_rn(y[r], y[r], q);
   }
-  if (twist) {
-    // twisted target: row 2k+1 (odd lane, as blocks start at even rows) gets c y_{2k}^2
-    const double yp = __shfl_xor(y, 1, 64);
-    if ((i & 1) && i < d) y = __fma_rn(twist[i], yp * yp, y);
-  }
-  const double q = wave_sum_f64(y * y);
-  if (lane == 0) part[(long)j * nrb + rb] = -0.5 * q;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+  const int rb = q4 * 4 + (lane >> 4);
+  if ((lane & 15) == 0 && i < d) part[(long)j * nrb + rb] = -0.5 * q;
 }
 
 bool tgt_h2_ok(int d, int P) { return d % (H2_KSPLIT * 32) == 0 && d % 64 == 0 && P % 64 == 0; }
@@ -249,7 +266,7 @@ hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rs
     hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2, 4>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
   const int nrb = tgt_row_blocks(d);
-  const long waves = (long)P * nrb;
+  const long waves = (long)P * ((nrb + 3) / 4);
   hipLaunchKernelGGL(k_tgt_h2_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, rsc, d,
                      P, nrb, part, twist);
   return hipGetLastError();
