@@ -33,7 +33,9 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of the target kernels from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE runs scaled by a device copy's counters (see profiles/); a
 # kernel missing here has changed since its counters were taken.
-TRAFFIC = {}   # kernel -> HBM bytes per launch at d=4096, P=256 (profiles/hbm_traffic_*.md), once measured
+# HBM bytes per target step at d=4096, P=256 (k_tgt_h2 + k_tgt_h2_reduce), from FETCH_SIZE x 2 + WRITE_SIZE
+# (profiles/hbm_traffic_k_tgt_h2_d4096_P256.md); taken for the kernels as they stand
+TRAFFIC = {"k_tgt_h2": (49189.0 * 2 + 16384.0 + 8247.0 * 2 + 128.0) * 1024}
 
 
 def log(msg):
@@ -711,6 +713,30 @@ def cpu_baseline(tgt, args):
     }
 
 
+def library_gemm_reference(d, P, torch):
+    """The vendor GEMM (torch.matmul on hipBLASLt) at the target's shape, for
+    context beside the roofline: one f16 product R V (d x d by d x P, FP32
+    accumulation inside) and the three-product form as one product of K = 3 d
+    ([R1 R0 R0] by [V0; V1; V0])."""
+    out = {}
+    for name, k in (("one_f16_product", d), ("three_products_as_K_3d", 3 * d)):
+        a = torch.randn(d, k, device="cuda").to(torch.float16)
+        b = torch.randn(k, P, device="cuda").to(torch.float16)
+        for _ in range(5):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 50 * 1e3
+        out[name] = {"us": us, "tflops": 2.0 * d * k * P / (us * 1e-6) / 1e12}
+        del a, b, c
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -851,6 +877,8 @@ def main():
                                 "executed_tflops": 4 * pf / dtp / 1e12, "executed_frac": 4 * pf / dtp / PEAK["bf16"],
                                 "avg_us": dtp * 1e6,
                                 "work": "d (d + 1) P n_lag flops per window (useful, triangular); 4 x that executed"}
+    if args.precision == "mixed" and split:
+        roofline["library_reference"] = library_gemm_reference(args.d, args.P, torch)
     stages = {k: {"ms_per_window": v[0] / args.profile_windows, "regions": v[1]} for k, v in prof.items() if v[1]}
     # the PSRF fold of a merged window (profiled windows only): store read + accumulators read and written
     psrf = None
@@ -875,7 +903,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16+f64", "fp32": "f32+f64", "fp64": "f64"}[args.precision],
+        "dtype": {"mixed": "bf16+f16+f64", "fp32": "f32+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"Gaussian target d={args.d} (lambda_i=i^-2, seed 2), P={args.P} chains, "
                                f"n_lag={args.n_lag}, beta={args.beta}, warm start; step = one window",
