@@ -590,9 +590,12 @@ extern "C" int diam_init(diam_ctx** out, const diam_config* cfg, const diam_targ
   } else {
     HIPCHK_INIT(dk::init_eval(c->prec == dk::P64, c->X, tgt->mu, c->V, c->Z, d, P, s));
     if (c->h2) {
-      HIPCHK_INIT(dk::h2_scales(c->X, tgt->mu, c->L, (const float*)tgt->R, d, P, c->vsc, c->R2, c->rsc, s));
+      // log pi(x0) at scales from the states' spread, then the scales of the
+      // proposals (the identity factor's spread included)
+      HIPCHK_INIT(dk::h2_scales(c->X, tgt->mu, c->L, (const float*)tgt->R, d, P, c->vsc, c->R2, c->rsc, s, 1));
       HIPCHK_INIT(dk::h2_split_v(c->X, tgt->mu, c->vsc, d, P, c->V2, s));
       HIPCHK_INIT(dk::tgt_gauss_h2(c->R2, c->V2, c->rsc, d, P, c->Yp, c->lpp_part, s, tgt->twist));
+      HIPCHK_INIT(dk::h2_scales(c->X, tgt->mu, c->L, (const float*)tgt->R, d, P, c->vsc, c->R2, c->rsc, s, 0));
     } else {
       HIPCHK_INIT(dk::tgt_gauss(c->prec, tgt->R, c->V, d, P, c->lpp_part, s, tgt->twist));
     }

@@ -29,7 +29,8 @@ hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, doub
 // scaled R and V (FP32-equivalent products); needs tgt_h2_ok(d, P) and Yp
 // scratch of tgt_h2_scratch_bytes.  h2_scales computes the coordinate scales
 // vsc (d floats) from the states X (d x P) about mu and the lower factor L
-// (d x d column-major FP64), then the row scales rsc (d FP64) and both parts
+// (d x d column-major FP64; states_only: from the states' spread alone, for
+// evaluating the states themselves), then the row scales rsc (d FP64) and both parts
 // of the scaled R (FP32 row-major) into R2 (2 d^2 halves, each part in
 // 16 x 32 blocks ordered by column block, then row block); h2_split_v writes
 // both parts of the scaled X - mu into V2 (2 d P halves).  The step kernel
@@ -37,7 +38,7 @@ hipError_t tgt_gauss(Prec prec, const void* R, const void* V, int d, int P, doub
 bool tgt_h2_ok(int d, int P);
 size_t tgt_h2_scratch_bytes(int d, int P);
 hipError_t h2_scales(const double* X, const double* mu, const double* L, const float* R, int d, int P, float* vsc,
-                     uint16_t* R2, double* rsc, hipStream_t s);
+                     uint16_t* R2, double* rsc, hipStream_t s, int states_only = 0);
 hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d, int P, uint16_t* V2,
                       hipStream_t s);
 hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rsc, int d, int P, float* Yp,

@@ -88,10 +88,11 @@ constexpr double H2_RANGE = 65520.0;
 
 // vsc[k] = 2^(6 - e_k) with sigma_k < 2^e_k (frexp), sigma_k the larger of
 // max_p |x_kp - mu_k| and the 2-norm of row k of the lower factor L
-// (column-major), e_k clamped to [-100, 100].  64 rows per block, one per
+// (column-major; the spread of the proposals), or the former alone for an
+// evaluation of the states themselves; e_k clamped to [-100, 100].  64 rows per block, one per
 // lane; the 16 waves split the columns of L and the chains.
 __global__ __launch_bounds__(1024) void k_h2_vscale(const double* __restrict__ X, const double* __restrict__ mu,
-                                                    const double* __restrict__ L, int d, int P,
+                                                    const double* __restrict__ L, int d, int P, int states_only,
                                                     float* __restrict__ vsc) {
   __shared__ double sdev[16][64], srn[16][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -113,7 +114,9 @@ __global__ __launch_bounds__(1024) void k_h2_vscale(const double* __restrict__ X
     dev = fmax(dev, sdev[q][lane]);
     rn += srn[q][lane];
   }
-  const double sig = fmax(dev, sqrt(rn));
+  // states_only (the evaluation of the states themselves): their spread
+  // alone, the factor's row norm only where they do not spread
+  const double sig = (states_only && dev > 0.0) ? dev : fmax(dev, sqrt(rn));
   int e = 0;
   if (sig > 0.0 && isfinite(sig)) {
     frexp(sig, &e);  // sig < 2^e
@@ -170,8 +173,9 @@ __global__ __launch_bounds__(256) void k_h2_split_v(const double* __restrict__ X
 }
 
 hipError_t h2_scales(const double* X, const double* mu, const double* L, const float* R, int d, int P, float* vsc,
-                     uint16_t* R2, double* rsc, hipStream_t s) {
-  hipLaunchKernelGGL(k_h2_vscale, dim3((unsigned)((d + 63) / 64)), dim3(1024), 0, s, X, mu, L, d, P, vsc);
+                     uint16_t* R2, double* rsc, hipStream_t s, int states_only) {
+  hipLaunchKernelGGL(k_h2_vscale, dim3((unsigned)((d + 63) / 64)), dim3(1024), 0, s, X, mu, L, d, P, states_only,
+                     vsc);
   hipLaunchKernelGGL(k_h2_split_r, dim3(d), dim3(256), 0, s, R, (const float*)vsc, d, (u16*)R2, rsc);
   return hipGetLastError();
 }

@@ -163,3 +163,52 @@ def test_mixed_target_reports_a_proposal_outside_the_half_range():
     with pytest.raises(diam.DiamError, match="range of the mixed-form target"):
         s.update_proposal()
     s.close()
+
+
+def test_mixed_target_over_coordinate_scales_from_1e_minus6_to_1e6():
+    """The mixed form brings x - mu and R into the half range with power-of-two
+    scales per coordinate (from the states' spread and the factor's row norms,
+    chosen again at every update) and per row of R.  On a Gaussian whose
+    coordinate scales span twelve decades, log pi of the states must match
+    FP64 at FP32 level at the start, after the warm-start update and after a
+    window of steps evaluated at the new scales."""
+    d, P, n_lag = 256, 64, 16
+    rng = np.random.default_rng(11)
+    sk = 10.0 ** rng.uniform(-6.0, 6.0, d)
+    Q = np.linalg.qr(rng.standard_normal((d, d)))[0]
+    lam = rng.uniform(0.5, 2.0, d)
+    R = (Q / np.sqrt(lam)).T / sk                     # diag(lam)^-1/2 Q^T diag(sk)^-1
+    R32 = R.astype(np.float32).astype(np.float64)     # the library reads R in FP32
+    mu = sk * rng.standard_normal(d)
+    B = (sk[:, None] * Q) * np.sqrt(lam)              # x = mu + B w, w ~ N(0, I)
+    Sigma = B @ B.T
+    x0 = mu[:, None] + B @ rng.standard_normal((d, P))
+    cfg = diam.make_config(d, P, n_lag, "mixed", seed=21)
+    s = diam.Sampler(cfg, dev(mu), dev(R, torch.float32), dev(x0.T))
+
+    def check(where):
+        X = host(s.get_f64(diam.F_X, (P, d))).T
+        y = R32 @ (X - mu[:, None])
+        lp_ref = -0.5 * np.sum(y * y, axis=0)
+        lp = host(s.get_f64(diam.F_LOGP, (P,)))
+        err = float(np.max(np.abs(lp - lp_ref) / (1.0 + np.abs(lp_ref))))
+        print(f"\n[{where}] log pi relative error {err:.2e}, log pi mean {lp_ref.mean():.1f}", flush=True)
+        # FP32 level: sqrt(d) u32 relative on sums of O(1) terms
+        assert err < 4 * math.sqrt(d) * 2.0 ** -24, (where, err)
+
+    check("start")
+    S0 = Sigma + np.outer(mu, mu)
+    st, _ = s.seed_moments(dev(S0), dev(mu), 10.0 * P * n_lag)
+    assert st == diam.OK
+    check("after the update")
+    nacc = np.zeros(P, dtype=np.int32)
+    n = dev(nacc, torch.int32)
+    s.step_batch(n_lag, n_accepted=n)
+    assert host(n).sum() > 0.5 * P * n_lag            # the states moved: log pi came from the half path
+    check("after a window")
+    s.merge_moments()
+    st, _ = s.update_proposal()
+    assert st == diam.OK
+    s.step_batch(n_lag)
+    check("after a second window")
+    s.close()
