@@ -882,10 +882,14 @@ DEV double readlane_f64(double v, int src) {
 // Column c is published through a double-buffered LDS vector; after one
 // workgroup barrier every wavefront that owns columns right of c applies the
 // rank-1 update to its part of each row, without per-element masks (entries
-// right of the diagonal collect values that are never read).  Look-ahead: the
-// wavefront owning column c + 1 updates that column first, takes its pivot
-// (from lane c + 1 by readlane) and publishes it before its other updates, so
-// one barrier per column separates consecutive pivots.  The pivot step forms
+// right of the diagonal collect values that are never read).  Blocks of
+// CHOL_CB columns with look-ahead: the wavefront owning the next block
+// applies the block just published to that block first, factors its CB
+// columns in turn (each updating the later ones of the block from its own
+// registers and the pivot row's value by readlane) and publishes them before
+// its other updates, so one barrier per CB columns separates consecutive
+// blocks (per column in the earlier design: 20 to 9 us per 64 x 64 core,
+// the factor bitwise unchanged).  The pivot step forms
 // y ~ 1/sqrt(pivot) by the hardware reciprocal square root refined with two
 // Newton-Raphson steps, then L(c, c) = pivot y and L(r, c) = a(r, c) y; a
 // pivot that is not > 0 (or NaN) gives a diagonal that is not > 0.  Each
@@ -894,10 +898,12 @@ DEV double readlane_f64(double v, int src) {
 // [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1, C^-1]] with 32 x 32 blocks:
 // one wavefront forms A^-1 and C^-1 by substitution (lane c of each half a
 // column), then all four form the two products.
-// LDS: two column buffers, the factored block (whose zero upper-right
+// LDS: two buffers of CB columns, the factored block (whose zero upper-right
 // quarter then holds B A^-1), the reciprocal diagonal, A^-1 and C^-1.
 constexpr int CHOL_DIAG_THREADS = 256;
-constexpr int CHOL_DIAG_LDS = 2 * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB + 2 * 32 * 33;  // doubles
+constexpr int CHOL_CB = 4;  // columns factored per workgroup barrier
+static_assert((CHOL_NB / 4) % CHOL_CB == 0, "a column block lies within one wavefront's columns");
+constexpr int CHOL_DIAG_LDS = 2 * CHOL_CB * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB + 2 * 32 * 33;  // doubles
 
 // 1/sqrt(x): hardware estimate, then two Newton-Raphson steps
 // y <- y + y (1 - x y^2) / 2 (NaN for x < 0 or NaN, +inf for x = 0)
@@ -926,9 +932,9 @@ DEV void tri_inverse_col32(const double (*Ls)[CHOL_NB + 1], const double* rdiag,
 DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* __restrict__ Linv,
                         int* __restrict__ info, double* sh) {
   constexpr int H = CHOL_NB / 4;  // columns per wavefront
-  double (*colv)[CHOL_NB] = (double (*)[CHOL_NB])sh;
-  double (*Ls)[CHOL_NB + 1] = (double (*)[CHOL_NB + 1])(sh + 2 * CHOL_NB);
-  double* rdiag = sh + 2 * CHOL_NB + CHOL_NB * (CHOL_NB + 1);
+  double (*colp)[CHOL_CB][CHOL_NB] = (double (*)[CHOL_CB][CHOL_NB])sh;  // [parity][column of block][row]
+  double (*Ls)[CHOL_NB + 1] = (double (*)[CHOL_NB + 1])(sh + 2 * CHOL_CB * CHOL_NB);
+  double* rdiag = sh + 2 * CHOL_CB * CHOL_NB + CHOL_NB * (CHOL_NB + 1);
   double (*Ai)[33] = (double (*)[33])(rdiag + CHOL_NB);
   double (*Ci)[33] = Ai + 32;
   const int t = threadIdx.x, r = t & 63;
@@ -946,29 +952,56 @@ DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* _
     a[k] = v;
   }
   // pivot step of column c by the wavefront holding it (its local column kc)
-  auto pivot = [&](int c, int kc) {
+  auto pivot = [&](int c, int kc, double* dst) {
     const double piv = readlane_f64(a[kc], c);
     const double y = rsqrt_nr(piv);
     const double l = (r == c) ? piv * y : a[kc] * y;
     a[kc] = l;
-    colv[c & 1][r] = (r >= c) ? l : 0.0;
+    dst[r] = (r >= c) ? l : 0.0;
   };
-  if (w == 0) pivot(0, 0);
+  // the owner of block (n .. n + CB - 1) factors its columns in turn, each
+  // updating the later ones of the block from its own registers and the
+  // pivot row's value (readlane), and publishes them
+  auto own_block = [&](int n, int buf) {
+    const int k0 = n % H;
 #pragma unroll
-  for (int c = 0; c < CHOL_NB; ++c) {
-    const int wc = c / H, c1 = c + 1, w1 = c1 / H, k1 = c1 % H;
+    for (int t = 0; t < CHOL_CB; ++t) {
+      pivot(n + t, k0 + t, colp[buf][t]);
+      const double lt = (r >= n + t) ? a[k0 + t] : 0.0;
+#pragma unroll
+      for (int u = t + 1; u < CHOL_CB; ++u) a[k0 + u] = __fma_rn(-lt, readlane_f64(a[k0 + t], n + u), a[k0 + u]);
+    }
+  };
+  if (w == 0) own_block(0, 0);
+#pragma unroll
+  for (int q = 0; q < CHOL_NB / CHOL_CB; ++q) {
+    const int c0 = CHOL_CB * q, wc = c0 / H, n0 = c0 + CHOL_CB, wn = n0 / H;
+    const int buf = q & 1;
     __syncthreads();
-    if (c1 < CHOL_NB && w == w1) {
-      // owner of column c + 1: that column, its pivot, then the rest right of c
-      const double lr = colv[c & 1][r];
-      a[k1] = __fma_rn(-lr, colv[c & 1][w1 * H + k1], a[k1]);
-      pivot(c1, k1);
+    if (n0 < CHOL_NB && w == wn) {
+      // owner of the next block: the published block applied to its columns,
+      // that block factored and published, then the rest of its columns
+      double lb[CHOL_CB];
 #pragma unroll
-      for (int k = (w1 == wc) ? k1 + 1 : 1; k < H; ++k) a[k] = __fma_rn(-lr, colv[c & 1][w1 * H + k], a[k]);
+      for (int t = 0; t < CHOL_CB; ++t) lb[t] = colp[buf][t][r];
+      const int k0 = n0 % H;
+#pragma unroll
+      for (int u = 0; u < CHOL_CB; ++u)
+#pragma unroll
+        for (int t = 0; t < CHOL_CB; ++t) a[k0 + u] = __fma_rn(-lb[t], colp[buf][t][n0 + u], a[k0 + u]);
+      own_block(n0, buf ^ 1);
+#pragma unroll
+      for (int k = (wn == wc) ? k0 + CHOL_CB : CHOL_CB; k < H; ++k)
+#pragma unroll
+        for (int t = 0; t < CHOL_CB; ++t) a[k] = __fma_rn(-lb[t], colp[buf][t][w * H + k], a[k]);
     } else if (w > wc) {
-      const double lr = colv[c & 1][r];
+      double lb[CHOL_CB];
 #pragma unroll
-      for (int k = 0; k < H; ++k) a[k] = __fma_rn(-lr, colv[c & 1][w * H + k], a[k]);
+      for (int t = 0; t < CHOL_CB; ++t) lb[t] = colp[buf][t][r];
+#pragma unroll
+      for (int k = 0; k < H; ++k)
+#pragma unroll
+        for (int t = 0; t < CHOL_CB; ++t) a[k] = __fma_rn(-lb[t], colp[buf][t][w * H + k], a[k]);
     }
   }
 #pragma unroll
@@ -2409,7 +2442,11 @@ __global__ __launch_bounds__(PERSIST_THREADS) void gk_persist(const BProb* __res
         }
       }
     }
-    __syncthreads();  // the item's stores, in every wavefront, before thread 0 publishes it
+    // the item's stores, in every wavefront, complete (a workgroup barrier
+    // alone does not wait for other wavefronts' stores) before thread 0
+    // publishes the item with its agent-scope release
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
     prev_g = g;
   }
 }

@@ -157,24 +157,27 @@ def test_persistent_loop_at_the_batched_size():
     dims = [int(x) for x in synth.batch_dims(48)]
     ts = [synth.gaussian_target(d, 1000 + g) for g, d in enumerate(dims)]
     x0 = [synth.gaussian_exact_draws(t, P, 2000 + g) for g, t in enumerate(ts)]
-    ref, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
-    per, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
-    per.set_persistent(True)
-    times = {}
-    for name, b in (("grouped", ref), ("persistent", per)):
-        assert b.window()[0] == diam.OK
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        assert b.window()[0] == diam.OK
-        torch.cuda.synchronize()
-        times[name] = 1e3 * (time.perf_counter() - t0)
-    for g in range(48):
-        for f in FIELDS + [diam.F_ACC, diam.F_LA]:
-            assert torch.equal(ref.get(g, f), per.get(g, f)), (g, f)
-    log(f"48 targets: persistent loop bitwise equal to the grouped launches over 2 windows; ms per window "
-        f"{times}")
-    ref.close()
-    per.close()
+    # three fresh pairs: a publication race in the loop shows as a
+    # difference in some problem of some run, not in every run
+    for rep in range(3):
+        ref, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
+        per, _ = make_batch(ts, x0, P, nl, 77, float(P) * 12800)
+        per.set_persistent(True)
+        times = {}
+        for name, b in (("grouped", ref), ("persistent", per)):
+            assert b.window()[0] == diam.OK
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assert b.window()[0] == diam.OK
+            torch.cuda.synchronize()
+            times[name] = 1e3 * (time.perf_counter() - t0)
+        for g in range(48):
+            for f in FIELDS + [diam.F_ACC, diam.F_LA]:
+                assert torch.equal(ref.get(g, f), per.get(g, f)), (rep, g, f)
+        log(f"48 targets, run {rep}: persistent loop bitwise equal to the grouped launches over 2 windows; "
+            f"ms per window {times}")
+        ref.close()
+        per.close()
 
 
 def _worst_z(t, X):
