@@ -850,12 +850,7 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
   const int d = c->cfg.d, P = c->cfg.P;
   const long K = (long)c->siw * P;
   hipStream_t s = c->stream;
-  const void* Xs = c->win;
   const int ps = prof_begin(c, DIAM_ST_MERGE);
-  if (c->prec == dk::PMIX) {
-    HIPCHK(dk::transpose_bf16((const uint16_t*)c->win, (uint16_t*)c->wint, d, K, s));
-    Xs = c->wint;
-  }
   double* G = c->Lnew;  // scratch until the next factorisation
   bool global = true;
   long Kg = K;
@@ -871,7 +866,7 @@ extern "C" int diam_merge_moments(diam_ctx* c) {
       Kg = (long)llround(c->loc_n) * P;
     }
   } else {
-    HIPCHK(dk::syrk_window(c->prec, Xs, d, K, G, c->h, c->syrk, s));
+    HIPCHK(dk::syrk_window(c->prec, c->win, c->wint, d, K, G, c->h, c->syrk, s));
   }
   if (global) HIPCHK(dk::fold_moments(G, c->h, c->xr, c->N, Kg, c->S, c->m, d, s));
   prof_end(c, ps);

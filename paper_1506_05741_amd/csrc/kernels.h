@@ -85,8 +85,9 @@ hipError_t trigemm(Prec prec, const void* L, const void* W, const void* Wlo, voi
 // triangle (G(i,j), i >= j, at row j, column i), plus row sums h.
 // f64/f32: column-major Xs (ld = d); bf16: row-major transposed window (ld = K).
 size_t syrk_scratch_bytes(int prec, int d, long K);
-hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s);
-hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipStream_t s);
+// Xw: the window (col-major d x K); Xt: room for its row-major copy (bf16 only)
+hipError_t syrk_window(Prec prec, const void* Xw, void* Xt, int d, long K, double* G, double* h, void* scratch,
+                       hipStream_t s);
 
 // Fold the window into the global moments (counts N -> N + K).
 hipError_t fold_moments(const double* G, const double* h, const double* sft, double N, long K, double* S, double* m,

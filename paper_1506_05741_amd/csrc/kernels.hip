@@ -664,6 +664,65 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const u16* __restrict__ 
   }
 }
 
+// Transposition of the col-major d x K bf16 window into row-major (ld K) with
+// the row sums over K taken on the way (whole 64 x 64 tiles: d and K multiples
+// of 64).  Workgroup (bx, by) owns rows 64 bx .. 64 bx + 63 and the K range of
+// chunk by; its four wavefronts take the chunk's 64-column tiles in turn.  In
+// a tile, lane (g, q) = (lane % 8, lane / 8) reads columns 8 q .. 8 q + 7 of
+// rows 8 g .. 8 g + 7 as eight 16-byte loads, transposes the 8 x 8 block in
+// registers and writes it as eight 16-byte row pieces.  The bf16 values are
+// summed in FP64 (exact: each has 8 significant bits).
+DEV uint32_t pack_lo16(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+DEV uint32_t pack_hi16(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+
+__global__ __launch_bounds__(256) void k_transpose_rowsum_bf16(const u16* __restrict__ in, u16* __restrict__ out,
+                                                               int d, long K, long kchunk,
+                                                               double* __restrict__ hpart) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane & 7, q = lane >> 3;
+  const int i0 = blockIdx.x * 64 + 8 * g;
+  const long kb = (long)blockIdx.y * kchunk, ke = kb + kchunk < K ? kb + kchunk : K;
+  double hs[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) hs[r] = 0.0;
+  for (long k0 = kb + 64 * w; k0 < ke; k0 += 256) {
+    uint32_t v[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint4 x = *(const uint4*)(in + i0 + (k0 + 8 * q + j) * d);
+      v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int c = r >> 1;
+      uint32_t o[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        o[m] = (r & 1) ? pack_hi16(v[2 * m][c], v[2 * m + 1][c]) : pack_lo16(v[2 * m][c], v[2 * m + 1][c]);
+      *(uint4*)(out + (long)(i0 + r) * K + k0 + 8 * q) = make_uint4(o[0], o[1], o[2], o[3]);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        hs[r] += (double)__uint_as_float((r & 1) ? (v[j][c] & 0xffff0000u) : (v[j][c] << 16));
+    }
+  }
+  // lanes of one row group (same g) hold the sums of its eight column groups
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    double s = hs[r];
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (q == 0) red[w][8 * g + r] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    hpart[(long)blockIdx.y * d + i] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                      (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ Gpart, int ns,
                                                        const double* __restrict__ hpart, int nh, int d,
                                                        double* __restrict__ G, double* __restrict__ h) {
@@ -724,11 +783,33 @@ size_t syrk_scratch_bytes(int prec, int d, long K) {
   return (size_t)ns * d * d * sizeof(double) + (size_t)64 * d * sizeof(double);
 }
 
-hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, double* h, void* scratch, hipStream_t s) {
+hipError_t syrk_window(Prec prec, const void* Xw, void* Xt, int d, long K, double* G, double* h, void* scratch,
+                       hipStream_t s) {
   const int ns = syrk_splits(prec, d, K);
   const int kchunk = (int)syrk_kchunk(prec, d, K);
   double* Gpart = (double*)scratch;
   double* hpart = Gpart + (size_t)ns * d * d;
+  // row sums: at most 64 K-chunks
+  int nh = (int)((K + 4095) / 4096) < 64 ? (int)((K + 4095) / 4096) : 64;
+  int hchunk = (int)((K + nh - 1) / nh);
+  // the bf16 window is scattered from its row-major copy (K contiguous per
+  // coordinate); whole tiles take the transposition with the row sums fused
+  const void* Xs = Xw;
+  bool h_done = false;
+  if (prec == PMIX) {
+    if (d % 64 == 0 && K % 64 == 0 && (uintptr_t)Xw % 16 == 0 && (uintptr_t)Xt % 16 == 0) {
+      const long hc = (K / 64 + nh - 1) / nh * 64;
+      nh = (int)((K + hc - 1) / hc);
+      hchunk = (int)hc;
+      hipLaunchKernelGGL(k_transpose_rowsum_bf16, dim3(d / 64, nh), dim3(256), 0, s, (const u16*)Xw, (u16*)Xt, d, K,
+                         hc, hpart);
+      h_done = true;
+    } else {
+      hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((K + 63) / 64), cdiv(d, 64)), dim3(256), 0, s,
+                         (const u16*)Xw, (u16*)Xt, d, K);
+    }
+    Xs = Xt;
+  }
   const int nt = syrk_tiles(prec, d, K);
   dim3 grid(nt, ns);
   if (syrk_pl(prec, d, K) && (uintptr_t)Xs % 16 == 0)
@@ -741,28 +822,19 @@ hipError_t syrk_window(Prec prec, const void* Xs, int d, long K, double* G, doub
     const int vec_ok = (K % 8 == 0) && ((uintptr_t)Xs % 16 == 0);
     hipLaunchKernelGGL(k_syrk_bf16, grid, dim3(256), 0, s, (const u16*)Xs, d, (int)K, kchunk, vec_ok, Gpart);
   }
-  // row sums: at most 64 K-chunks
-  const int nh = (int)((K + 4095) / 4096) < 64 ? (int)((K + 4095) / 4096) : 64;
-  const int hchunk = (int)((K + nh - 1) / nh);
   if (prec == P64)
     hipLaunchKernelGGL((k_rowsum<double, true>), dim3(cdiv(d, 64), nh), dim3(256), 0, s, (const double*)Xs, d, (int)K,
                        hchunk, hpart);
   else if (prec == P32)
     hipLaunchKernelGGL((k_rowsum<float, true>), dim3(cdiv(d, 64), nh), dim3(256), 0, s, (const float*)Xs, d, (int)K,
                        hchunk, hpart);
-  else
+  else if (!h_done)
     hipLaunchKernelGGL((k_rowsum<u16, false>), dim3(cdiv(d, 4), nh), dim3(256), 0, s, (const u16*)Xs, d, (int)K,
                        hchunk, hpart);
   // reduce the splits in order into G (lower) and h
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_splits, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, Gpart, ns, hpart, nh, d, G, h);
-  return hipGetLastError();
-}
-
-hipError_t transpose_bf16(const uint16_t* in, uint16_t* out, int d, long K, hipStream_t s) {
-  dim3 grid((unsigned)((K + 63) / 64), cdiv(d, 64));
-  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, s, in, out, d, K);
   return hipGetLastError();
 }
 
