@@ -10,7 +10,7 @@
 // * bf16 conversion (round to nearest even) and the hi/lo split; the two-part
 //   IEEE half split.
 // * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals.
-// * deterministic wavefront reductions.
+// * cross-lane moves and deterministic wavefront reductions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -102,15 +102,79 @@ DEV double u01_f64(uint32_t a, uint32_t b) {
 // uniform in (0,1) from 24 random bits, exact in fp32
 DEV float u01_f32(uint32_t a) { return ((float)(a >> 8) + 0.5f) * 0x1.0p-24f; }
 
+// ---- cross-lane moves without the LDS unit ---------------------------------
+// The value of lane l ^ OFF, for OFF = 32 and 16 by the gfx950 lane-swap
+// instructions (v_permlane32_swap: lanes 32..63 of the first operand trade
+// with lanes 0..31 of the second; v_permlane16_swap: odd 16-lane rows of the
+// first trade with even rows of the second; with both operands the same
+// value, one of the two results holds the partner), OFF = 8 by a rotation of
+// each 16-lane row by 8 and OFF = 2, 1 by quad permutations (all exact
+// partners for any values).  Every lane of the wavefront must be active.
+template <int CTRL> DEV uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+enum { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128 };
+
+template <int OFF> DEV uint32_t lane_xor_u32(uint32_t v) {
+  static_assert(OFF == 32 || OFF == 16 || OFF == 8 || OFF == 2 || OFF == 1, "no exact move for this offset");
+  if (OFF == 32 || OFF == 16) {
+    const auto r = OFF == 32 ? __builtin_amdgcn_permlane32_swap(v, v, false, false)
+                             : __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const bool low = (__lane_id() & OFF) == 0;
+    return low ? r[1] : r[0];
+  }
+  return dpp_u32<OFF == 8 ? DPP_ROW_ROR8 : OFF == 2 ? DPP_QUAD_XOR2 : DPP_QUAD_XOR1>(v);
+}
+template <int OFF> DEV float lane_xor_f32(float v) { return __uint_as_float(lane_xor_u32<OFF>(__float_as_uint(v))); }
+template <int OFF> DEV double lane_xor_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = lane_xor_u32<OFF>((uint32_t)b), hi = lane_xor_u32<OFF>((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // ---- wavefront reductions (fixed butterfly order: deterministic) ----------
-DEV double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// v + v(l ^ 32), v + v(l ^ 16), ..., v + v(l ^ 1): every lane gets the same
+// sum.  The xor-4 partner is taken by rotating each 16-lane row by 4, which
+// reaches a lane congruent to l ^ 4 mod 8; after the 32, 16 and 8 steps the
+// values depend on the lane only mod 8, so that lane holds the partner's
+// value and the sum is the butterfly's bit for bit.
+template <typename T> DEV T wave_sum_t(T v) {
+  v += sizeof(T) == 8 ? (T)lane_xor_f64<32>((double)v) : (T)lane_xor_f32<32>((float)v);
+  v += sizeof(T) == 8 ? (T)lane_xor_f64<16>((double)v) : (T)lane_xor_f32<16>((float)v);
+  v += sizeof(T) == 8 ? (T)lane_xor_f64<8>((double)v) : (T)lane_xor_f32<8>((float)v);
+  if (sizeof(T) == 8) {
+    const uint64_t b = (uint64_t)__double_as_longlong((double)v);
+    const uint32_t lo = dpp_u32<DPP_ROW_ROR4>((uint32_t)b), hi = dpp_u32<DPP_ROW_ROR4>((uint32_t)(b >> 32));
+    v += (T)__longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  } else {
+    v += (T)__uint_as_float(dpp_u32<DPP_ROW_ROR4>(__float_as_uint((float)v)));
+  }
+  v += sizeof(T) == 8 ? (T)lane_xor_f64<2>((double)v) : (T)lane_xor_f32<2>((float)v);
+  v += sizeof(T) == 8 ? (T)lane_xor_f64<1>((double)v) : (T)lane_xor_f32<1>((float)v);
   return v;
 }
-DEV float wave_sum_f32(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+DEV double wave_sum_f64(double v) { return wave_sum_t<double>(v); }
+DEV float wave_sum_f32(float v) { return wave_sum_t<float>(v); }
+// Sum over each 16-lane row in the butterfly order 8, 4, 2, 1 (every lane of
+// the row gets it; the xor-4 step as in wave_sum_t).
+DEV double row16_sum_f64(double v) {
+  v += lane_xor_f64<8>(v);
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = dpp_u32<DPP_ROW_ROR4>((uint32_t)b), hi = dpp_u32<DPP_ROW_ROR4>((uint32_t)(b >> 32));
+  v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  v += lane_xor_f64<2>(v);
+  v += lane_xor_f64<1>(v);
+  return v;
+}
+// Largest value of the wavefront (every lane gets it; the maximum does not
+// depend on the order of the comparisons).
+DEV float wave_max_f32(float v) {
+  v = fmaxf(v, lane_xor_f32<32>(v));
+  v = fmaxf(v, lane_xor_f32<16>(v));
+  v = fmaxf(v, lane_xor_f32<8>(v));
+  v = fmaxf(v, __uint_as_float(dpp_u32<DPP_ROW_ROR4>(__float_as_uint(v))));
+  v = fmaxf(v, lane_xor_f32<2>(v));
+  v = fmaxf(v, lane_xor_f32<1>(v));
   return v;
 }
 

@@ -44,7 +44,7 @@ DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d,
             // twisted target: row 2k+1 gets c y_{2k}^2 added before squaring.  Its
             // partner row sits in the same lane (FP32 layout: rows 4q + r) or in
             // lane ^ 16 (FP64 layout: rows 4r + q)
-            const double yp = (sizeof(T) == 8) ? __shfl_xor(y, 16, 64) : (double)f.c[m][n][r & ~1];
+            const double yp = (sizeof(T) == 8) ? lane_xor_f64<16>(y) : (double)f.c[m][n][r & ~1];
             int ti, tj;
             frag_coords<BM, BN, T>(m, n, r, ti, tj);
             const int i = i0 + ti;
@@ -52,8 +52,8 @@ DEV void tgt_gauss_tile(const T* __restrict__ R, const T* __restrict__ V, int d,
           }
           s = __fma_rn(y, y, s);
         }
-      s += __shfl_xor(s, 16, 64);
-      s += __shfl_xor(s, 32, 64);
+      s += lane_xor_f64<16>(s);
+      s += lane_xor_f64<32>(s);
       if (lane < 16) red[wm][wn * (BN / 2) + n * 16 + lane] = s;
     }
   }
@@ -136,8 +136,7 @@ __global__ __launch_bounds__(256) void k_h2_split_r(const float* __restrict__ R,
   const float* row = R + (long)i * d;
   float mx = 0.0f;
   for (int k = t; k < d; k += 256) mx = fmaxf(mx, fabsf(row[k] / vsc[k]));
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  mx = wave_max_f32(mx);
   if ((t & 63) == 0) red[t >> 6] = mx;
   __syncthreads();
   mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
@@ -250,8 +249,7 @@ __global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__
 #pragma unroll
     for (int r = 0; r < 4; ++r) q = __fma_rn(y[r], y[r], q);
   }
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+  q = row16_sum_f64(q);
   const int rb = q4 * 4 + (lane >> 4);
   if ((lane & 15) == 0 && i < d) part[(long)j * nrb + rb] = -0.5 * q;
 }
@@ -710,9 +708,9 @@ __global__ __launch_bounds__(256) void k_transpose_rowsum_bf16(const u16* __rest
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     double s = hs[r];
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
+    s += lane_xor_f64<8>(s);
+    s += lane_xor_f64<16>(s);
+    s += lane_xor_f64<32>(s);
     if (q == 0) red[w][8 * g + r] = s;
   }
   __syncthreads();

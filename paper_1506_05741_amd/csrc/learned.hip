@@ -59,8 +59,8 @@ __global__ __launch_bounds__(512) void k_tgt_logreg(const float* __restrict__ A,
             s += (double)(y[i] * t - softplus_f(t));
           }
         }
-      s += __shfl_xor(s, 16, 64);
-      s += __shfl_xor(s, 32, 64);
+      s += lane_xor_f64<16>(s);
+      s += lane_xor_f64<32>(s);
       if (lane < 16) red[wm][wn * (BN / 2) + n * 16 + lane] = s;
     }
   }
