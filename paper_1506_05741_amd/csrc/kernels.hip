@@ -669,7 +669,8 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const u16* __restrict__ 
 // a tile, lane (g, q) = (lane % 8, lane / 8) reads columns 8 q .. 8 q + 7 of
 // rows 8 g .. 8 g + 7 as eight 16-byte loads, transposes the 8 x 8 block in
 // registers and writes it as eight 16-byte row pieces.  The bf16 values are
-// summed in FP64 (exact: each has 8 significant bits).
+// summed in FP64 in a fixed order (exact while a row's values span less than
+// 2^29 in magnitude: each has 8 significant bits).
 DEV uint32_t pack_lo16(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
 DEV uint32_t pack_hi16(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
@@ -2077,6 +2078,9 @@ DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write) {
 // Paired-row loads and stores for the update half (d even, so that every
 // chain's column starts on an even element): lane l owns rows 2l, 2l + 1 of
 // its 128-row chunk and moves them with 16-, 8- or 4-byte accesses.
+#ifndef STEP_CPW
+#define STEP_CPW 2
+#endif
 template <int PR> struct Pair2;
 template <> struct Pair2<P64> { typedef double2 XI; typedef double2 W; };
 template <> struct Pair2<P32> { typedef float2 XI; typedef float2 W; };
@@ -2119,86 +2123,116 @@ DEV void store_win2(void* win, long e, double v0, double v1) {
   }
 }
 
-template <int PR>
-DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
+// The update of chain 4 pq + (wave) over row chunks CPW cb .. CPW cb + CPW - 1
+// (STEP_RCH rows each; chunks past nch are skipped).  The wavefront takes
+// the chain's decision once, issues every load that does not depend on it
+// first, and keeps one partial per chunk, so the partials are those of one
+// chunk per wavefront whatever CPW is.
+template <int PR, int CPW = 1>
+DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int p = pq * 4 + w;
   if (p >= a.P) return;
   const int d = a.d, P = a.P;
-  const int i = ch * STEP_RCH + 2 * lane;
-  const bool in = i < d;  // d even: the pair lies wholly inside or outside
-  const long e = i + (long)p * d;
-  const bool acc = a.do_accept && (a.fuse_dec ? decide_wave(a, nch, p, ch == 0) : a.acc_out[p] != 0);
-  double x0 = 0, x1 = 0, z0 = 0, z1 = 0, r0 = 0, r1 = 0;
-  double c0 = 0, c1 = 0, wc0 = 0, wc1 = 0, n0 = 0, n1 = 0, wn0 = 0, wn1 = 0, m0 = 0, m1 = 0;
-  if (in) {
-    const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e), rv = *(const double2*)(a.xr + i);
-    x0 = xv.x; x1 = xv.y; z0 = zv.x; z1 = zv.y; r0 = rv.x; r1 = rv.y;
-    const long ew = i + (long)p * (a.ldw ? a.ldw : d);
-    if (acc) {
-      load_xi2<PR>(a.xi_cur, ew, c0, c1);
-      load_w2<PR>(a.w_cur, a.wlo_cur, ew, wc0, wc1);
-    }
-    if (a.do_propose) {
-      load_xi2<PR>(a.xi_nxt, ew, n0, n1);
-      load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, wn0, wn1);
-      if (a.mu) {
-        const double2 mv = *(const double2*)(a.mu + i);
-        m0 = mv.x; m1 = mv.y;
+  const long ldw = a.ldw ? a.ldw : d;
+  int ii[CPW];
+  bool in[CPW];
+  double x0[CPW], x1[CPW], z0[CPW], z1[CPW], r0[CPW], r1[CPW];
+  double c0[CPW], c1[CPW], wc0[CPW], wc1[CPW], n0[CPW], n1[CPW], wn0[CPW], wn1[CPW], m0[CPW], m1[CPW];
+  float2 sv[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int ch = cb * CPW + c;
+    ii[c] = ch * STEP_RCH + 2 * lane;
+    in[c] = ch < nch && ii[c] < d;  // d even: the pair lies wholly inside or outside
+    x0[c] = x1[c] = z0[c] = z1[c] = r0[c] = r1[c] = 0.0;
+    c0[c] = c1[c] = wc0[c] = wc1[c] = n0[c] = n1[c] = wn0[c] = wn1[c] = m0[c] = m1[c] = 0.0;
+    sv[c] = make_float2(0.f, 0.f);
+    if (in[c]) {
+      const int i = ii[c];
+      const long e = i + (long)p * d, ew = i + (long)p * ldw;
+      const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e);
+      const double2 rv = *(const double2*)(a.xr + i);
+      x0[c] = xv.x; x1[c] = xv.y; z0[c] = zv.x; z1[c] = zv.y; r0[c] = rv.x; r1[c] = rv.y;
+      if (a.do_propose) {
+        load_xi2<PR>(a.xi_nxt, ew, n0[c], n1[c]);
+        load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, wn0[c], wn1[c]);
+        if (a.mu) {
+          const double2 mv = *(const double2*)(a.mu + i);
+          m0[c] = mv.x; m1[c] = mv.y;
+        }
+        if (a.vh) sv[c] = *(const float2*)(a.vsc + i);
       }
     }
   }
-  double zacc = 0.0, xacc = 0.0;
-  double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
-  if (in) {
-    if (a.do_accept) {
-      if (acc) {
-        x0 = propose1(r0, x0, a.rho, c0);
-        x1 = propose1(r1, x1, a.rho, c1);
-        z0 = __fma_rn(a.c, wc0, a.rho * z0);
-        z1 = __fma_rn(a.c, wc1, a.rho * z1);
-        *(double2*)(a.X + e) = make_double2(x0, x1);
-        *(double2*)(a.Z + e) = make_double2(z0, z1);
+  const bool acc = a.do_accept && (a.fuse_dec ? decide_wave(a, nch, p, cb == 0) : a.acc_out[p] != 0);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c)
+    if (in[c] && acc) {
+      const long ew = ii[c] + (long)p * ldw;
+      load_xi2<PR>(a.xi_cur, ew, c0[c], c1[c]);
+      load_w2<PR>(a.w_cur, a.wlo_cur, ew, wc0[c], wc1[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int ch = cb * CPW + c;
+    if (ch >= nch) break;
+    const int i = ii[c];
+    const long e = i + (long)p * d;
+    double zacc = 0.0, xacc = 0.0;
+    double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
+    if (in[c]) {
+      double xa = x0[c], xb = x1[c], za = z0[c], zb = z1[c];
+      const double ra = r0[c], rb = r1[c];
+      if (a.do_accept) {
+        if (acc) {
+          xa = propose1(ra, xa, a.rho, c0[c]);
+          xb = propose1(rb, xb, a.rho, c1[c]);
+          za = __fma_rn(a.c, wc0[c], a.rho * za);
+          zb = __fma_rn(a.c, wc1[c], a.rho * zb);
+          *(double2*)(a.X + e) = make_double2(xa, xb);
+          *(double2*)(a.Z + e) = make_double2(za, zb);
+        }
+        store_win2<PR>(a.win, i + (a.win_col0 + p) * (long)d, xa - ra, xb - rb);
+        for (int k = 0; k < a.nproj; ++k) {
+          const double2 pv = *(const double2*)(a.proj + i + (long)k * d);
+          pacc[k] = __fma_rn(pv.y, xb, __fma_rn(pv.x, xa, pacc[k]));
+        }
       }
-      store_win2<PR>(a.win, i + (a.win_col0 + p) * (long)d, x0 - r0, x1 - r1);
+      if (a.do_propose) {
+        const double xp0 = propose1(ra, xa, a.rho, n0[c]), xp1 = propose1(rb, xb, a.rho, n1[c]);
+        if (a.vh) {
+          u16 h0, l0, h1, l1;
+          const double s0 = (xp0 - m0[c]) * (double)sv[c].x, s1 = (xp1 - m1[c]) * (double)sv[c].y;
+          if (fmax(fabs(s0), fabs(s1)) >= H2_RANGE) atomicOr(a.err, 2);
+          split_f16(s0, h0, l0);
+          split_f16(s1, h1, l1);
+          *(uint32_t*)(a.vh + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          *(uint32_t*)(a.vh + (long)d * P + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        } else {
+          const long ev = i + (long)p * (a.ldv ? a.ldv : d);
+          if (a.v32 || PR != P64)
+            *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - m0[c]), (float)(xp1 - m1[c]));
+          else *(double2*)((double*)a.V + ev) = make_double2(xp0 - m0[c], xp1 - m1[c]);
+        }
+        const double zp0 = __fma_rn(a.c, wn0[c], a.rho * za), zp1 = __fma_rn(a.c, wn1[c], a.rho * zb);
+        zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
+        xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
+      }
+    }
+    if (a.do_propose) {
+      zacc = wave_sum_f64(zacc);
+      if (lane == 0) a.zq_part_nxt[(long)p * nch + ch] = zacc;
+      if (a.prior_w > 0.0) {
+        xacc = wave_sum_f64(xacc);
+        if (lane == 0) a.pq_part_nxt[(long)p * nch + ch] = xacc;
+      }
+    }
+    if (a.do_accept && a.nproj > 0) {
       for (int k = 0; k < a.nproj; ++k) {
-        const double2 pv = *(const double2*)(a.proj + i + (long)k * d);
-        pacc[k] = __fma_rn(pv.y, x1, __fma_rn(pv.x, x0, pacc[k]));
+        const double v = wave_sum_f64(pacc[k]);
+        if (lane == 0) a.proj_part[((long)ch * a.nproj + k) * P + p] = v;
       }
-    }
-    if (a.do_propose) {
-      const double xp0 = propose1(r0, x0, a.rho, n0), xp1 = propose1(r1, x1, a.rho, n1);
-      if (a.vh) {
-        u16 h0, l0, h1, l1;
-        const float2 sv = *(const float2*)(a.vsc + i);
-        const double s0 = (xp0 - m0) * (double)sv.x, s1 = (xp1 - m1) * (double)sv.y;
-        if (fmax(fabs(s0), fabs(s1)) >= H2_RANGE) atomicOr(a.err, 2);
-        split_f16(s0, h0, l0);
-        split_f16(s1, h1, l1);
-        *(uint32_t*)(a.vh + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        *(uint32_t*)(a.vh + (long)d * P + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
-      } else {
-        const long ev = i + (long)p * (a.ldv ? a.ldv : d);
-        if (a.v32 || PR != P64) *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - m0), (float)(xp1 - m1));
-        else *(double2*)((double*)a.V + ev) = make_double2(xp0 - m0, xp1 - m1);
-      }
-      const double zp0 = __fma_rn(a.c, wn0, a.rho * z0), zp1 = __fma_rn(a.c, wn1, a.rho * z1);
-      zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
-      xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
-    }
-  }
-  if (a.do_propose) {
-    zacc = wave_sum_f64(zacc);
-    if (lane == 0) a.zq_part_nxt[(long)p * nch + ch] = zacc;
-    if (a.prior_w > 0.0) {
-      xacc = wave_sum_f64(xacc);
-      if (lane == 0) a.pq_part_nxt[(long)p * nch + ch] = xacc;
-    }
-  }
-  if (a.do_accept && a.nproj > 0) {
-    for (int k = 0; k < a.nproj; ++k) {
-      const double v = wave_sum_f64(pacc[k]);
-      if (lane == 0) a.proj_part[((long)ch * a.nproj + k) * P + p] = v;
     }
   }
 }
@@ -2206,8 +2240,8 @@ DEV void step_update2(const StepArgs& a, int ch, int nch, int pq) {
 // eight waves per SIMD: the P * d / 128 waves of a step at P = 256, d = 4096
 // fit the chip in one round (the argument block alone would hold it to seven)
 template <int PR, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_step(StepArgs a, int nch) {
-  if (MODE == 2 && (a.d & 1) == 0) step_update2<PR>(a, blockIdx.x, nch, blockIdx.y);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8 / STEP_CPW))) void k_step(StepArgs a, int nch) {
+  if (MODE == 2 && (a.d & 1) == 0) step_update2<PR, STEP_CPW>(a, blockIdx.x, nch, blockIdx.y);
   else step_body<PR, MODE>(a, blockIdx.x, nch, blockIdx.y);
 }
 
@@ -2216,7 +2250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // decision.
 hipError_t step(const StepArgs& a, hipStream_t s) {
   const int nch = step_chunks(a.d);
-  const dim3 gupd(nch, cdiv(a.P, 4));
+  const dim3 gupd((a.d & 1) == 0 ? cdiv(nch, STEP_CPW) : nch, cdiv(a.P, 4));
   // the decision moves into the update launch where one wavefront can take it
   StepArgs b = a;
   b.fuse_dec = a.do_accept && !a.da && a.nrb <= 64 && nch <= 64 && (a.d & 1) == 0;
