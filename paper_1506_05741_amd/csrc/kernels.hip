@@ -191,7 +191,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict
                                                           int d, int P, float* __restrict__ Yp) {
   typedef W32Frag<BM, BN, WGM, WGN> F;
   __shared__ __attribute__((aligned(1024))) u16 lds[h2_lds_elems<BM, BN, ST>()];
-  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
+  int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN, ks = blockIdx.z;
+  if (gridDim.y == 1 && gridDim.z == 1) {
+    // one-dimensional grid: workgroups go round-robin to the eight XCDs, and
+    // XCDs x and x + 4 take K range x mod 4, each half of the (row, chain)
+    // tiles, a row block's chain tiles adjacent; an XCD then reads only its
+    // quarter of x - mu and each tile of R once (requires the split into 4
+    // and an even number of (row, chain) tiles, checked by the launcher)
+    const int ncb = P / BN, half = (d / BM) * ncb / 2;
+    const int xcd = blockIdx.x & 7, q = (xcd >> 2) * half + (blockIdx.x >> 3);
+    ks = xcd & 3;
+    i0 = (q / ncb) * BM;
+    j0 = (q % ncb) * BN;
+  }
   const int kl = d / H2_KSPLIT;
   // the output pointer is loaded before the loop: a scalar load left in
   // flight there would make every LDS wait of the pipelined loop a full one
@@ -254,6 +266,9 @@ __global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__
   if ((lane & 15) == 0 && i < d) part[(long)j * nrb + rb] = -0.5 * q;
 }
 
+#ifndef TGT_H2_XMAP
+#define TGT_H2_XMAP 1
+#endif
 bool tgt_h2_ok(int d, int P) { return d % (H2_KSPLIT * 32) == 0 && d % 64 == 0 && P % 64 == 0; }
 
 size_t tgt_h2_scratch_bytes(int d, int P) { return (size_t)H2_KSPLIT * d * P * sizeof(float); }
@@ -261,7 +276,11 @@ size_t tgt_h2_scratch_bytes(int d, int P) { return (size_t)H2_KSPLIT * d * P * s
 hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rsc, int d, int P, float* Yp,
                         double* part, hipStream_t s, const double* twist) {
   // 128 x 128 tiles on 8 waves where they fit
-  if (d % 128 == 0 && P % 128 == 0)
+  static_assert(H2_KSPLIT == 4, "the XCD mapping pairs the eight XCDs with four K ranges");
+  if (d % 128 == 0 && P % 128 == 0 && (d / 128) * (P / 128) % 2 == 0 && TGT_H2_XMAP)
+    hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2, 4>), dim3((d / 128) * (P / 128) * H2_KSPLIT), dim3(512), 0, s,
+                       (const u16*)R2, (const u16*)V2, d, P, Yp);
+  else if (d % 128 == 0 && P % 128 == 0)
     hipLaunchKernelGGL((k_tgt_h2<128, 128, 4, 2, 4>), dim3(d / 128, P / 128, H2_KSPLIT), dim3(512), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
   else
