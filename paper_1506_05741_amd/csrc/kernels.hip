@@ -1684,6 +1684,7 @@ __global__ __launch_bounds__(256) void k_normals(int prec, uint32_t k0, uint32_t
       if (2 * q + 1 < total) w[2 * q + 1] = rad * sn;
     }
   } else {
+    const bool vec = (uintptr_t)W % 16 == 0 && (prec == P32 || (uintptr_t)Wlo % 8 == 0);
     for (long q = (long)blockIdx.x * 256 + threadIdx.x; 4 * q < total; q += stride) {
       const uint64_t ctr = (uint64_t)(g0 + 4 * q);
       const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
@@ -1693,6 +1694,19 @@ __global__ __launch_bounds__(256) void k_normals(int prec, uint32_t k0, uint32_t
       sincosf(6.28318530717958647692f * ub, &s1, &c1);
       sincosf(6.28318530717958647692f * ud, &s2, &c2);
       const float v[4] = {ra * c1, ra * s1, rc * c2, rc * s2};
+      if (4 * q + 3 < total && vec) {
+        // the thread's four values as one 16-byte (FP32) or two 8-byte stores
+        if (prec == P32) {
+          *(float4*)((float*)W + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          u16 hi[4], lo[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) split_bf16(v[e], hi[e], lo[e]);
+          *(uint2*)((u16*)W + 4 * q) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+          *(uint2*)((u16*)Wlo + 4 * q) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+        }
+        continue;
+      }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const long idx = 4 * q + e;
