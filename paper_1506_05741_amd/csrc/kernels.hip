@@ -993,7 +993,8 @@ DEV double readlane_f64(double v, int src) {
 constexpr int CHOL_DIAG_THREADS = 256;
 constexpr int CHOL_CB = 4;  // columns factored per workgroup barrier
 static_assert((CHOL_NB / 4) % CHOL_CB == 0, "a column block lies within one wavefront's columns");
-constexpr int CHOL_DIAG_LDS = 2 * CHOL_CB * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB + 2 * 32 * 33;  // doubles
+constexpr int CHOL_DIAG_LDS =
+    2 * CHOL_CB * CHOL_NB + CHOL_NB * (CHOL_NB + 1) + CHOL_NB + 2 * 32 * 33 + 4 * 16 * 17;  // doubles
 
 // 1/sqrt(x): hardware estimate, then two Newton-Raphson steps
 // y <- y + y (1 - x y^2) / 2 (NaN for x < 0 or NaN, +inf for x = 0)
@@ -1007,11 +1008,11 @@ DEV double rsqrt_nr(double x) {
   return y;
 }
 
-// Column c (0 .. 31) of the inverse of the lower-triangular 32 x 32 block of
+// Column c (0 .. 15) of the inverse of the lower-triangular 16 x 16 block of
 // Ls starting at (o, o), by forward substitution (four partial sums).
-DEV void tri_inverse_col32(const double (*Ls)[CHOL_NB + 1], const double* rdiag, int o, double* x, int c) {
+DEV void tri_inverse_col16(const double (*Ls)[CHOL_NB + 1], const double* rdiag, int o, double* x, int c) {
 #pragma unroll
-  for (int rr = 0; rr < 32; ++rr) {
+  for (int rr = 0; rr < 16; ++rr) {
     double s[4] = {(rr == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < rr; ++q) s[q & 3] = __fma_rn(-Ls[o + rr][o + q], x[q], s[q & 3]);
@@ -1027,6 +1028,7 @@ DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* _
   double* rdiag = sh + 2 * CHOL_CB * CHOL_NB + CHOL_NB * (CHOL_NB + 1);
   double (*Ai)[33] = (double (*)[33])(rdiag + CHOL_NB);
   double (*Ci)[33] = Ai + 32;
+  double (*Di)[16][17] = (double (*)[16][17])(Ai + 64);
   const int t = threadIdx.x, r = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   double a[H];
@@ -1111,14 +1113,54 @@ DEV void chol_diag_core(double* __restrict__ A, int d, int j0, int jn, double* _
     rdiag[r] = 1.0 / diag;
   }
   __syncthreads();
-  if (w == 0) {
-    // lanes 0 .. 31: column r of A^-1; lanes 32 .. 63: column r - 32 of C^-1
-    const int o = (r < 32) ? 0 : 32, c = r - o;
-    double x[32];
-    tri_inverse_col32(Ls, rdiag, o, x, c);
-    double (*D)[33] = (r < 32) ? Ai : Ci;
+  // the inverses of the four 16 x 16 diagonal blocks, one per wavefront
+  // (lane c < 16: column c, by substitution; zeros above the diagonal)
+  if (r < 16) {
+    double x[16];
+    tri_inverse_col16(Ls, rdiag, 16 * w, x, r);
 #pragma unroll
-    for (int q = 0; q < 32; ++q) D[q][c] = x[q];
+    for (int q = 0; q < 16; ++q) Di[w][q][r] = x[q];
+  }
+  __syncthreads();
+  // the two 32 x 32 halves, [[D0, 0], [E, D1]]^-1 = [[D0^-1, 0], [-D1^-1 E
+  // D0^-1, D1^-1]], half hh on wavefronts 2 hh and 2 hh + 1: thread u forms
+  // row u / 8, columns 2 (u % 8) .. + 1 of T = E D0^-1 into the factor's zero
+  // block Ls[o + i][o + 16 + j], then of -D1^-1 T, and copies its share of
+  // the diagonal blocks and the zero block into A^-1 (hh = 0) or C^-1
+  {
+    const int hh = w >> 1, u = t & 127, o = 32 * hh;
+    const int ui = u >> 3, uj = (u & 7) * 2;
+    double (*Dst)[33] = hh ? Ci : Ai;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double e = Ls[o + 16 + ui][o + k];
+      s0 = __fma_rn(e, Di[2 * hh][k][uj], s0);
+      s1 = __fma_rn(e, Di[2 * hh][k][uj + 1], s1);
+    }
+    Ls[o + ui][o + 16 + uj] = s0;
+    Ls[o + ui][o + 16 + uj + 1] = s1;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      Dst[ui][uj + e] = Di[2 * hh][ui][uj + e];
+      Dst[16 + ui][16 + uj + e] = Di[2 * hh + 1][ui][uj + e];
+      Dst[ui][16 + uj + e] = 0.0;
+    }
+  }
+  __syncthreads();
+  {
+    const int hh = w >> 1, u = t & 127, o = 32 * hh;
+    const int ui = u >> 3, uj = (u & 7) * 2;
+    double (*Dst)[33] = hh ? Ci : Ai;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double g = Di[2 * hh + 1][ui][k];
+      s0 = __fma_rn(-g, Ls[o + k][o + 16 + uj], s0);
+      s1 = __fma_rn(-g, Ls[o + k][o + 16 + uj + 1], s1);
+    }
+    Dst[16 + ui][uj] = s0;
+    Dst[16 + ui][uj + 1] = s1;
   }
   __syncthreads();
   // T = B A^-1 (B = rows 32 .. 63, columns 0 .. 31 of L; A^-1 lower) into
