@@ -985,11 +985,13 @@ DEV double readlane_f64(double v, int src) {
 // pivot that is not > 0 (or NaN) gives a diagonal that is not > 0.  Each
 // entry of the lower triangle sees the updates in the same order as a
 // right-looking factorisation.  The block inverse is formed as
-// [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1, C^-1]] with 32 x 32 blocks:
-// one wavefront forms A^-1 and C^-1 by substitution (lane c of each half a
-// column), then all four form the two products.
-// LDS: two buffers of CB columns, the factored block (whose zero upper-right
-// quarter then holds B A^-1), the reciprocal diagonal, A^-1 and C^-1.
+// [[A, 0], [B, C]]^-1 = [[A^-1, 0], [-C^-1 B A^-1, C^-1]] twice: each
+// wavefront inverts one 16 x 16 diagonal block by substitution (lane c a
+// column), two wavefronts per 32 x 32 half combine two of them with two
+// 16 x 16 products, then all four combine the halves (32 x 32 products).
+// LDS: two buffers of CB columns, the factored block (whose zero upper
+// triangle then holds the products' intermediate terms), the reciprocal
+// diagonal, A^-1 and C^-1 of the 32 x 32 halves, the four 16 x 16 inverses.
 constexpr int CHOL_DIAG_THREADS = 256;
 constexpr int CHOL_CB = 4;  // columns factored per workgroup barrier
 static_assert((CHOL_NB / 4) % CHOL_CB == 0, "a column block lies within one wavefront's columns");
