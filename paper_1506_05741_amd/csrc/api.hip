@@ -689,6 +689,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
   ps = prof_begin(c, DIAM_ST_STEP);
   HIPCHK(dk::step(a, s));
   prof_end(c, ps);
+  // mixed Gaussian form: the target's K-split reduction runs inside the step
+  const bool fuse_h2 = c->h2 && !c->da_on && dk::step_h2_ok(d, P, c->nrb);
   for (int t = 0; t < n; ++t) {
     const int cu = c->cur, nx = cu ^ 1;
     const double* u_t = Up + (long)t * stages * P;
@@ -706,7 +708,7 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
       HIPCHK(dk::tgt_logreg(c->tgt.A, c->tgt.y, c->tgt.n_obs, c->da_on ? c->Vs : (const float*)c->V, d, P,
                             c->da_on ? c->nsurv : nullptr, c->lpp_part, s));
     else if (c->h2)
-      HIPCHK(dk::tgt_gauss_h2(c->R2, c->V2, c->rsc, d, P, c->Yp, c->lpp_part, s, c->tgt.twist));
+      HIPCHK(dk::tgt_gauss_h2(c->R2, c->V2, c->rsc, d, P, c->Yp, fuse_h2 ? nullptr : c->lpp_part, s, c->tgt.twist));
     else
       HIPCHK(dk::tgt_gauss(prec, c->tgt.R, c->V, d, P, c->lpp_part, s, c->tgt.twist));
     prof_end(c, ps);
@@ -745,7 +747,8 @@ extern "C" int diam_step_batch(diam_ctx* c, int32_t n, const double* W, const do
     a.wlo_nxt = at(Wlop, (long)(t + 1) * dP, 2);
     a.zq_part_nxt = c->zq_part + (long)nx * c->nch * P;
     ps = prof_begin(c, DIAM_ST_STEP);
-    HIPCHK(dk::step(a, s));
+    if (fuse_h2) HIPCHK(dk::step_h2(a, c->Yp, c->rsc, c->lpp_part, c->tgt.twist, s));
+    else HIPCHK(dk::step(a, s));
     prof_end(c, ps);
     c->cur = nx;
   }

@@ -41,6 +41,8 @@ hipError_t h2_scales(const double* X, const double* mu, const double* L, const f
                      uint16_t* R2, double* rsc, hipStream_t s, int states_only = 0);
 hipError_t h2_split_v(const double* X, const double* mu, const float* vsc, int d, int P, uint16_t* V2,
                       hipStream_t s);
+// Products into the K-split partials Yp, then their reduction into part; with
+// part = nullptr the products only (the reduction then runs in step_h2).
 hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rsc, int d, int P, float* Yp,
                         double* part, hipStream_t s, const double* twist = nullptr);
 // Logistic: part[p][rb] = sum_{j in rb} y_j t_jp - softplus(t_jp), t = A x'
@@ -163,6 +165,13 @@ struct StepArgs {
   int32_t* wacc;                          // P: accepted proposals since the last update (optional)
 };
 hipError_t step(const StepArgs& a, hipStream_t s);
+// One accepting step of the mixed form with the half target's reduction:
+// the products of tgt_gauss_h2 (called with part = nullptr) in Yp, reduced,
+// decided and applied in one launch (no delayed acceptance; d a multiple of
+// 256 up to 4096).
+bool step_h2_ok(int d, int P, int nrb);
+hipError_t step_h2(const StepArgs& a, const float* Yp, const double* rsc, double* part, const double* twist,
+                   hipStream_t s);
 // PSRF accumulators (Section 2.4.2, M = 1): merge the nw stored states of
 // each chain of the window (store shifted by xr, column p + P t) into the
 // running per-chain means and sums of squared deviations (d x P each) that

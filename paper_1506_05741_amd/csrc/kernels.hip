@@ -231,14 +231,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_tgt_h2(const u16* __restrict
 // wave per chain and four 64-row blocks: lane l takes rows 4l .. 4l + 3 of the
 // wave's 256 (16-byte loads), sixteen lanes make one block (d is a multiple
 // of 64, so a block is wholly inside or outside).
-__global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__ Yp, const double* __restrict__ rsc,
-                                                       int d, int P, int nrb, double* __restrict__ part,
-                                                       const double* __restrict__ twist) {
+// Rows 256 q4 .. 256 q4 + 255 of chain j on one wavefront: the four row-block
+// terms go to part; every lane returns its block's term.
+DEV double h2_reduce_wave(const float* __restrict__ Yp, const double* __restrict__ rsc, int d, int P, int nrb,
+                          double* __restrict__ part, const double* __restrict__ twist, int j, int q4) {
   const int lane = threadIdx.x & 63;
-  const int nq = (nrb + 3) / 4;
-  const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wid >= (long)P * nq) return;
-  const int j = (int)(wid / nq), q4 = (int)(wid % nq);
   const int i = q4 * 256 + 4 * lane;
   double q = 0.0;
   if (i < d) {
@@ -264,6 +261,16 @@ __global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__
   q = row16_sum_f64(q);
   const int rb = q4 * 4 + (lane >> 4);
   if ((lane & 15) == 0 && i < d) part[(long)j * nrb + rb] = -0.5 * q;
+  return -0.5 * q;
+}
+
+__global__ __launch_bounds__(256) void k_tgt_h2_reduce(const float* __restrict__ Yp, const double* __restrict__ rsc,
+                                                       int d, int P, int nrb, double* __restrict__ part,
+                                                       const double* __restrict__ twist) {
+  const int nq = (nrb + 3) / 4;
+  const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wid >= (long)P * nq) return;
+  h2_reduce_wave(Yp, rsc, d, P, nrb, part, twist, (int)(wid / nq), (int)(wid % nq));
 }
 
 #ifndef TGT_H2_XMAP
@@ -286,6 +293,7 @@ hipError_t tgt_gauss_h2(const uint16_t* R2, const uint16_t* V2, const double* rs
   else
     hipLaunchKernelGGL((k_tgt_h2<64, 64, 2, 2, 4>), dim3(d / 64, P / 64, H2_KSPLIT), dim3(256), 0, s,
                        (const u16*)R2, (const u16*)V2, d, P, Yp);
+  if (!part) return hipGetLastError();  // the reduction runs inside the step (step_h2)
   const int nrb = tgt_row_blocks(d);
   const long waves = (long)P * ((nrb + 3) / 4);
   hipLaunchKernelGGL(k_tgt_h2_reduce, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, (const float*)Yp, rsc, d,
@@ -2124,9 +2132,10 @@ __global__ __launch_bounds__(256) void k_decide(StepArgs a, int nch) { decide_bl
 // shuffle sum plus exact zeros, so these sums, log alpha and the verdict are
 // bitwise decide_block's.  Every row-chunk workgroup of the chain takes the
 // (cheap, L2-resident) decision; only `write` stores its outputs.
-DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write) {
+// parts: the chain's nrb target partials (global memory or LDS).
+DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double* parts) {
   const int lane = threadIdx.x & 63;
-  double s = lane < a.nrb ? 0.0 + a.lpp_part[(long)p * a.nrb + lane] : 0.0;
+  double s = lane < a.nrb ? 0.0 + parts[lane] : 0.0;
   s = wave_sum_f64(s);
   if (a.prior_w > 0.0) {
     double pq = lane < nch ? 0.0 + a.pq_part_cur[(long)p * nch + lane] : 0.0;
@@ -2200,67 +2209,79 @@ DEV void store_win2(void* win, long e, double v0, double v1) {
   }
 }
 
-// The update of chain 4 pq + (wave) over row chunks CPW cb .. CPW cb + CPW - 1
-// (STEP_RCH rows each; chunks past nch are skipped).  The wavefront takes
-// the chain's decision once, issues every load that does not depend on it
-// first, and keeps one partial per chunk, so the partials are those of one
-// chunk per wavefront whatever CPW is.
-template <int PR, int CPW = 1>
-DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int p = pq * 4 + w;
-  if (p >= a.P) return;
-  const int d = a.d, P = a.P;
-  const long ldw = a.ldw ? a.ldw : d;
+// The update of chain p over row chunks CPW cb .. CPW cb + CPW - 1 (STEP_RCH
+// rows each; chunks past nch are skipped), one wavefront, in two phases:
+// upd_load issues every load that does not depend on the chain's decision,
+// upd_finish takes the decision, loads the accepted proposal's Xi and W,
+// and stores.  One partial per chunk, so the partials are those of one chunk
+// per wavefront whatever CPW is.
+template <int PR, int CPW>
+struct UpdRegs {
   int ii[CPW];
   bool in[CPW];
   double x0[CPW], x1[CPW], z0[CPW], z1[CPW], r0[CPW], r1[CPW];
-  double c0[CPW], c1[CPW], wc0[CPW], wc1[CPW], n0[CPW], n1[CPW], wn0[CPW], wn1[CPW], m0[CPW], m1[CPW];
+  double n0[CPW], n1[CPW], wn0[CPW], wn1[CPW], m0[CPW], m1[CPW];
   float2 sv[CPW];
+};
+
+template <int PR, int CPW>
+DEV void upd_load(const StepArgs& a, int p, int cb, int nch, UpdRegs<PR, CPW>& g) {
+  const int lane = threadIdx.x & 63;
+  const int d = a.d;
+  const long ldw = a.ldw ? a.ldw : d;
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     const int ch = cb * CPW + c;
-    ii[c] = ch * STEP_RCH + 2 * lane;
-    in[c] = ch < nch && ii[c] < d;  // d even: the pair lies wholly inside or outside
-    x0[c] = x1[c] = z0[c] = z1[c] = r0[c] = r1[c] = 0.0;
-    c0[c] = c1[c] = wc0[c] = wc1[c] = n0[c] = n1[c] = wn0[c] = wn1[c] = m0[c] = m1[c] = 0.0;
-    sv[c] = make_float2(0.f, 0.f);
-    if (in[c]) {
-      const int i = ii[c];
+    g.ii[c] = ch * STEP_RCH + 2 * lane;
+    g.in[c] = ch < nch && g.ii[c] < d;  // d even: the pair lies wholly inside or outside
+    g.x0[c] = g.x1[c] = g.z0[c] = g.z1[c] = g.r0[c] = g.r1[c] = 0.0;
+    g.n0[c] = g.n1[c] = g.wn0[c] = g.wn1[c] = g.m0[c] = g.m1[c] = 0.0;
+    g.sv[c] = make_float2(0.f, 0.f);
+    if (g.in[c]) {
+      const int i = g.ii[c];
       const long e = i + (long)p * d, ew = i + (long)p * ldw;
       const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e);
       const double2 rv = *(const double2*)(a.xr + i);
-      x0[c] = xv.x; x1[c] = xv.y; z0[c] = zv.x; z1[c] = zv.y; r0[c] = rv.x; r1[c] = rv.y;
+      g.x0[c] = xv.x; g.x1[c] = xv.y; g.z0[c] = zv.x; g.z1[c] = zv.y; g.r0[c] = rv.x; g.r1[c] = rv.y;
       if (a.do_propose) {
-        load_xi2<PR>(a.xi_nxt, ew, n0[c], n1[c]);
-        load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, wn0[c], wn1[c]);
+        load_xi2<PR>(a.xi_nxt, ew, g.n0[c], g.n1[c]);
+        load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, g.wn0[c], g.wn1[c]);
         if (a.mu) {
           const double2 mv = *(const double2*)(a.mu + i);
-          m0[c] = mv.x; m1[c] = mv.y;
+          g.m0[c] = mv.x; g.m1[c] = mv.y;
         }
-        if (a.vh) sv[c] = *(const float2*)(a.vsc + i);
+        if (a.vh) g.sv[c] = *(const float2*)(a.vsc + i);
       }
     }
   }
-  const bool acc = a.do_accept && (a.fuse_dec ? decide_wave(a, nch, p, cb == 0) : a.acc_out[p] != 0);
+}
+
+template <int PR, int CPW>
+DEV void upd_finish(const StepArgs& a, int p, int cb, int nch, bool acc, const UpdRegs<PR, CPW>& g) {
+  const int lane = threadIdx.x & 63;
+  const int d = a.d, P = a.P;
+  const long ldw = a.ldw ? a.ldw : d;
+  double c0[CPW], c1[CPW], wc0[CPW], wc1[CPW];
 #pragma unroll
-  for (int c = 0; c < CPW; ++c)
-    if (in[c] && acc) {
-      const long ew = ii[c] + (long)p * ldw;
+  for (int c = 0; c < CPW; ++c) {
+    c0[c] = c1[c] = wc0[c] = wc1[c] = 0.0;
+    if (g.in[c] && acc) {
+      const long ew = g.ii[c] + (long)p * ldw;
       load_xi2<PR>(a.xi_cur, ew, c0[c], c1[c]);
       load_w2<PR>(a.w_cur, a.wlo_cur, ew, wc0[c], wc1[c]);
     }
+  }
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     const int ch = cb * CPW + c;
     if (ch >= nch) break;
-    const int i = ii[c];
+    const int i = g.ii[c];
     const long e = i + (long)p * d;
     double zacc = 0.0, xacc = 0.0;
     double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
-    if (in[c]) {
-      double xa = x0[c], xb = x1[c], za = z0[c], zb = z1[c];
-      const double ra = r0[c], rb = r1[c];
+    if (g.in[c]) {
+      double xa = g.x0[c], xb = g.x1[c], za = g.z0[c], zb = g.z1[c];
+      const double ra = g.r0[c], rb = g.r1[c];
       if (a.do_accept) {
         if (acc) {
           xa = propose1(ra, xa, a.rho, c0[c]);
@@ -2277,10 +2298,10 @@ DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
         }
       }
       if (a.do_propose) {
-        const double xp0 = propose1(ra, xa, a.rho, n0[c]), xp1 = propose1(rb, xb, a.rho, n1[c]);
+        const double xp0 = propose1(ra, xa, a.rho, g.n0[c]), xp1 = propose1(rb, xb, a.rho, g.n1[c]);
         if (a.vh) {
           u16 h0, l0, h1, l1;
-          const double s0 = (xp0 - m0[c]) * (double)sv[c].x, s1 = (xp1 - m1[c]) * (double)sv[c].y;
+          const double s0 = (xp0 - g.m0[c]) * (double)g.sv[c].x, s1 = (xp1 - g.m1[c]) * (double)g.sv[c].y;
           if (fmax(fabs(s0), fabs(s1)) >= H2_RANGE) atomicOr(a.err, 2);
           split_f16(s0, h0, l0);
           split_f16(s1, h1, l1);
@@ -2289,10 +2310,10 @@ DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
         } else {
           const long ev = i + (long)p * (a.ldv ? a.ldv : d);
           if (a.v32 || PR != P64)
-            *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - m0[c]), (float)(xp1 - m1[c]));
-          else *(double2*)((double*)a.V + ev) = make_double2(xp0 - m0[c], xp1 - m1[c]);
+            *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - g.m0[c]), (float)(xp1 - g.m1[c]));
+          else *(double2*)((double*)a.V + ev) = make_double2(xp0 - g.m0[c], xp1 - g.m1[c]);
         }
-        const double zp0 = __fma_rn(a.c, wn0[c], a.rho * za), zp1 = __fma_rn(a.c, wn1[c], a.rho * zb);
+        const double zp0 = __fma_rn(a.c, g.wn0[c], a.rho * za), zp1 = __fma_rn(a.c, g.wn1[c], a.rho * zb);
         zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
         xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
       }
@@ -2312,6 +2333,40 @@ DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
       }
     }
   }
+}
+
+// The update of chain 4 pq + (wave) over the chunks of cb.
+template <int PR, int CPW = 1>
+DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
+  const int w = threadIdx.x >> 6;
+  const int p = pq * 4 + w;
+  if (p >= a.P) return;
+  UpdRegs<PR, CPW> g;
+  upd_load<PR, CPW>(a, p, cb, nch, g);
+  const bool acc =
+      a.do_accept && (a.fuse_dec ? decide_wave(a, nch, p, cb == 0, a.lpp_part + (long)p * a.nrb) : a.acc_out[p] != 0);
+  upd_finish<PR, CPW>(a, p, cb, nch, acc, g);
+}
+
+// One step of the mixed form with the half target's reduction folded in:
+// workgroup p (d / 256 wavefronts) issues its update loads, reduces the
+// K-split partial products of its rows into the row-block terms of log pi
+// (stored to part as the separate reduction does, and kept in LDS), then
+// every wavefront takes the chain's decision from the LDS terms (bitwise the
+// sums of the separate path) and updates its two 128-row chunks; wavefront 0
+// writes the decision's outputs.
+__global__ __launch_bounds__(1024) void k_step_h2(StepArgs a, int nch, const float* __restrict__ Yp,
+                                                  const double* __restrict__ rsc, double* __restrict__ part,
+                                                  const double* __restrict__ twist) {
+  __shared__ double lpp[64];
+  const int p = blockIdx.x, v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  UpdRegs<PMIX, 2> g;
+  upd_load<PMIX, 2>(a, p, v, nch, g);
+  const double q = h2_reduce_wave(Yp, rsc, a.d, a.P, a.nrb, part, twist, p, v);
+  if ((lane & 15) == 0) lpp[v * 4 + (lane >> 4)] = q;
+  __syncthreads();
+  const bool acc = decide_wave(a, nch, p, v == 0, lpp);
+  upd_finish<PMIX, 2>(a, p, v, nch, acc, g);
 }
 
 // eight waves per SIMD: the P * d / 128 waves of a step at P = 256, d = 4096
@@ -2335,6 +2390,19 @@ hipError_t step(const StepArgs& a, hipStream_t s) {
   if (a.prec == P64) hipLaunchKernelGGL((k_step<P64, 2>), gupd, dim3(256), 0, s, b, nch);
   else if (a.prec == P32) hipLaunchKernelGGL((k_step<P32, 2>), gupd, dim3(256), 0, s, b, nch);
   else hipLaunchKernelGGL((k_step<PMIX, 2>), gupd, dim3(256), 0, s, b, nch);
+  return hipGetLastError();
+}
+
+bool step_h2_ok(int d, int P, int nrb) {
+  return d % 256 == 0 && d <= 4096 && nrb == d / 64 && step_chunks(d) <= 64 && tgt_h2_ok(d, P);
+}
+
+hipError_t step_h2(const StepArgs& a, const float* Yp, const double* rsc, double* part, const double* twist,
+                   hipStream_t s) {
+  if (a.prec != PMIX || !a.vh || !a.do_accept || a.da || !step_h2_ok(a.d, a.P, a.nrb)) return hipErrorInvalidValue;
+  StepArgs b = a;
+  b.fuse_dec = 1;
+  hipLaunchKernelGGL(k_step_h2, dim3(a.P), dim3(64 * (a.d / 256)), 0, s, b, step_chunks(a.d), Yp, rsc, part, twist);
   return hipGetLastError();
 }
 
@@ -2614,7 +2682,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void gk_persist(const BProb* __res
       const StepArgs a = g_step_args(b, sp, g);
       const int w = threadIdx.x >> 6;
       if (kind == 1) {
-        for (int p = w; p < st.P; p += PERSIST_THREADS / 64) decide_wave(a, b.nch, p, true);
+        for (int p = w; p < st.P; p += PERSIST_THREADS / 64) decide_wave(a, b.nch, p, true, a.lpp_part + (long)p * a.nrb);
       } else {
         // eight waves: chains 8k .. 8k + 7 per pass (the bodies take chain 4 pq + wave)
         for (int pq = 0; pq * 4 < st.P; pq += PERSIST_THREADS / 256) {
