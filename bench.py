@@ -33,9 +33,11 @@ HBM_PEAK = 8.0e12
 # HBM bytes per launch of the target kernels from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE runs scaled by a device copy's counters (see profiles/); a
 # kernel missing here has changed since its counters were taken.
-# HBM bytes per target step at d=4096, P=256 (k_tgt_h2 + k_tgt_h2_reduce), from FETCH_SIZE x 2 + WRITE_SIZE
-# (profiles/hbm_traffic_k_tgt_h2_d4096_P256.md); taken for the kernels as they stand
-TRAFFIC = {"k_tgt_h2": (36894.5 * 2 + 16384.0 + 8246.0 * 2 + 128.0) * 1024}
+# HBM bytes per launch of k_tgt_h2 at d=4096, P=256 (the target's products;
+# their K-split reduction runs inside the step kernel k_step_h2), from
+# FETCH_SIZE x 2 + WRITE_SIZE (profiles/hbm_traffic_k_tgt_h2_d4096_P256.md);
+# taken for the kernel as it stands
+TRAFFIC = {"k_tgt_h2": (36894.5 * 2 + 16384.0) * 1024}
 
 
 def log(msg):
@@ -848,8 +850,8 @@ def main():
         # product: frac counts the method's 2 d^2 P flops, executed_frac the
         # three products the matrix cores run
         traffic = TRAFFIC.get("k_tgt_h2") if (args.d, args.P) == (4096, 256) else None
-        roofline = {"kernel": "k_tgt_h2 + k_tgt_h2_reduce (two-part half MFMA, FP32-equivalent; Y = R (x - mu), "
-                              "column sums of Y^2)",
+        roofline = {"kernel": "k_tgt_h2 (two-part half MFMA, FP32-equivalent; Y = R (x - mu) as four K-split "
+                              "partials, reduced and squared inside the step kernel k_step_h2)",
                     "bound": "mfma", "achieved": useful / dt / 1e12, "peak": PEAK["fp16"] / 1e12,
                     "unit": "TFLOP/s", "frac": useful / dt / PEAK["fp16"],
                     "traffic": traffic,
