@@ -37,7 +37,7 @@ HBM_PEAK = 8.0e12
 # their K-split reduction runs inside the step kernel k_step_h2), from
 # FETCH_SIZE x 2 + WRITE_SIZE (profiles/hbm_traffic_k_tgt_h2_d4096_P256.md);
 # taken for the kernel as it stands
-TRAFFIC = {"k_tgt_h2": (36894.5 * 2 + 16384.0) * 1024}
+TRAFFIC = {"k_tgt_h2": (36902.5 * 2 + 16384.0) * 1024}
 
 
 def log(msg):
