@@ -2164,6 +2164,8 @@ DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double
 // Paired-row loads and stores for the update half (d even, so that every
 // chain's column starts on an even element): lane l owns rows 2l, 2l + 1 of
 // its 128-row chunk and moves them with 16-, 8- or 4-byte accesses.
+// 128-row chunks per wavefront of the update (two: half the wavefronts take
+// the same decision; one or four ran slower at d = 4096, P = 256)
 #ifndef STEP_CPW
 #define STEP_CPW 2
 #endif
@@ -2369,8 +2371,9 @@ __global__ __launch_bounds__(1024) void k_step_h2(StepArgs a, int nch, const flo
   upd_finish<PMIX, 2>(a, p, v, nch, acc, g);
 }
 
-// eight waves per SIMD: the P * d / 128 waves of a step at P = 256, d = 4096
-// fit the chip in one round (the argument block alone would hold it to seven)
+// STEP_CPW chunks per wavefront and 8 / STEP_CPW waves per SIMD: the
+// P * d / (128 STEP_CPW) wavefronts of a step at P = 256, d = 4096 fit the
+// chip in one round (the argument block alone would hold it below that)
 template <int PR, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8 / STEP_CPW))) void k_step(StepArgs a, int nch) {
   if (MODE == 2 && (a.d & 1) == 0) step_update2<PR, STEP_CPW>(a, blockIdx.x, nch, blockIdx.y);
