@@ -2685,7 +2685,8 @@ __global__ __launch_bounds__(PERSIST_THREADS) void gk_persist(const BProb* __res
       const StepArgs a = g_step_args(b, sp, g);
       const int w = threadIdx.x >> 6;
       if (kind == 1) {
-        for (int p = w; p < st.P; p += PERSIST_THREADS / 64) decide_wave(a, b.nch, p, true, a.lpp_part + (long)p * a.nrb);
+        for (int p = w; p < st.P; p += PERSIST_THREADS / 64)
+          decide_wave(a, b.nch, p, true, a.lpp_part + (long)p * a.nrb);
       } else {
         // eight waves: chains 8k .. 8k + 7 per pass (the bodies take chain 4 pq + wave)
         for (int pq = 0; pq * 4 < st.P; pq += PERSIST_THREADS / 256) {
