@@ -1365,9 +1365,44 @@ __global__ __launch_bounds__(256) void k_round_factor(int prec, double* __restri
   if (e < (long)d * d) round_factor_elem(prec, L, Llow, d, e);
 }
 
+// The mixed form's rounding by 64 x 64 tiles: the column-major factor is
+// read and written back along its columns, and the row-major hi and lo
+// copies leave through an LDS transpose along their rows (each element's
+// arithmetic is round_factor_elem's).
+__global__ __launch_bounds__(256) void k_round_factor_hl(double* __restrict__ L, u16* __restrict__ Llow, int d) {
+  __shared__ u16 th[64][66], tl[64][66];  // [column][row] of the tile
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int i = i0 + tx, j = j0 + jj;
+    u16 hi = 0, lo = 0;
+    if (i < d && j < d) {
+      const long e = i + (long)j * d;
+      const double v = (i >= j) ? L[e] : 0.0;
+      hi = f32_to_bf16_bits((float)v);
+      const double rem = v - (double)bf16_bits_to_f32(hi);
+      lo = f32_to_bf16_bits((float)rem);
+      L[e] = (double)bf16_bits_to_f32(hi) + (double)bf16_bits_to_f32(lo);
+    }
+    th[jj][tx] = hi;
+    tl[jj][tx] = lo;
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int i = i0 + ii, j = j0 + tx;
+    if (i < d && j < d) {
+      Llow[(long)i * d + j] = th[tx][ii];
+      Llow[(long)d * d + (long)i * d + j] = tl[tx][ii];
+    }
+  }
+}
+
 hipError_t round_factor(Prec prec, double* L, void* Llow, int d, hipStream_t s) {
   if (prec == P64) return hipSuccess;
-  hipLaunchKernelGGL(k_round_factor, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, (int)prec, L, Llow, d);
+  if (prec == PMIX)
+    hipLaunchKernelGGL(k_round_factor_hl, dim3(cdiv(d, 64), cdiv(d, 64)), dim3(256), 0, s, L, (u16*)Llow, d);
+  else
+    hipLaunchKernelGGL(k_round_factor, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, (int)prec, L, Llow, d);
   return hipGetLastError();
 }
 
