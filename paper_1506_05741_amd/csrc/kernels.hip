@@ -887,16 +887,37 @@ __global__ __launch_bounds__(256) void k_fold_mean(const double* __restrict__ h,
   if (i < d) fold_mean_elem(h, sft, N, n, m, i);
 }
 
+// fold_S_elem by 64 x 64 tiles of S: the scatter's upper-storage tile that
+// holds the tile's values, G(min(i, j), max(i, j)), is read along its columns
+// into LDS first, so the tiles below the diagonal do not read G at a stride
+// of d (each element's arithmetic is fold_S_elem's).
 __global__ __launch_bounds__(256) void k_fold_S(const double* __restrict__ G, const double* __restrict__ h,
                                                 const double* __restrict__ sft, double N, double n,
                                                 double* __restrict__ S, int d) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e < (long)d * d) fold_S_elem(G, h, sft, N, n, S, d, e);
+  __shared__ double T[64][65];
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int r0 = 64 * min(bx, by), c0 = 64 * max(bx, by);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int c = ty; c < 64; c += 4) {
+    const int r = r0 + tx, cc = c0 + c;
+    T[tx][c] = (r < d && cc < d) ? G[r + (long)cc * d] : 0.0;
+  }
+  __syncthreads();
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int i = 64 * bx + tx, j = 64 * by + jj;
+    if (i < d && j < d) {
+      const int a = i > j ? i : j, b = i > j ? j : i;
+      const double g = T[b - r0][a - c0];
+      const long e = i + (long)j * d;
+      const double sxx = g + sft[a] * h[b] + h[a] * sft[b] + n * sft[a] * sft[b];
+      S[e] = (N * S[e] + sxx) / (N + n);
+    }
+  }
 }
 
 hipError_t fold_moments(const double* G, const double* h, const double* sft, double N, long K, double* S, double* m,
                         int d, hipStream_t s) {
-  hipLaunchKernelGGL(k_fold_S, dim3(cdiv((long)d * d, 256)), dim3(256), 0, s, G, h, sft, N, (double)K, S, d);
+  hipLaunchKernelGGL(k_fold_S, dim3(cdiv(d, 64), cdiv(d, 64)), dim3(256), 0, s, G, h, sft, N, (double)K, S, d);
   hipLaunchKernelGGL(k_fold_mean, dim3(cdiv(d, 256)), dim3(256), 0, s, h, sft, N, (double)K, m, d);
   return hipGetLastError();
 }
