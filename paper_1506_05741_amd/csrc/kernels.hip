@@ -1776,11 +1776,27 @@ hipError_t trsm_whiten_batched(const double* L, long sA, const double* X, const 
 // ============================================================================
 // random numbers: Philox4x32-10 counters (stream 0 = W, 1 + g = U stage g)
 // ============================================================================
+// Four FP32 normals from counter ctr of the stream (Box-Muller on the four
+// 24-bit uniforms of one Philox block).
+DEV void normals4_f32(uint32_t k0, uint32_t k1, uint64_t ctr, float* v) {
+  const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
+  const float ua = u01_f32(r.x), ub = u01_f32(r.y), uc = u01_f32(r.z), ud = u01_f32(r.w);
+  const float ra = sqrtf(-2.0f * logf(ua)), rc = sqrtf(-2.0f * logf(uc));
+  float s1, c1, s2, c2;
+  sincosf(6.28318530717958647692f * ub, &s1, &c1);
+  sincosf(6.28318530717958647692f * ud, &s2, &c2);
+  v[0] = ra * c1;
+  v[1] = ra * s1;
+  v[2] = rc * c2;
+  v[3] = rc * s2;
+}
+
 __global__ __launch_bounds__(256) void k_normals(int prec, uint32_t k0, uint32_t k1, long g0, long total,
                                                  void* __restrict__ W, void* __restrict__ Wlo) {
   const long stride = (long)gridDim.x * 256;
+  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
   if (prec == P64) {
-    for (long q = (long)blockIdx.x * 256 + threadIdx.x; 2 * q < total; q += stride) {
+    for (long q = gid; 2 * q < total; q += stride) {
       const uint64_t ctr = (uint64_t)(g0 + 2 * q);
       const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
       const double u1 = u01_f64(r.x, r.y), u2 = u01_f64(r.z, r.w);
@@ -1793,15 +1809,9 @@ __global__ __launch_bounds__(256) void k_normals(int prec, uint32_t k0, uint32_t
     }
   } else {
     const bool vec = (uintptr_t)W % 16 == 0 && (prec == P32 || (uintptr_t)Wlo % 8 == 0);
-    for (long q = (long)blockIdx.x * 256 + threadIdx.x; 4 * q < total; q += stride) {
-      const uint64_t ctr = (uint64_t)(g0 + 4 * q);
-      const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
-      const float ua = u01_f32(r.x), ub = u01_f32(r.y), uc = u01_f32(r.z), ud = u01_f32(r.w);
-      const float ra = sqrtf(-2.0f * logf(ua)), rc = sqrtf(-2.0f * logf(uc));
-      float s1, c1, s2, c2;
-      sincosf(6.28318530717958647692f * ub, &s1, &c1);
-      sincosf(6.28318530717958647692f * ud, &s2, &c2);
-      const float v[4] = {ra * c1, ra * s1, rc * c2, rc * s2};
+    for (long q = gid; 4 * q < total; q += stride) {
+      float v[4];
+      normals4_f32(k0, k1, (uint64_t)(g0 + 4 * q), v);
       if (4 * q + 3 < total && vec) {
         // the thread's four values as one 16-byte (FP32) or two 8-byte stores
         if (prec == P32) {
@@ -2555,15 +2565,14 @@ __global__ __launch_bounds__(256) void gk_normals(uint32_t k0, uint32_t k1, cons
                                                   long per_window, long total, float* __restrict__ W) {
   const long g0 = *win * per_window;
   const long stride = (long)gridDim.x * 256;
+  const bool vec = (uintptr_t)W % 16 == 0;
   for (long q = (long)blockIdx.x * 256 + threadIdx.x; 4 * q < total; q += stride) {
-    const uint64_t ctr = (uint64_t)(g0 + 4 * q);
-    const u4_t r = philox4x32_10({(uint32_t)ctr, (uint32_t)(ctr >> 32), 0u, 0u}, k0, k1);
-    const float ua = u01_f32(r.x), ub = u01_f32(r.y), uc = u01_f32(r.z), ud = u01_f32(r.w);
-    const float ra = sqrtf(-2.0f * logf(ua)), rc = sqrtf(-2.0f * logf(uc));
-    float s1, c1, s2, c2;
-    sincosf(6.28318530717958647692f * ub, &s1, &c1);
-    sincosf(6.28318530717958647692f * ud, &s2, &c2);
-    const float v[4] = {ra * c1, ra * s1, rc * c2, rc * s2};
+    float v[4];
+    normals4_f32(k0, k1, (uint64_t)(g0 + 4 * q), v);
+    if (vec && 4 * q + 3 < total) {
+      *(float4*)(W + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+      continue;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       if (4 * q + e < total) W[4 * q + e] = v[e];
