@@ -212,3 +212,40 @@ def test_mixed_target_over_coordinate_scales_from_1e_minus6_to_1e6():
     s.step_batch(n_lag)
     check("after a second window")
     s.close()
+
+
+def test_mixed_step_traces_log_density_and_projections():
+    """The mixed form's single-launch step at d = 256 (the target's K-split
+    reduction, the decision and the update in one kernel) records per step the
+    log density of the current states and their projections: checked against
+    the FP64 log density (of the FP32-rounded R the target was given) and the
+    FP64 projections of the sampler's own states, after each of three
+    single-step calls and after a call of the window's remaining steps."""
+    d, P, n_lag = 256, 64, 6
+    t, x0, s = make(d, P, n_lag, "mixed", tseed=3)
+    proj = np.stack([t.v_max, t.v_min])
+    trace = torch.zeros((n_lag, 3, P), dtype=torch.float64, device="cuda")
+    s.set_trace(dev(proj), trace)
+    R32 = t.R.astype(np.float32).astype(np.float64)
+
+    def check(row, where):
+        X = host(s.get_f64(diam.F_X, (P, d))).T
+        y = R32 @ (X - t.mu[:, None])
+        lp_ref = -0.5 * np.sum(y * y, axis=0)
+        tr = host(trace[row])
+        err = float(np.max(np.abs(tr[0] - lp_ref) / (1.0 + np.abs(lp_ref))))
+        assert err < 4 * math.sqrt(d) * 2.0 ** -24, (where, err)
+        assert np.allclose(tr[1:], proj @ X, rtol=1e-12, atol=1e-12), where
+        return X
+
+    X = host(s.get_f64(diam.F_X, (P, d))).T
+    moved = 0
+    for k in range(3):
+        s.step_batch(1)
+        Xn = check(k, f"single step {k}")
+        moved += int(np.any(Xn != X, axis=0).sum())
+        X = Xn
+    s.step_batch(n_lag - 3)  # the window holds n_lag steps
+    check(n_lag - 1, "end of a call of the remaining steps")
+    assert moved > P, moved  # most chains accepted at least once in three steps
+    s.close()
