@@ -171,10 +171,15 @@ Tiles build_tiles(const std::vector<int>& dims, int P, int n) {
     for (int bx = 0; bx < cdivh(dims[g], pbm); ++bx)
       for (int by = 0; by < cdivh(P, 32); ++by) T.pitems.push_back({0, g, bx, by, 0});
   }
-  for (int g : order) T.pitems.push_back({1, g, 0, 0, ntg[g]});
+  // a decision item only where the update items cannot take the decision
+  std::vector<int> ndec(G);
+  for (int g = 0; g < G; ++g)
+    ndec[g] = dk::persist_fused_decision(dims[g], cdivh(dims[g], pbm), dk::step_chunks(dims[g])) ? 0 : 1;
   for (int g : order)
-    for (int ch = 0; ch < dk::step_chunks(dims[g]); ++ch) T.pitems.push_back({2, g, ch, 0, ntg[g] + 1});
-  for (int g = 0; g < G; ++g) T.pstep[g] = ntg[g] + 1 + dk::step_chunks(dims[g]);
+    if (ndec[g]) T.pitems.push_back({1, g, 0, 0, ntg[g]});
+  for (int g : order)
+    for (int ch = 0; ch < dk::step_chunks(dims[g]); ++ch) T.pitems.push_back({2, g, ch, 0, ntg[g] + ndec[g]});
+  for (int g = 0; g < G; ++g) T.pstep[g] = ntg[g] + ndec[g] + dk::step_chunks(dims[g]);
   return T;
 }
 

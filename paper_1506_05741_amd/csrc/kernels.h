@@ -243,6 +243,9 @@ constexpr int PERSIST_THREADS = 512;
 // Target tile rows the persistent loop uses (the default tile shape: 64 rows,
 // two k-groups), so the decisions' partial sums fit one wavefront.
 constexpr int PERSIST_TGT_CFG = 2;
+// Problems whose update items take the chain's decision themselves (bitwise
+// the decision item's sums), so the persistent loop needs no decision item.
+__host__ __device__ inline bool persist_fused_decision(int d, int nrb, int nch) { return (d & 1) == 0 && nrb <= 64 && nch <= 64; }
 hipError_t g_persist(const BProb* pr, const PItem* items, int nitems, const BStep& st, const PCtl& ctl, int grid,
                      hipStream_t s);
 // Workgroups of the persistent loop that fit one CU at once.

@@ -2747,7 +2747,10 @@ __global__ __launch_bounds__(PERSIST_THREADS) void gk_persist(const BProb* __res
     } else {
       BStep sp = st;
       sp.t = t;
-      const StepArgs a = g_step_args(b, sp, g);
+      StepArgs a = g_step_args(b, sp, g);
+      // the update items take the decision themselves where no decision item
+      // was queued (the same predicate as the queue's construction)
+      a.fuse_dec = kind == 2 && persist_fused_decision(b.d, b.nrb, b.nch) ? 1 : 0;
       const int w = threadIdx.x >> 6;
       if (kind == 1) {
         for (int p = w; p < st.P; p += PERSIST_THREADS / 64)
