@@ -39,6 +39,29 @@ constexpr int eld() { return BK + 16 / (int)sizeof(T); }
 template <int BK>
 DEV int eperm(int k) { return (k & 3) * (BK / 4) + (k >> 2); }
 
+// Element (r, k) at which staging vector c of an operand slice starts; the
+// vector runs along k (KC) or along r.  Column-major FP64 slices with BK = 16
+// give the 16 lanes of a quarter-wavefront four row pairs at four k = k0,
+// k0 + 4, k0 + 8, k0 + 12, whose LDS slots (order eperm) are adjacent:
+// their 8-byte LDS stores then cover all banks once, where sixteen row pairs
+// at one k put four lanes on each bank; the global reads stay whole 128-byte
+// column segments.  Which thread moves which element changes nothing else.
+template <typename T, int ROWS, int BK, bool KC>
+DEV void e_slot(int c, int& r, int& k) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  if (KC) {
+    r = c / (BK / VEC);
+    k = (c % (BK / VEC)) * VEC;
+  } else if (sizeof(T) == 8 && BK == 16 && ROWS % 16 == 0) {
+    const int hi = c >> 5;
+    r = 2 * (((c >> 2) & 7) + 8 * (hi >> 2));
+    k = (hi & 3) + 4 * (c & 3);
+  } else {
+    k = c / (ROWS / VEC);
+    r = (c % (ROWS / VEC)) * VEC;
+  }
+}
+
 // Staging registers of one operand slice (ROWS x BK) for one thread of a
 // 256-thread k-group: NV vectors of VEC elements (16 bytes each).
 template <typename T, int ROWS, int BK>
@@ -61,7 +84,7 @@ DEV void e_load(EStage<T, ROWS, BK>& s, int t, const T* __restrict__ p, long ld,
   for (int e = 0; e < EStage<T, ROWS, BK>::NV; ++e) {
     const int c = t + e * NT;
     int r, k;
-    if (KC) { r = c / (BK / VEC); k = (c % (BK / VEC)) * VEC; } else { k = c / (ROWS / VEC); r = (c % (ROWS / VEC)) * VEC; }
+    e_slot<T, ROWS, BK, KC>(c, r, k);
     const int gr = r0 + r, gk = k0 + k;
     T* dst = &s.v[e * VEC];
     const T* q = KC ? p + (long)gr * ld + gk : p + gr + (long)gk * ld;
@@ -85,7 +108,7 @@ DEV void e_store(const EStage<T, ROWS, BK>& s, int t, T* lds) {
   for (int e = 0; e < EStage<T, ROWS, BK>::NV; ++e) {
     const int c = t + e * NT;
     int r, k;
-    if (KC) { r = c / (BK / VEC); k = (c % (BK / VEC)) * VEC; } else { k = c / (ROWS / VEC); r = (c % (ROWS / VEC)) * VEC; }
+    e_slot<T, ROWS, BK, KC>(c, r, k);
 #pragma unroll
     for (int x = 0; x < VEC; ++x) {
       if (KC) lds[r * LD + eperm<BK>(k + x)] = s.v[e * VEC + x];
