@@ -42,10 +42,12 @@ DEV int eperm(int k) { return (k & 3) * (BK / 4) + (k >> 2); }
 // Element (r, k) at which staging vector c of an operand slice starts; the
 // vector runs along k (KC) or along r.  Column-major FP64 slices with BK = 16
 // give the 16 lanes of a quarter-wavefront four row pairs at four k = k0,
-// k0 + 4, k0 + 8, k0 + 12, whose LDS slots (order eperm) are adjacent:
-// their 8-byte LDS stores then cover all banks once, where sixteen row pairs
-// at one k put four lanes on each bank; the global reads stay whole 128-byte
-// column segments.  Which thread moves which element changes nothing else.
+// k0 + 4, k0 + 8, k0 + 12, whose LDS slots (order eperm) are adjacent, so
+// their 8-byte LDS stores cover the banks once, where sixteen row pairs at
+// one k put four lanes on each bank.  Lane bits 0 and 3 pick the k, bits 1,
+// 2 and 4 the row pair: each group of 8 lanes then also stores both rows of
+// its pairs on distinct banks.  Which thread moves which element changes
+// nothing else.
 template <typename T, int ROWS, int BK, bool KC>
 DEV void e_slot(int c, int& r, int& k) {
   constexpr int VEC = 16 / (int)sizeof(T);
@@ -54,8 +56,10 @@ DEV void e_slot(int c, int& r, int& k) {
     k = (c % (BK / VEC)) * VEC;
   } else if (sizeof(T) == 8 && BK == 16 && ROWS % 16 == 0) {
     const int hi = c >> 5;
-    r = 2 * (((c >> 2) & 7) + 8 * (hi >> 2));
-    k = (hi & 3) + 4 * (c & 3);
+    const int q = (c & 1) | ((c >> 2) & 2);
+    const int jp = ((c >> 1) & 3) | ((c >> 2) & 4);
+    r = 2 * (jp + 8 * (hi >> 2));
+    k = (hi & 3) + 4 * q;
   } else {
     k = c / (ROWS / VEC);
     r = (c % (ROWS / VEC)) * VEC;
