@@ -99,7 +99,8 @@ DEV double u01_f64(uint32_t a, uint32_t b) {
   uint64_t k = (((uint64_t)a << 32) | b) >> 12;
   return ((double)k + 0.5) * 0x1.0p-52;
 }
-// uniform in (0,1) from 24 random bits, exact in fp32
+// uniform in (0,1) from 24 random bits, exact in fp32; a Box-Muller radius
+// sqrt(-2 ln u) built from it is at most sqrt(50 ln 2) ~ 5.89
 DEV float u01_f32(uint32_t a) { return ((float)(a >> 8) + 0.5f) * 0x1.0p-24f; }
 
 // ---- cross-lane moves without the LDS unit ---------------------------------
