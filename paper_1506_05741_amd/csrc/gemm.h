@@ -46,8 +46,13 @@ DEV int eperm(int k) { return (k & 3) * (BK / 4) + (k >> 2); }
 // their 8-byte LDS stores cover the banks once, where sixteen row pairs at
 // one k put four lanes on each bank.  Lane bits 0 and 3 pick the k, bits 1,
 // 2 and 4 the row pair: each group of 8 lanes then also stores both rows of
-// its pairs on distinct banks.  Which thread moves which element changes
-// nothing else.
+// its pairs on distinct banks.  Column-major FP32 slices with BK = 32 (a
+// vector is four rows at one k): lane bits 0 and 1 pick k among four values
+// four apart, bit 2 the neighbour k + 1, bits 3 to 5 one of eight row quads.
+// Where sixteen row quads at four adjacent k put eight lanes on one bank, a
+// wavefront's stores then meet each bank at most twice, and its global reads
+// stay eight 128-byte column segments.  Which thread moves which element
+// changes nothing else.
 template <typename T, int ROWS, int BK, bool KC>
 DEV void e_slot(int c, int& r, int& k) {
   constexpr int VEC = 16 / (int)sizeof(T);
@@ -60,6 +65,11 @@ DEV void e_slot(int c, int& r, int& k) {
     const int jp = ((c >> 1) & 3) | ((c >> 2) & 4);
     r = 2 * (jp + 8 * (hi >> 2));
     k = (hi & 3) + 4 * q;
+  } else if (sizeof(T) == 4 && BK == 32 && ROWS % 16 == 0) {
+    const int kh = (c & 3) | (((c >> 6) & 1) << 2);
+    const int j = ((c >> 3) & 7) | ((c >> 8) << 3);
+    r = 4 * j;
+    k = 4 * kh + ((c >> 2) & 1) + 2 * ((c >> 7) & 1);
   } else {
     k = c / (ROWS / VEC);
     r = (c % (ROWS / VEC)) * VEC;
