@@ -2241,32 +2241,6 @@ template <> struct Pair2<P32> { typedef float2 XI; typedef float2 W; };
 template <> struct Pair2<PMIX> { typedef float2 XI; typedef uint32_t W; };
 
 template <int PR>
-DEV void load_w2(const void* w, const void* wlo, long e, double& w0, double& w1) {
-  if (PR == P64) {
-    const double2 v = *(const double2*)((const double*)w + e);
-    w0 = v.x; w1 = v.y;
-  } else if (PR == P32) {
-    const float2 v = *(const float2*)((const float*)w + e);
-    w0 = v.x; w1 = v.y;
-  } else {
-    const uint32_t h = *(const uint32_t*)((const u16*)w + e), l = *(const uint32_t*)((const u16*)wlo + e);
-    w0 = (double)bf16_bits_to_f32((u16)(h & 0xffff)) + (double)bf16_bits_to_f32((u16)(l & 0xffff));
-    w1 = (double)bf16_bits_to_f32((u16)(h >> 16)) + (double)bf16_bits_to_f32((u16)(l >> 16));
-  }
-}
-
-template <int PR>
-DEV void load_xi2(const void* xi, long e, double& v0, double& v1) {
-  if (PR == P64) {
-    const double2 v = *(const double2*)((const double*)xi + e);
-    v0 = v.x; v1 = v.y;
-  } else {
-    const float2 v = *(const float2*)((const float*)xi + e);
-    v0 = v.x; v1 = v.y;
-  }
-}
-
-template <int PR>
 DEV void store_win2(void* win, long e, double v0, double v1) {
   if (PR == P64) {
     *(double2*)((double*)win + e) = make_double2(v0, v1);
@@ -2279,16 +2253,55 @@ DEV void store_win2(void* win, long e, double v0, double v1) {
 
 // The update of chain p over row chunks CPW cb .. CPW cb + CPW - 1 (STEP_RCH
 // rows each; chunks past nch are skipped), one wavefront, in two phases:
-// upd_load issues every load that does not depend on the chain's decision,
-// upd_finish takes the decision, loads the accepted proposal's Xi and W,
-// and stores.  One partial per chunk, so the partials are those of one chunk
+// upd_load issues every load that does not depend on the chain's decision
+// (keeping the raw bits, so nothing waits for them there), upd_finish takes
+// the decision, loads the accepted proposal's Xi and W for every chunk
+// before it converts any, and stores.  One partial per chunk, so the partials are those of one chunk
 // per wavefront whatever CPW is.
+// A row pair of a proposal's Xi and W as loaded (both bf16 parts of W in the
+// mixed form); the conversion to double (raw_xi, raw_w; W = hi + lo in the
+// mixed form) is left to where the values are used, so that the loads stay
+// in flight until then instead of being waited for at once.
+template <int PR> struct Raw2;
+template <> struct Raw2<P64> { double2 xi, w; };
+template <> struct Raw2<P32> { float2 xi, w; };
+template <> struct Raw2<PMIX> { float2 xi; uint32_t wh, wl; };
+
+DEV void raw_zero(Raw2<P64>& r) { r.xi = make_double2(0.0, 0.0); r.w = make_double2(0.0, 0.0); }
+DEV void raw_zero(Raw2<P32>& r) { r.xi = make_float2(0.f, 0.f); r.w = make_float2(0.f, 0.f); }
+DEV void raw_zero(Raw2<PMIX>& r) { r.xi = make_float2(0.f, 0.f); r.wh = r.wl = 0u; }
+
+DEV void raw_load(Raw2<P64>& r, const void* xi, const void* w, const void*, long e) {
+  r.xi = *(const double2*)((const double*)xi + e);
+  r.w = *(const double2*)((const double*)w + e);
+}
+DEV void raw_load(Raw2<P32>& r, const void* xi, const void* w, const void*, long e) {
+  r.xi = *(const float2*)((const float*)xi + e);
+  r.w = *(const float2*)((const float*)w + e);
+}
+DEV void raw_load(Raw2<PMIX>& r, const void* xi, const void* w, const void* wlo, long e) {
+  r.xi = *(const float2*)((const float*)xi + e);
+  r.wh = *(const uint32_t*)((const u16*)w + e);
+  r.wl = *(const uint32_t*)((const u16*)wlo + e);
+}
+
+DEV void raw_xi(const Raw2<P64>& r, double& v0, double& v1) { v0 = r.xi.x; v1 = r.xi.y; }
+DEV void raw_xi(const Raw2<P32>& r, double& v0, double& v1) { v0 = r.xi.x; v1 = r.xi.y; }
+DEV void raw_xi(const Raw2<PMIX>& r, double& v0, double& v1) { v0 = r.xi.x; v1 = r.xi.y; }
+DEV void raw_w(const Raw2<P64>& r, double& w0, double& w1) { w0 = r.w.x; w1 = r.w.y; }
+DEV void raw_w(const Raw2<P32>& r, double& w0, double& w1) { w0 = r.w.x; w1 = r.w.y; }
+DEV void raw_w(const Raw2<PMIX>& r, double& w0, double& w1) {
+  w0 = (double)bf16_bits_to_f32((u16)(r.wh & 0xffff)) + (double)bf16_bits_to_f32((u16)(r.wl & 0xffff));
+  w1 = (double)bf16_bits_to_f32((u16)(r.wh >> 16)) + (double)bf16_bits_to_f32((u16)(r.wl >> 16));
+}
+
 template <int PR, int CPW>
 struct UpdRegs {
   int ii[CPW];
   bool in[CPW];
   double x0[CPW], x1[CPW], z0[CPW], z1[CPW], r0[CPW], r1[CPW];
-  double n0[CPW], n1[CPW], wn0[CPW], wn1[CPW], m0[CPW], m1[CPW];
+  double m0[CPW], m1[CPW];
+  Raw2<PR> nw[CPW];  // the next proposal's Xi and W
   float2 sv[CPW];
 };
 
@@ -2303,7 +2316,8 @@ DEV void upd_load(const StepArgs& a, int p, int cb, int nch, UpdRegs<PR, CPW>& g
     g.ii[c] = ch * STEP_RCH + 2 * lane;
     g.in[c] = ch < nch && g.ii[c] < d;  // d even: the pair lies wholly inside or outside
     g.x0[c] = g.x1[c] = g.z0[c] = g.z1[c] = g.r0[c] = g.r1[c] = 0.0;
-    g.n0[c] = g.n1[c] = g.wn0[c] = g.wn1[c] = g.m0[c] = g.m1[c] = 0.0;
+    g.m0[c] = g.m1[c] = 0.0;
+    raw_zero(g.nw[c]);
     g.sv[c] = make_float2(0.f, 0.f);
     if (g.in[c]) {
       const int i = g.ii[c];
@@ -2312,8 +2326,7 @@ DEV void upd_load(const StepArgs& a, int p, int cb, int nch, UpdRegs<PR, CPW>& g
       const double2 rv = *(const double2*)(a.xr + i);
       g.x0[c] = xv.x; g.x1[c] = xv.y; g.z0[c] = zv.x; g.z1[c] = zv.y; g.r0[c] = rv.x; g.r1[c] = rv.y;
       if (a.do_propose) {
-        load_xi2<PR>(a.xi_nxt, ew, g.n0[c], g.n1[c]);
-        load_w2<PR>(a.w_nxt, a.wlo_nxt, ew, g.wn0[c], g.wn1[c]);
+        raw_load(g.nw[c], a.xi_nxt, a.w_nxt, a.wlo_nxt, ew);
         if (a.mu) {
           const double2 mv = *(const double2*)(a.mu + i);
           g.m0[c] = mv.x; g.m1[c] = mv.y;
@@ -2329,15 +2342,11 @@ DEV void upd_finish(const StepArgs& a, int p, int cb, int nch, bool acc, const U
   const int lane = threadIdx.x & 63;
   const int d = a.d, P = a.P;
   const long ldw = a.ldw ? a.ldw : d;
-  double c0[CPW], c1[CPW], wc0[CPW], wc1[CPW];
+  Raw2<PR> cw[CPW];  // the accepted proposal's Xi and W
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
-    c0[c] = c1[c] = wc0[c] = wc1[c] = 0.0;
-    if (g.in[c] && acc) {
-      const long ew = g.ii[c] + (long)p * ldw;
-      load_xi2<PR>(a.xi_cur, ew, c0[c], c1[c]);
-      load_w2<PR>(a.w_cur, a.wlo_cur, ew, wc0[c], wc1[c]);
-    }
+    raw_zero(cw[c]);
+    if (g.in[c] && acc) raw_load(cw[c], a.xi_cur, a.w_cur, a.wlo_cur, g.ii[c] + (long)p * ldw);
   }
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
@@ -2352,10 +2361,13 @@ DEV void upd_finish(const StepArgs& a, int p, int cb, int nch, bool acc, const U
       const double ra = g.r0[c], rb = g.r1[c];
       if (a.do_accept) {
         if (acc) {
-          xa = propose1(ra, xa, a.rho, c0[c]);
-          xb = propose1(rb, xb, a.rho, c1[c]);
-          za = __fma_rn(a.c, wc0[c], a.rho * za);
-          zb = __fma_rn(a.c, wc1[c], a.rho * zb);
+          double c0, c1, wc0, wc1;
+          raw_xi(cw[c], c0, c1);
+          raw_w(cw[c], wc0, wc1);
+          xa = propose1(ra, xa, a.rho, c0);
+          xb = propose1(rb, xb, a.rho, c1);
+          za = __fma_rn(a.c, wc0, a.rho * za);
+          zb = __fma_rn(a.c, wc1, a.rho * zb);
           *(double2*)(a.X + e) = make_double2(xa, xb);
           *(double2*)(a.Z + e) = make_double2(za, zb);
         }
@@ -2366,7 +2378,10 @@ DEV void upd_finish(const StepArgs& a, int p, int cb, int nch, bool acc, const U
         }
       }
       if (a.do_propose) {
-        const double xp0 = propose1(ra, xa, a.rho, g.n0[c]), xp1 = propose1(rb, xb, a.rho, g.n1[c]);
+        double n0, n1, wn0, wn1;
+        raw_xi(g.nw[c], n0, n1);
+        raw_w(g.nw[c], wn0, wn1);
+        const double xp0 = propose1(ra, xa, a.rho, n0), xp1 = propose1(rb, xb, a.rho, n1);
         if (a.vh) {
           u16 h0, l0, h1, l1;
           const double s0 = (xp0 - g.m0[c]) * (double)g.sv[c].x, s1 = (xp1 - g.m1[c]) * (double)g.sv[c].y;
@@ -2381,7 +2396,7 @@ DEV void upd_finish(const StepArgs& a, int p, int cb, int nch, bool acc, const U
             *(float2*)((float*)a.V + ev) = make_float2((float)(xp0 - g.m0[c]), (float)(xp1 - g.m1[c]));
           else *(double2*)((double*)a.V + ev) = make_double2(xp0 - g.m0[c], xp1 - g.m1[c]);
         }
-        const double zp0 = __fma_rn(a.c, g.wn0[c], a.rho * za), zp1 = __fma_rn(a.c, g.wn1[c], a.rho * zb);
+        const double zp0 = __fma_rn(a.c, wn0, a.rho * za), zp1 = __fma_rn(a.c, wn1, a.rho * zb);
         zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
         xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
       }
@@ -2416,6 +2431,112 @@ DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
   upd_finish<PR, CPW>(a, p, cb, nch, acc, g);
 }
 
+// The update half of k_step_h2, where every 128-row chunk lies inside d (d a
+// multiple of 256, two chunks per wavefront), the target's mean and the
+// proposal's scales are set, and PROP tells whether the step proposes.  Its
+// loads are issued without branches and kept raw, so the compiler keeps them
+// in flight until their first use (the shared upd_load and upd_finish wait
+// for each chunk's loads at the branches that guard them); the arithmetic and
+// the stores are those of upd_finish.
+template <bool PROP>
+DEV void upd_load_h2(const StepArgs& a, int p, int cb, UpdRegs<PMIX, 2>& g) {
+  const int lane = threadIdx.x & 63;
+  const int d = a.d;
+  const long ldw = a.ldw ? a.ldw : d;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = (cb * 2 + c) * STEP_RCH + 2 * lane;
+    g.ii[c] = i;
+    g.in[c] = true;
+    const long e = i + (long)p * d, ew = i + (long)p * ldw;
+    const double2 xv = *(const double2*)(a.X + e), zv = *(const double2*)(a.Z + e);
+    const double2 rv = *(const double2*)(a.xr + i);
+    g.x0[c] = xv.x; g.x1[c] = xv.y; g.z0[c] = zv.x; g.z1[c] = zv.y; g.r0[c] = rv.x; g.r1[c] = rv.y;
+    if (PROP) {
+      raw_load(g.nw[c], a.xi_nxt, a.w_nxt, a.wlo_nxt, ew);
+      const double2 mv = *(const double2*)(a.mu + i);
+      g.m0[c] = mv.x; g.m1[c] = mv.y;
+      g.sv[c] = *(const float2*)(a.vsc + i);
+    } else {
+      raw_zero(g.nw[c]);
+      g.m0[c] = g.m1[c] = 0.0;
+      g.sv[c] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+template <bool PROP>
+DEV void upd_finish_h2(const StepArgs& a, int p, int cb, int nch, bool acc, const UpdRegs<PMIX, 2>& g) {
+  const int lane = threadIdx.x & 63;
+  const int d = a.d, P = a.P;
+  const long ldw = a.ldw ? a.ldw : d;
+  double xa[2], xb[2], za[2], zb[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    xa[c] = g.x0[c]; xb[c] = g.x1[c]; za[c] = g.z0[c]; zb[c] = g.z1[c];
+  }
+  if (acc) {
+    // both chunks' accepted Xi and W in flight before either is converted
+    Raw2<PMIX> cw[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) raw_load(cw[c], a.xi_cur, a.w_cur, a.wlo_cur, g.ii[c] + (long)p * ldw);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double c0, c1, wc0, wc1;
+      raw_xi(cw[c], c0, c1);
+      raw_w(cw[c], wc0, wc1);
+      xa[c] = propose1(g.r0[c], xa[c], a.rho, c0);
+      xb[c] = propose1(g.r1[c], xb[c], a.rho, c1);
+      za[c] = __fma_rn(a.c, wc0, a.rho * za[c]);
+      zb[c] = __fma_rn(a.c, wc1, a.rho * zb[c]);
+      const long e = g.ii[c] + (long)p * d;
+      *(double2*)(a.X + e) = make_double2(xa[c], xb[c]);
+      *(double2*)(a.Z + e) = make_double2(za[c], zb[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int ch = cb * 2 + c;
+    const int i = g.ii[c];
+    const long e = i + (long)p * d;
+    const double ra = g.r0[c], rb = g.r1[c];
+    store_win2<PMIX>(a.win, i + (a.win_col0 + p) * (long)d, xa[c] - ra, xb[c] - rb);
+    double pacc[MAXPROJ] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < a.nproj; ++k) {
+      const double2 pv = *(const double2*)(a.proj + i + (long)k * d);
+      pacc[k] = __fma_rn(pv.y, xb[c], __fma_rn(pv.x, xa[c], pacc[k]));
+    }
+    if (PROP) {
+      double n0, n1, wn0, wn1;
+      raw_xi(g.nw[c], n0, n1);
+      raw_w(g.nw[c], wn0, wn1);
+      const double xp0 = propose1(ra, xa[c], a.rho, n0), xp1 = propose1(rb, xb[c], a.rho, n1);
+      u16 h0, l0, h1, l1;
+      const double s0 = (xp0 - g.m0[c]) * (double)g.sv[c].x, s1 = (xp1 - g.m1[c]) * (double)g.sv[c].y;
+      if (fmax(fabs(s0), fabs(s1)) >= H2_RANGE) atomicOr(a.err, 2);
+      split_f16(s0, h0, l0);
+      split_f16(s1, h1, l1);
+      *(uint32_t*)(a.vh + e) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      *(uint32_t*)(a.vh + (long)d * P + e) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      const double zp0 = __fma_rn(a.c, wn0, a.rho * za[c]), zp1 = __fma_rn(a.c, wn1, a.rho * zb[c]);
+      double zacc = __fma_rn(zp1, zp1, __fma_rn(zp0, zp0, 0.0));
+      double xacc = __fma_rn(xp1, xp1, __fma_rn(xp0, xp0, 0.0));
+      zacc = wave_sum_f64(zacc);
+      if (lane == 0) a.zq_part_nxt[(long)p * nch + ch] = zacc;
+      if (a.prior_w > 0.0) {
+        xacc = wave_sum_f64(xacc);
+        if (lane == 0) a.pq_part_nxt[(long)p * nch + ch] = xacc;
+      }
+    }
+    if (a.nproj > 0) {
+      for (int k = 0; k < a.nproj; ++k) {
+        const double v = wave_sum_f64(pacc[k]);
+        if (lane == 0) a.proj_part[((long)ch * a.nproj + k) * P + p] = v;
+      }
+    }
+  }
+}
+
 // One step of the mixed form with the half target's reduction folded in:
 // workgroup p (d / 256 wavefronts) issues its update loads, reduces the
 // K-split partial products of its rows into the row-block terms of log pi
@@ -2423,18 +2544,19 @@ DEV void step_update2(const StepArgs& a, int cb, int nch, int pq) {
 // every wavefront takes the chain's decision from the LDS terms (bitwise the
 // sums of the separate path) and updates its two 128-row chunks; wavefront 0
 // writes the decision's outputs.
+template <bool PROP>
 __global__ __launch_bounds__(1024) void k_step_h2(StepArgs a, int nch, const float* __restrict__ Yp,
                                                   const double* __restrict__ rsc, double* __restrict__ part,
                                                   const double* __restrict__ twist) {
   __shared__ double lpp[64];
   const int p = blockIdx.x, v = threadIdx.x >> 6, lane = threadIdx.x & 63;
   UpdRegs<PMIX, 2> g;
-  upd_load<PMIX, 2>(a, p, v, nch, g);
+  upd_load_h2<PROP>(a, p, v, g);
   const double q = h2_reduce_wave(Yp, rsc, a.d, a.P, a.nrb, part, twist, p, v);
   if ((lane & 15) == 0) lpp[v * 4 + (lane >> 4)] = q;
   __syncthreads();
   const bool acc = decide_wave(a, nch, p, v == 0, lpp);
-  upd_finish<PMIX, 2>(a, p, v, nch, acc, g);
+  upd_finish_h2<PROP>(a, p, v, nch, acc, g);
 }
 
 // STEP_CPW chunks per wavefront and 8 / STEP_CPW waves per SIMD: the
@@ -2468,10 +2590,16 @@ bool step_h2_ok(int d, int P, int nrb) {
 
 hipError_t step_h2(const StepArgs& a, const float* Yp, const double* rsc, double* part, const double* twist,
                    hipStream_t s) {
-  if (a.prec != PMIX || !a.vh || !a.do_accept || a.da || !step_h2_ok(a.d, a.P, a.nrb)) return hipErrorInvalidValue;
+  if (a.prec != PMIX || !a.vh || !a.mu || !a.vsc || !a.do_accept || a.da || !step_h2_ok(a.d, a.P, a.nrb))
+    return hipErrorInvalidValue;
   StepArgs b = a;
   b.fuse_dec = 1;
-  hipLaunchKernelGGL(k_step_h2, dim3(a.P), dim3(64 * (a.d / 256)), 0, s, b, step_chunks(a.d), Yp, rsc, part, twist);
+  if (a.do_propose)
+    hipLaunchKernelGGL(k_step_h2<true>, dim3(a.P), dim3(64 * (a.d / 256)), 0, s, b, step_chunks(a.d), Yp, rsc, part,
+                       twist);
+  else
+    hipLaunchKernelGGL(k_step_h2<false>, dim3(a.P), dim3(64 * (a.d / 256)), 0, s, b, step_chunks(a.d), Yp, rsc,
+                       part, twist);
   return hipGetLastError();
 }
 
