@@ -2199,21 +2199,38 @@ __global__ __launch_bounds__(256) void k_decide(StepArgs a, int nch) { decide_bl
 // bitwise decide_block's.  Every row-chunk workgroup of the chain takes the
 // (cheap, L2-resident) decision; only `write` stores its outputs.
 // parts: the chain's nrb target partials (global memory or LDS).
-DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double* parts) {
+// The decision's inputs other than the target's row-block terms, all written
+// by earlier launches: this lane's z-norm (and prior) partial of the
+// proposal, the current state's log pi and z-norm, and the uniform.  A kernel
+// that waits for the target's terms can load these first.
+struct DecIn {
+  double zs, pq, lp, zq, u;
+};
+
+DEV DecIn decide_inputs(const StepArgs& a, int nch, int p) {
+  const int lane = threadIdx.x & 63;
+  DecIn in;
+  in.zs = lane < nch ? 0.0 + a.zq_part_cur[(long)p * nch + lane] : 0.0;
+  in.pq = (a.prior_w > 0.0 && lane < nch) ? 0.0 + a.pq_part_cur[(long)p * nch + lane] : 0.0;
+  in.lp = a.lp_cur[p];
+  in.zq = a.zq_cur[p];
+  in.u = a.u[p];
+  return in;
+}
+
+DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double* parts, const DecIn& in) {
   const int lane = threadIdx.x & 63;
   double s = lane < a.nrb ? 0.0 + parts[lane] : 0.0;
   s = wave_sum_f64(s);
   if (a.prior_w > 0.0) {
-    double pq = lane < nch ? 0.0 + a.pq_part_cur[(long)p * nch + lane] : 0.0;
-    pq = wave_sum_f64(pq);
+    const double pq = wave_sum_f64(in.pq);
     s = __fma_rn(-a.prior_w, pq, s);
   }
   const double lpp = s;
-  double zs = lane < nch ? 0.0 + a.zq_part_cur[(long)p * nch + lane] : 0.0;
-  zs = wave_sum_f64(zs);
-  const double lp = a.lp_cur[p], zq = a.zq_cur[p];
+  const double zs = wave_sum_f64(in.zs);
+  const double lp = in.lp, zq = in.zq;
   const double la = (lpp + zs * a.inv2a2) - (lp + zq * a.inv2a2);
-  const bool acc = log(a.u[p]) < la;  // NaN compares false: rejected
+  const bool acc = log(in.u) < la;  // NaN compares false: rejected
   if (write && lane == 0) {
     a.lp_nxt[p] = acc ? lpp : lp;
     a.zq_nxt[p] = acc ? zs : zq;
@@ -2225,6 +2242,10 @@ DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double
     if (isinf(lpp) && lpp > 0.0) atomicOr(a.err, 1);
   }
   return acc;
+}
+
+DEV bool decide_wave(const StepArgs& a, int nch, int p, bool write, const double* parts) {
+  return decide_wave(a, nch, p, write, parts, decide_inputs(a, nch, p));
 }
 
 // Paired-row loads and stores for the update half (d even, so that every
@@ -2552,10 +2573,11 @@ __global__ __launch_bounds__(1024) void k_step_h2(StepArgs a, int nch, const flo
   const int p = blockIdx.x, v = threadIdx.x >> 6, lane = threadIdx.x & 63;
   UpdRegs<PMIX, 2> g;
   upd_load_h2<PROP>(a, p, v, g);
+  const DecIn din = decide_inputs(a, nch, p);
   const double q = h2_reduce_wave(Yp, rsc, a.d, a.P, a.nrb, part, twist, p, v);
   if ((lane & 15) == 0) lpp[v * 4 + (lane >> 4)] = q;
   __syncthreads();
-  const bool acc = decide_wave(a, nch, p, v == 0, lpp);
+  const bool acc = decide_wave(a, nch, p, v == 0, lpp, din);
   upd_finish_h2<PROP>(a, p, v, nch, acc, g);
 }
 
